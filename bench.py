@@ -1,0 +1,230 @@
+"""Throughput of the suggestion scoring path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+
+A step is one whole scoring pass over one batch of 512 profiled kernels x 64
+versions (all subsets of 6 optimisations) x 128 FP32 counter events:
+cycle-normalised features, per-optimisation ridge predictions, subset
+composition and top-3 ranking above the 1.05x threshold (one persistent HIP
+kernel).  32 distinct batches are resident in HBM (540 MB, more than the
+256 MB last-level cache) and the timed steps cycle through them from a
+captured hipGraph; the model is fitted beforehand on 512 other kernels.
+
+Printed: one JSON line.  value = candidate speedup predictions (subset-table
+entries, kernel x S != 0) per second; suggestions/s = kernels ranked per
+second.  roofline = the scoring kernel's algorithmic bytes per launch over its
+average duration in the timed region.  cpu_baseline = the FP64 oracle on the
+host cores on one batch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+K_BATCH, E, D, B = 512, 128, 6, 6
+N_BATCHES = 32
+METRIC = "candidate speedup predictions/sec + suggestions/sec; surrogate vs plain at equal MAPE"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def path_bytes(N, E, K, n, table=True, tsize=4):
+    """Algorithmic HBM bytes of one scoring pass: every counter and cycle value
+    read once, the table and the suggestion lists written once."""
+    return N * (E + 1) * tsize + (N * tsize if table else 0) + K * n * (4 + tsize) + K * 4
+
+
+def cpu_baseline(model_o, batch, budget_s=12.0):
+    from threadpoolctl import threadpool_info
+    from oracle import plain as P
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        P.run(model_o, batch)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or reps >= 200:
+            break
+    entries = reps * len(batch.nopts) * ((1 << B) - 1)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    return {"value": entries / dt, "unit": "predictions/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"FP64 numpy oracle (grid, composition, ranking) on one 512-kernel batch, "
+                      f"{reps} repetitions in {dt:.1f} s; BLAS threads {threads} of {os.cpu_count()} host CPUs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3200)
+    ap.add_argument("--warmup", type=int, default=320)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from synthgen import make_batch
+    from paper_1910_07776_amd import plain as G
+
+    steps = max(N_BATCHES, (args.steps + N_BATCHES - 1) // N_BATCHES * N_BATCHES)
+    warm = (args.warmup + N_BATCHES - 1) // N_BATCHES
+    dev = torch.device("cuda", 0)
+
+    log("generating inputs")
+    train = make_batch(1910, range(10 ** 6, 10 ** 6 + K_BATCH), E, D)
+    test = make_batch(1910, range(K_BATCH * N_BATCHES), E, D)
+    nb_rows = K_BATCH << B
+    ctx = G.Context(0)
+    ptr = G.Plan(ctx, train.nopts, train.opt_ids, E, D)
+    tc, tcy = torch.from_numpy(train.counters).to(dev), torch.from_numpy(train.cycles).to(dev)
+    G.fit(ctx, ptr, tc, tcy)
+    G.sync(ctx)
+    # GPU fit time (column statistics, features, Gram, Cholesky)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        G.fit(ctx, ptr, tc, tcy)
+    ev1.record()
+    G.sync(ctx)
+    fit_ms = ev0.elapsed_time(ev1) / 10
+
+    cnt_all = torch.from_numpy(test.counters).to(dev)
+    cyc_all = torch.from_numpy(test.cycles).to(dev)
+    plan = G.Plan(ctx, test.nopts[:K_BATCH], test.opt_ids[:K_BATCH * D], E, D)
+    n = ctx.params["n_suggest"]
+    outs = [{"idx": torch.empty((K_BATCH, n), dtype=torch.int32, device=dev),
+             "score": torch.empty((K_BATCH, n), dtype=torch.float32, device=dev),
+             "count": torch.empty(K_BATCH, dtype=torch.int32, device=dev),
+             "table": torch.empty(nb_rows, dtype=torch.float32, device=dev)} for _ in range(N_BATCHES)]
+    views = [(cnt_all[i * nb_rows:(i + 1) * nb_rows], cyc_all[i * nb_rows:(i + 1) * nb_rows])
+             for i in range(N_BATCHES)]
+    tune = G.autotune(ctx, plan, *views[0], reps=10)
+    log(f"autotuned launch: {tune['waves']} waves x unroll {tune['unroll']}")
+    # eager pass first (validates arguments), then capture all batches once
+    for i in range(N_BATCHES):
+        G.suggest(ctx, plan, *views[i], out=outs[i])
+    G.sync(ctx)
+    g = G.Graph(ctx)
+    with g.capture():
+        for i in range(N_BATCHES):
+            G.suggest(ctx, plan, *views[i], out=outs[i])
+    stream = torch.cuda.current_stream()
+    log(f"warmup {warm * N_BATCHES} steps")
+    for _ in range(warm):
+        g.launch()
+    torch.cuda.synchronize()
+    log(f"timing {steps} steps")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps // N_BATCHES):
+        g.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    G.sync(ctx)
+    gpu_ms = e0.elapsed_time(e1)
+    ms_per_step = gpu_ms / steps
+    entries = K_BATCH * ((1 << B) - 1)
+    value = entries * steps / (gpu_ms / 1e3)
+    sugg_rate = K_BATCH * steps / (gpu_ms / 1e3)
+    by = path_bytes(nb_rows, E, K_BATCH, n)
+    achieved = by / (ms_per_step / 1e3) / 1e9
+    log(f"{ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s, wall {wall:.2f} s")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "predictions/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm * N_BATCHES, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plain method, 512 kernels x 64 versions x 128 FP32 events, top-3 per kernel",
+                   "kernels_per_step": K_BATCH, "versions_per_kernel": 1 << B, "events": E,
+                   "distinct_resident_batches": N_BATCHES, "launch": "hipGraph of 32 passes",
+                   "autotuned": {"waves": tune["waves"], "unroll": tune["unroll"]}},
+        "suggestions_per_s": sugg_rate,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "path_kernel", "bytes_per_launch": by},
+        "fit_ms": fit_ms,
+    }
+
+    if not args.no_extra:
+        out["ragged_16384"] = ragged_extra(G, ctx, dev)
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        from oracle import plain as P
+        om = P.fit(train, D)
+        one = P.SubBatch(test, range(K_BATCH))
+        out["cpu_baseline"] = cpu_baseline(om, one)
+    print(json.dumps(out), flush=True)
+
+
+def ragged_extra(G, ctx, dev):
+    """The 16,384-kernel ragged batch (4-10 of 10 optimisations, 4.8M versions,
+    2.5 GB of counters) in one persistent launch."""
+    import torch
+    from synthgen import make_batch
+    log("ragged batch: generating 2 x 16384 kernels")
+    tr = make_batch(1910, range(10 ** 6, 10 ** 6 + 16384), 128, 10, brange=(4, 10))
+    ptr = G.Plan(ctx, tr.nopts, tr.opt_ids, 128, 10)
+    c, cy = torch.from_numpy(tr.counters).to(dev), torch.from_numpy(tr.cycles).to(dev)
+    G.fit(ctx, ptr, c, cy)
+    G.sync(ctx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    G.fit(ctx, ptr, c, cy)
+    e1.record()
+    G.sync(ctx)
+    fit_ms = e0.elapsed_time(e1)
+    del c, cy, ptr, tr
+    te = make_batch(1910, range(16384), 128, 10, brange=(4, 10))
+    plan = G.Plan(ctx, te.nopts, te.opt_ids, 128, 10)
+    c, cy = torch.from_numpy(te.counters).to(dev), torch.from_numpy(te.cycles).to(dev)
+    n = ctx.params["n_suggest"]
+    out = {"idx": torch.empty((te.K, n), dtype=torch.int32, device=dev),
+           "score": torch.empty((te.K, n), dtype=torch.float32, device=dev),
+           "count": torch.empty(te.K, dtype=torch.int32, device=dev),
+           "table": torch.empty(te.N, dtype=torch.float32, device=dev)}
+    tune = G.autotune(ctx, plan, c, cy, reps=3)
+    log(f"ragged autotuned launch: {tune['waves']} waves x unroll {tune['unroll']}")
+    G.suggest(ctx, plan, c, cy, out=out)
+    G.sync(ctx)
+    g = G.Graph(ctx)
+    with g.capture():
+        G.suggest(ctx, plan, c, cy, out=out)
+    for _ in range(3):
+        g.launch()
+    reps = 20
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        g.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    G.sync(ctx)
+    ms = e0.elapsed_time(e1) / reps
+    entries = int(te.N - te.K)
+    by = path_bytes(te.N, 128, te.K, n)
+    gbs = by / (ms / 1e3) / 1e9
+    log(f"ragged: {ms:.3f} ms/pass, {gbs:.0f} GB/s")
+    return {"kernels": te.K, "versions": int(te.N), "ms_per_pass": ms,
+            "predictions_per_s": entries / (ms / 1e3), "suggestions_per_s": te.K / (ms / 1e3),
+            "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_pass": by, "fit_ms": fit_ms,
+            "autotuned": {"waves": tune["waves"], "unroll": tune["unroll"]}, "tune_ms": tune["times_ms"]}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * sugg.h - C ABI of the optimisation-suggestion scoring library (gfx950).
+ *
+ * The library implements the data-parallel path of the suggestion tool of
+ * Taheri, Qasem and Burtscher, "A Tool for Automatically Suggesting
+ * Source-Code Optimizations for Complex GPU Kernels": profiled counter vectors
+ * are normalised by the cycle count (Section 2, Tier 1), one regression model
+ * per optimisation is trained on before/after version pairs and predicts the
+ * speedup of adding it (Section 2, Tier 2; Sections 3.3-3.4), and the
+ * candidates are sorted by expected benefit and kept above a threshold
+ * (Section 2, Tier 3).
+ *
+ * Data model
+ *   A batch ("plan") holds K kernels.  Kernel k has B_k binary optimisations
+ *   (0 <= B_k <= SUGG_MAX_OPTS) with global ids O_k[0..B_k), strictly
+ *   ascending, each < D.  Every version S in [0, 2^B_k) (bit b of S set means
+ *   optimisation O_k[b] is applied) has one profiled row.  Rows are stored
+ *   kernel after kernel: row(k, S) = row_off[k] + S with
+ *   row_off[k] = sum_{i<k} 2^B_i, N = row_off[K] rows in total.
+ *   counters: N x E row-major, cycles: N, both of the plan's dtype, device
+ *   memory owned by the caller.  Every value must be finite and > 0.
+ *
+ * Conventions
+ *   - Every call returns SUGG_OK (0) or a negative SUGG_E_* code; the message
+ *     is available from sugg_last_error().  No exception crosses the ABI.
+ *   - Argument and shape errors are detected on the host, synchronously.
+ *     Data errors (non-finite or non-positive counters, a singular system)
+ *     are detected on the device and returned by the next sugg_sync().
+ *   - Work is enqueued on the caller's HIP stream and is asynchronous unless
+ *     stated otherwise; a context must not be used from two streams at once
+ *     (calls that overlap on one context race on its model and status word).
+ *   - Device pointers are caller-owned; the library allocates its own
+ *     workspace at plan creation (and on the first fit with a plan), never in
+ *     sugg_predict, sugg_suggest or sugg_rank_suggest.
+ */
+#ifndef SUGG_H
+#define SUGG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SUGG_API __attribute__((visibility("default")))
+
+enum {
+  SUGG_OK = 0,
+  SUGG_E_ARG = -1,           /* bad argument (null pointer, bad enum, bad n) */
+  SUGG_E_SHAPE = -2,         /* inconsistent sizes or layout */
+  SUGG_E_BAD_COUNTER = -3,   /* a counter or cycle count that is <= 0, NaN or Inf */
+  SUGG_E_UNTRAINED_OPT = -4, /* an optimisation id with no fitted model */
+  SUGG_E_SINGULAR = -5,      /* a regression system is not positive definite */
+  SUGG_E_BUDGET = -6,        /* request exceeds a size limit of the library */
+  SUGG_E_HIP = -7,           /* HIP runtime error */
+  SUGG_E_STATE = -8          /* call out of order (e.g. predict before fit) */
+};
+
+enum { SUGG_F32 = 0, SUGG_F64 = 1 };          /* dtype of counters and results */
+enum { SUGG_FIT_STATS = 1, SUGG_APPLY = 2 };  /* sugg_load_features modes */
+
+#define SUGG_MAX_OPTS 12      /* max optimisations per kernel (4096 versions) */
+#define SUGG_MAX_EVENTS 256   /* max counter events per row */
+#define SUGG_MAX_GLOBAL_OPTS 64
+#define SUGG_MAX_SUGGEST 8    /* max suggestions per segment */
+
+typedef struct sugg_ctx sugg_ctx;
+typedef struct sugg_plan sugg_plan;
+typedef struct sugg_graph sugg_graph;
+
+typedef struct {
+  double lambda;      /* ridge penalty on the feature weights (intercept unpenalised) */
+  double tau;         /* threshold on the predicted log-speedup; strict ">" */
+  int32_t n_suggest;  /* suggestions kept per kernel, 1..SUGG_MAX_SUGGEST */
+  int32_t reserved;
+} sugg_params;
+
+/* Context: owns the fitted model (column statistics and one regression per
+ * global optimisation id), the device status word and its error message.
+ * device: HIP device ordinal; params may be NULL (lambda 1e-2, tau ln 1.05,
+ * n_suggest 3). */
+SUGG_API int32_t sugg_create(sugg_ctx** out, int32_t device, const sugg_params* params);
+SUGG_API void sugg_destroy(sugg_ctx* ctx);
+SUGG_API const char* sugg_last_error(const sugg_ctx* ctx);
+SUGG_API int32_t sugg_set_params(sugg_ctx* ctx, const sugg_params* params);
+SUGG_API int32_t sugg_get_params(const sugg_ctx* ctx, sugg_params* out);
+
+/* Plan: the structure of a batch (Section 3.3's version lattice per kernel).
+ * nopts[K] and opt_ids[sum B_k] are HOST arrays, copied.  D is the number of
+ * global optimisation ids, dtype SUGG_F32 or SUGG_F64.  Validates the layout,
+ * builds the ragged work list (kernels grouped by B, largest first) and
+ * uploads it.  Synchronous. */
+SUGG_API int32_t sugg_plan_create(sugg_ctx* ctx, int32_t K, int32_t E, int32_t D, int32_t dtype,
+                                  const int32_t* nopts, const int32_t* opt_ids, sugg_plan** out);
+SUGG_API void sugg_plan_destroy(sugg_plan* plan);
+SUGG_API int64_t sugg_plan_rows(const sugg_plan* plan);     /* N, or -1 */
+SUGG_API int32_t sugg_plan_max_opts(const sugg_plan* plan); /* max B_k, or -1 */
+
+/* Launch shape of the plan's scoring kernel: waves per workgroup (1-8),
+ * rows per lane group and pipeline stage (1, 2 or 4), workgroups (0 = as
+ * many as fit on the device at once).  Results do not depend on it. */
+SUGG_API int32_t sugg_plan_set_launch(sugg_plan* plan, int32_t waves, int32_t unroll, int32_t grid);
+SUGG_API int32_t sugg_plan_get_launch(const sugg_plan* plan, int32_t* waves, int32_t* unroll, int32_t* grid);
+
+/* Autotuner: times the fused scoring pass (sugg_suggest) of this plan on the
+ * given inputs for every candidate launch shape (waves 2, 4, 8 x unroll
+ * 1, 2, 4, in that order; reps timed passes each after one warm-up) and keeps
+ * the fastest in the plan.  times_ms (nullable, 9 floats) receives the mean
+ * pass time of each candidate.  Needs a fitted model; allocates and frees
+ * temporary outputs; synchronises the stream. */
+SUGG_API int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, const void* cycles,
+                               int32_t reps, float* times_ms, hipStream_t stream);
+
+/* Tier 1 (Section 2): features are ln(counter / cycles).
+ * mode SUGG_FIT_STATS: set the context's column statistics (mean, population
+ *   standard deviation; sigma < 1e-12 is replaced by 1) from all N rows,
+ *   computed in FP64 whatever the dtype.
+ * mode SUGG_APPLY: requires statistics; z_out (nullable) receives the
+ *   standardised features z = (x - mu) / sigma, N x E, plan dtype.
+ * FIT_STATS | APPLY does both. */
+SUGG_API int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* counters,
+                                    const void* cycles, int32_t mode, void* z_out, hipStream_t stream);
+
+/* Tier 2 training (Section 2; Sections 3.3-3.4): column statistics from the
+ * training rows, then for every global optimisation o with at least one
+ * before/after pair (version S without o, the same kernel's version S with o)
+ * a ridge regression of ln cyc(before) - ln cyc(after) on [z(before), 1]:
+ *   (X^T X + lambda diag(1,..,1,0)) w_o = X^T y,
+ * accumulated and solved by Cholesky in FP64.  Replaces the model. */
+SUGG_API int32_t sugg_fit(sugg_ctx* ctx, const sugg_plan* train, const void* counters,
+                          const void* cycles, hipStream_t stream);
+
+/* Tier 2 prediction.  Every global id used by the plan must be trained
+ * (else SUGG_E_UNTRAINED_OPT).
+ * grid_out (nullable): N x Bmax (Bmax = sugg_plan_max_opts), plan dtype;
+ *   grid[row(k,S)][b] = w_{O_k[b]} . [z, 1] for b < B_k not in S, NaN for
+ *   b in S or b >= B_k: the predicted log-speedup of adding optimisation b.
+ * table_out (required): N, plan dtype; table[row(k,S)] = sum over the bits b
+ *   of S, ascending, of the prediction for adding b to version S & (2^b - 1)
+ *   (the composed log-speedup of applying subset S; table[row(k,0)] = 0). */
+SUGG_API int32_t sugg_predict(sugg_ctx* ctx, const sugg_plan* plan, const void* counters,
+                              const void* cycles, void* grid_out, void* table_out, hipStream_t stream);
+
+/* Tier 3 (Section 2) over arbitrary segments: segment i is
+ * scores[seg_off[i] .. seg_off[i+1]) (device int64 offsets, non-decreasing);
+ * its first skip_head entries are never candidates.  Keeps entries with
+ * score > tau (NaN never), sorts by score descending then index ascending,
+ * writes the first n: idx_out[i*n + j] = index within the segment (-1 pad),
+ * score_out[i*n + j] (NaN pad), count_out[i] = number kept (<= n).
+ * 1 <= n <= SUGG_MAX_SUGGEST.  scores and score_out are of dtype. */
+SUGG_API int32_t sugg_rank_suggest(sugg_ctx* ctx, int32_t dtype, const void* scores,
+                                   const int64_t* seg_off, int32_t nseg, int32_t skip_head,
+                                   int32_t n, double tau, int32_t* idx_out, void* score_out,
+                                   int32_t* count_out, hipStream_t stream);
+
+/* The fused scoring path: sugg_predict's table plus, per kernel k, the top
+ * n_suggest subsets S >= 1 with table > tau (context parameters), in one
+ * persistent kernel.  table_out (nullable) as in sugg_predict; idx_out[K*n]
+ * holds subset bitmasks S, score_out[K*n] their composed log-speedups,
+ * count_out[K]; padding as in sugg_rank_suggest. */
+SUGG_API int32_t sugg_suggest(sugg_ctx* ctx, const sugg_plan* plan, const void* counters,
+                              const void* cycles, void* table_out, int32_t* idx_out,
+                              void* score_out, int32_t* count_out, hipStream_t stream);
+
+/* Waits for the stream, then returns and clears the device status word:
+ * SUGG_E_BAD_COUNTER or SUGG_E_SINGULAR if a kernel flagged one since the
+ * last sync, else SUGG_OK. */
+SUGG_API int32_t sugg_sync(sugg_ctx* ctx, hipStream_t stream);
+
+/* Graph capture of scoring passes (Tiers 1-3 of Section 2 replayed without
+ * per-launch host work).  Between sugg_capture_begin and sugg_capture_end on
+ * a non-default stream, sugg_predict / sugg_suggest / sugg_rank_suggest calls
+ * on that stream are recorded instead of run; the graph then replays them
+ * with sugg_graph_launch on any stream of the device.  The recorded calls
+ * keep their pointers: inputs are read and outputs written in place at every
+ * replay.  The scoring kernels re-arm their work counters themselves, so a
+ * graph holds kernel nodes only.  A plan must not run in two launches that
+ * overlap in time (they share its work counter). */
+SUGG_API int32_t sugg_capture_begin(sugg_ctx* ctx, hipStream_t stream);
+SUGG_API int32_t sugg_capture_end(sugg_ctx* ctx, hipStream_t stream, sugg_graph** out);
+SUGG_API int32_t sugg_graph_launch(sugg_ctx* ctx, sugg_graph* graph, hipStream_t stream);
+SUGG_API void sugg_graph_destroy(sugg_graph* graph);
+
+/* Model checkpoint (host arrays, synchronous).  W is D x (E+1), row o =
+ * feature weights of optimisation o followed by its intercept; counts[o] is
+ * its number of training pairs (0 = untrained). */
+SUGG_API int32_t sugg_model_shape(const sugg_ctx* ctx, int32_t* E, int32_t* D);
+SUGG_API int32_t sugg_model_get(sugg_ctx* ctx, double* mu, double* sigma, double* W, int64_t* counts);
+SUGG_API int32_t sugg_model_set(sugg_ctx* ctx, int32_t E, int32_t D, const double* mu,
+                                const double* sigma, const double* W, const int64_t* counts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUGG_H */

@@ -1,0 +1,846 @@
+// Host side of the C ABI declared in include/sugg.h: contexts, plans (the
+// ragged work lists), argument validation and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "sugg.h"
+
+using namespace sugg;
+
+namespace {
+
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct sugg_ctx {
+  int device = 0;
+  sugg_params params{};
+  std::string err;
+  int32_t* d_status = nullptr;
+  // model
+  int E = 0, D = 0;
+  bool has_stats = false, has_model = false;
+  double *mu64 = nullptr, *sig64 = nullptr, *isg64 = nullptr, *W64 = nullptr;
+  float *mu32 = nullptr, *isg32 = nullptr, *W32 = nullptr;
+  std::vector<int64_t> counts;
+  int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+  int hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return SUGG_OK;
+    return fail(SUGG_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  }
+  void free_model() {
+    dfree(mu64); dfree(sig64); dfree(isg64); dfree(W64);
+    dfree(mu32); dfree(isg32); dfree(W32);
+    E = D = 0;
+    has_stats = has_model = false;
+    counts.clear();
+  }
+  // (re)allocate model buffers for shape (e, d); keeps them when unchanged
+  int ensure_model(int e, int d) {
+    if (e == E && d == D && mu64) return SUGG_OK;
+    free_model();
+    hipError_t r = hipSuccess;
+    if (r == hipSuccess) r = hipMalloc((void**)&mu64, sizeof(double) * e);
+    if (r == hipSuccess) r = hipMalloc((void**)&sig64, sizeof(double) * e);
+    if (r == hipSuccess) r = hipMalloc((void**)&isg64, sizeof(double) * e);
+    if (r == hipSuccess) r = hipMalloc((void**)&mu32, sizeof(float) * e);
+    if (r == hipSuccess) r = hipMalloc((void**)&isg32, sizeof(float) * e);
+    if (r == hipSuccess && d > 0) r = hipMalloc((void**)&W64, sizeof(double) * (size_t)d * (e + 1));
+    if (r == hipSuccess && d > 0) r = hipMalloc((void**)&W32, sizeof(float) * (size_t)d * (e + 1));
+    if (r != hipSuccess) {
+      free_model();
+      return hip(r, "model allocation");
+    }
+    E = e;
+    D = d;
+    counts.assign(d, 0);
+    return SUGG_OK;
+  }
+};
+
+struct sugg_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+  ~sugg_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+struct sugg_plan {
+  sugg_ctx* ctx = nullptr;   // identity only: never dereferenced after creation
+  int device = 0;
+  int K = 0, E = 0, D = 0, dtype = SUGG_F32, Bmax = 0;
+  int64_t N = 0;
+  std::vector<int32_t> nopts, opt_ids;
+  std::vector<int64_t> row_off, opt_off;
+  std::vector<int64_t> opt_pairs;   // per global id: number of before/after pairs
+  // device structure
+  Item* d_items = nullptr;
+  KRec* d_recs = nullptr;
+  int32_t* d_queue = nullptr;
+  int n_items = 0, max_item_rows = 1, max_item_kernels = 1;
+  int uni_B = -1, uni_nk = 0;
+  PathLaunch cfg{4, 2, 0};   // launch shape of the scoring kernel (autotuned)
+  // statistics workspace
+  double* d_stat_partial = nullptr;
+  int stat_chunks = 1;
+  // fit workspace (allocated on the first fit)
+  bool fit_ready = false;
+  double* d_z64 = nullptr;
+  double* d_lcyc64 = nullptr;
+  double* d_gram_partial = nullptr;
+  double* d_solveA = nullptr;
+  double* d_reduced = nullptr;
+  GramWork* d_gwork = nullptr;
+  int64_t* d_pair_base = nullptr;
+  int64_t* d_pair_row0 = nullptr;
+  int32_t* d_pair_bit = nullptr;
+  int32_t* d_opt_work_begin = nullptr;
+  int n_gwork = 0;
+
+  ~sugg_plan() {
+    dfree(d_items); dfree(d_recs);
+    dfree(d_queue); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
+    dfree(d_solveA); dfree(d_reduced); dfree(d_gwork); dfree(d_pair_base); dfree(d_pair_row0); dfree(d_pair_bit);
+    dfree(d_opt_work_begin);
+  }
+};
+
+namespace {
+
+int cu_count(int device) {
+  int c = 0;
+  if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c <= 0) c = 256;
+  return c;
+}
+
+template <typename V>
+hipError_t upload(V*& dst, const void* src, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc((void**)&dst, bytes);
+  if (e != hipSuccess) return e;
+  if (src) e = hipMemcpy((void*)dst, src, bytes, hipMemcpyHostToDevice);
+  return e;
+}
+
+bool device_ok(sugg_ctx* ctx) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return false;
+  if (cur != ctx->device) return hipSetDevice(ctx->device) == hipSuccess;
+  return true;
+}
+
+int check_params(sugg_ctx* ctx, const sugg_params& p) {
+  if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)) return ctx->fail(SUGG_E_ARG, "lambda must be finite and >= 0");
+  if (std::isnan(p.tau)) return ctx->fail(SUGG_E_ARG, "tau is NaN");
+  if (p.n_suggest < 1 || p.n_suggest > SUGG_MAX_SUGGEST)
+    return ctx->fail(SUGG_E_ARG, "n_suggest must be in [1, %d]", SUGG_MAX_SUGGEST);
+  return SUGG_OK;
+}
+
+// Build the ragged work list: kernels grouped by B (largest first, a greedy
+// longest-processing-time order), small kernels packed into items of about
+// `target` rows, kernels of >= target rows alone.
+void build_items(const std::vector<int32_t>& nopts, const std::vector<int64_t>& row_off, int target,
+                 std::vector<Item>& items, std::vector<int32_t>& item_kernels, int& max_rows, int& max_nk) {
+  const int K = (int)nopts.size();
+  std::vector<int32_t> order(K);
+  for (int k = 0; k < K; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nopts[a] > nopts[b]; });
+  items.clear();
+  item_kernels = order;
+  max_rows = 1;
+  max_nk = 1;
+  int i = 0;
+  while (i < K) {
+    const int B = nopts[order[i]];
+    const int rows = 1 << B;
+    const int per = rows >= target ? 1 : target / rows;
+    int j = i;
+    while (j < K && j - i < per && nopts[order[j]] == B) ++j;
+    Item it;
+    std::memset(&it, 0, sizeof it);
+    it.first = i;
+    it.nk = j - i;
+    it.B = B;
+    it.R = it.nk << B;
+    bool adjacent = true;
+    for (int t = i; t + 1 < j; ++t) adjacent &= order[t + 1] == order[t] + 1;
+    it.row0 = adjacent ? row_off[order[i]] : -1;
+    items.push_back(it);
+    max_rows = std::max(max_rows, it.R);
+    max_nk = std::max(max_nk, it.nk);
+    i = j;
+  }
+}
+
+template <typename T>
+const T* model_mu(sugg_ctx* c);
+template <>
+const float* model_mu<float>(sugg_ctx* c) { return c->mu32; }
+template <>
+const double* model_mu<double>(sugg_ctx* c) { return c->mu64; }
+template <typename T>
+const T* model_isg(sugg_ctx* c);
+template <>
+const float* model_isg<float>(sugg_ctx* c) { return c->isg32; }
+template <>
+const double* model_isg<double>(sugg_ctx* c) { return c->isg64; }
+template <typename T>
+const T* model_W(sugg_ctx* c);
+template <>
+const float* model_W<float>(sugg_ctx* c) { return c->W32; }
+template <>
+const double* model_W<double>(sugg_ctx* c) { return c->W64; }
+
+__global__ void inv_kernel(const double* sig, double* isg, int E) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < E) isg[j] = 1.0 / sig[j];
+}
+
+__global__ void stats_to_f32_kernel(const double* mu, const double* sig, float* mu32, float* isg32, int E) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < E) {
+    mu32[j] = (float)mu[j];
+    isg32[j] = (float)(1.0 / sig[j]);
+  }
+}
+
+int prepare_fit(sugg_ctx* ctx, sugg_plan* p) {
+  if (p->fit_ready) return SUGG_OK;
+  const int E = p->E, D = p->D;
+  // per-optimisation list of (kernel, local bit); pair space prefix sums
+  std::vector<std::vector<std::pair<int, int>>> lists(D);
+  for (int k = 0; k < p->K; ++k)
+    for (int b = 0; b < p->nopts[k]; ++b) lists[p->opt_ids[p->opt_off[k] + b]].push_back({k, b});
+  int64_t total = 0;
+  for (int o = 0; o < D; ++o) total += p->opt_pairs[o];
+  const int target_items = 4 * cu_count(ctx->device);
+  int64_t chunk = total / std::max(1, target_items);
+  chunk = std::max<int64_t>(chunk, 256);
+  chunk = (chunk + 31) / 32 * 32;
+  std::vector<int64_t> pbase, prow0;
+  std::vector<int32_t> pbit, owb(D + 1, 0);
+  std::vector<GramWork> work;
+  for (int o = 0; o < D; ++o) {
+    owb[o] = (int)work.size();
+    const int lb = (int)pbase.size();
+    int64_t acc = 0;
+    for (auto& kb : lists[o]) {
+      pbase.push_back(acc);
+      prow0.push_back(p->row_off[kb.first]);
+      pbit.push_back(kb.second);
+      acc += (int64_t)1 << (p->nopts[kb.first] - 1);
+    }
+    const int le = (int)pbase.size();
+    for (int64_t s0 = 0; s0 < acc; s0 += chunk) {
+      GramWork w;
+      w.opt = o;
+      w.list_begin = lb;
+      w.list_end = le;
+      w.pad = 0;
+      w.s_begin = s0;
+      w.s_end = std::min(acc, s0 + chunk);
+      work.push_back(w);
+    }
+  }
+  owb[D] = (int)work.size();
+  hipError_t e = hipSuccess;
+  const size_t stride = (size_t)E * E + 2 * E + 2;
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_z64, sizeof(double) * std::max<int64_t>(1, p->N * E));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_lcyc64, sizeof(double) * std::max<int64_t>(1, p->N));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_gram_partial, sizeof(double) * stride * std::max<size_t>(1, work.size()));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_reduced, sizeof(double) * stride * std::max(1, D));
+  if (e == hipSuccess && sizeof(double) * (size_t)(E + 1) * (E + 1) > 150 * 1024)
+    e = hipMalloc((void**)&p->d_solveA, sizeof(double) * (size_t)(E + 1) * (E + 1) * std::max(1, D));
+  if (e == hipSuccess) e = upload(p->d_gwork, work.data(), sizeof(GramWork) * work.size());
+  if (e == hipSuccess) e = upload(p->d_pair_base, pbase.data(), sizeof(int64_t) * pbase.size());
+  if (e == hipSuccess) e = upload(p->d_pair_row0, prow0.data(), sizeof(int64_t) * prow0.size());
+  if (e == hipSuccess) e = upload(p->d_pair_bit, pbit.data(), sizeof(int32_t) * pbit.size());
+  if (e == hipSuccess) e = upload(p->d_opt_work_begin, owb.data(), sizeof(int32_t) * owb.size());
+  if (e != hipSuccess) return ctx->hip(e, "fit workspace");
+  p->n_gwork = (int)work.size();
+  p->fit_ready = true;
+  return SUGG_OK;
+}
+
+template <typename T>
+int run_fit(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, hipStream_t s) {
+  int rc = prepare_fit(ctx, p);
+  if (rc) return rc;
+  rc = ctx->ensure_model(p->E, p->D);
+  if (rc) return rc;
+  T* mu_t = (T*)(sizeof(T) == 4 ? (void*)ctx->mu32 : (void*)ctx->mu64);
+  T* isg_t = (T*)(sizeof(T) == 4 ? (void*)ctx->isg32 : (void*)ctx->isg64);
+  rc = ctx->hip(launch_colstats<T>(c, cyc, p->N, p->E, p->d_stat_partial, p->stat_chunks, ctx->mu64,
+                                   ctx->sig64, mu_t, isg_t, ctx->d_status, s), "column statistics");
+  if (rc) return rc;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(inv_kernel, dim3((p->E + 255) / 256), dim3(256), 0, s, ctx->sig64, ctx->isg64, p->E);
+  hipLaunchKernelGGL(stats_to_f32_kernel, dim3((p->E + 255) / 256), dim3(256), 0, s, ctx->mu64, ctx->sig64,
+                     ctx->mu32, ctx->isg32, p->E);
+  rc = ctx->hip(hipGetLastError(), "statistics");
+  if (rc) return rc;
+  rc = ctx->hip(launch_zfeat64<T>(c, cyc, p->N, p->E, ctx->mu64, ctx->sig64, p->d_z64, p->d_lcyc64, s), "features");
+  if (rc) return rc;
+  GramArgs g;
+  g.z64 = p->d_z64;
+  g.lcyc64 = p->d_lcyc64;
+  g.E = p->E;
+  g.work = p->d_gwork;
+  g.n_work = p->n_gwork;
+  g.pair_base = p->d_pair_base;
+  g.pair_row0 = p->d_pair_row0;
+  g.pair_bit = p->d_pair_bit;
+  g.partial = p->d_gram_partial;
+  rc = ctx->hip(launch_gram(g, s), "gram");
+  if (rc) return rc;
+  SolveArgs sa;
+  sa.partial = p->d_gram_partial;
+  sa.opt_work_begin = p->d_opt_work_begin;
+  sa.E = p->E;
+  sa.D = p->D;
+  sa.lambda = ctx->params.lambda;
+  sa.A = p->d_solveA;
+  sa.reduced = p->d_reduced;
+  sa.W64 = ctx->W64;
+  sa.W32 = ctx->W32;
+  sa.status = ctx->d_status;
+  rc = ctx->hip(launch_solve(sa, s), "solve");
+  if (rc) return rc;
+  for (int o = 0; o < p->D; ++o) ctx->counts[o] = p->opt_pairs[o];
+  ctx->has_stats = ctx->has_model = true;
+  return SUGG_OK;
+}
+
+int check_model_for(sugg_ctx* ctx, const sugg_plan* p) {
+  if (!ctx->has_model) return ctx->fail(SUGG_E_STATE, "no fitted model");
+  if (ctx->E != p->E) return ctx->fail(SUGG_E_SHAPE, "plan has E=%d, model E=%d", p->E, ctx->E);
+  for (int o = 0; o < p->D; ++o)
+    // the plan uses o exactly when it has before/after pairs for it
+    if (p->opt_pairs[o] > 0 && (o >= ctx->D || ctx->counts[o] == 0))
+      return ctx->fail(SUGG_E_UNTRAINED_OPT, "optimisation id %d has no fitted model", o);
+  return SUGG_OK;
+}
+
+// Upper bound of the fused kernel's dynamic LDS (weights, per-item tables,
+// metadata, cross-wave lists) for the widest configuration.
+size_t path_lds_bound(size_t tsize, int D, int E, int max_rows, int max_nk, int max_B) {
+  const int vpl = E <= 64 ? 4 : (E <= 128 ? 8 : 16);
+  return tsize * ((size_t)D * 16 * vpl + D + 2 * (size_t)max_rows) + 16 * (size_t)max_nk * (1 + max_B) +
+         (tsize + 8) * 8 * 8 + 256;
+}
+
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+constexpr int kTuneWaves[] = {2, 4, 8};
+constexpr int kTuneUnroll[] = {1, 2, 4};
+
+template <typename T>
+int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* grid, T* table,
+             int32_t* idx, T* score, int32_t* count, int n, hipStream_t s) {
+  if (p->K == 0) return SUGG_OK;
+  if (path_lds_bound(sizeof(T), ctx->D, p->E, p->max_item_rows, p->max_item_kernels, p->Bmax) > kLdsPerWorkgroup)
+    return ctx->fail(SUGG_E_BUDGET, "model of %d optimisations x %d events does not fit in LDS", ctx->D, p->E);
+  PathArgs<T> a;
+  a.counters = c;
+  a.cycles = cyc;
+  a.E = p->E;
+  a.D = ctx->D;
+  a.items = p->d_items;
+  a.recs = p->d_recs;
+  a.K = p->K;
+  a.uni_B = p->uni_B;
+  a.uni_nk = p->uni_nk;
+  a.n_items = p->n_items;
+  a.queue = p->d_queue;
+  a.mu = model_mu<T>(ctx);
+  a.isg = model_isg<T>(ctx);
+  a.W = model_W<T>(ctx);
+  a.grid = grid;
+  a.grid_ld = p->Bmax;
+  a.table = table;
+  a.idx_out = idx;
+  a.score_out = score;
+  a.count_out = count;
+  a.n = n;
+  a.tau = (T)ctx->params.tau;
+  a.status = ctx->d_status;
+  return ctx->hip(launch_path<T>(a, p->max_item_rows, p->max_item_kernels, std::max(1, p->Bmax), p->cfg, s),
+                  "scoring kernel");
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sugg_create(sugg_ctx** out, int32_t device, const sugg_params* params) {
+  if (!out) return SUGG_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SUGG_E_ARG;
+  sugg_ctx* c = new (std::nothrow) sugg_ctx();
+  if (!c) return SUGG_E_BUDGET;
+  c->device = device;
+  c->params.lambda = 1e-2;
+  c->params.tau = std::log(1.05);
+  c->params.n_suggest = 3;
+  if (params) {
+    if (check_params(c, *params)) {
+      delete c;
+      return SUGG_E_ARG;
+    }
+    c->params = *params;
+  }
+  if (hipSetDevice(device) != hipSuccess || hipMalloc((void**)&c->d_status, sizeof(int32_t)) != hipSuccess ||
+      hipMemset(c->d_status, 0, sizeof(int32_t)) != hipSuccess) {
+    delete c;
+    return SUGG_E_HIP;
+  }
+  *out = c;
+  return SUGG_OK;
+}
+
+void sugg_destroy(sugg_ctx* ctx) {
+  if (!ctx) return;
+  (void)device_ok(ctx);
+  ctx->free_model();
+  dfree(ctx->d_status);
+  delete ctx;
+}
+
+const char* sugg_last_error(const sugg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t sugg_set_params(sugg_ctx* ctx, const sugg_params* params) {
+  if (!ctx || !params) return SUGG_E_ARG;
+  int rc = check_params(ctx, *params);
+  if (rc) return rc;
+  ctx->params = *params;
+  return SUGG_OK;
+}
+
+int32_t sugg_get_params(const sugg_ctx* ctx, sugg_params* out) {
+  if (!ctx || !out) return SUGG_E_ARG;
+  *out = ctx->params;
+  return SUGG_OK;
+}
+
+int32_t sugg_plan_create(sugg_ctx* ctx, int32_t K, int32_t E, int32_t D, int32_t dtype, const int32_t* nopts,
+                         const int32_t* opt_ids, sugg_plan** out) {
+  if (!ctx || !out) return SUGG_E_ARG;
+  *out = nullptr;
+  if (K < 0 || (K > 0 && !nopts)) return ctx->fail(SUGG_E_ARG, "bad K or null nopts");
+  if (E < 1 || E > SUGG_MAX_EVENTS) return ctx->fail(SUGG_E_SHAPE, "E=%d outside [1, %d]", E, SUGG_MAX_EVENTS);
+  if (D < 0 || D > SUGG_MAX_GLOBAL_OPTS) return ctx->fail(SUGG_E_SHAPE, "D=%d outside [0, %d]", D, SUGG_MAX_GLOBAL_OPTS);
+  if (dtype != SUGG_F32 && dtype != SUGG_F64) return ctx->fail(SUGG_E_ARG, "bad dtype %d", dtype);
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device %d", ctx->device);
+  sugg_plan* p = new (std::nothrow) sugg_plan();
+  if (!p) return ctx->fail(SUGG_E_BUDGET, "out of host memory");
+  p->ctx = ctx;
+  p->device = ctx->device;
+  p->K = K;
+  p->E = E;
+  p->D = D;
+  p->dtype = dtype;
+  p->nopts.assign(nopts, nopts + K);
+  p->row_off.assign(K + 1, 0);
+  p->opt_off.assign(K + 1, 0);
+  for (int k = 0; k < K; ++k) {
+    const int B = p->nopts[k];
+    if (B < 0 || B > SUGG_MAX_OPTS) {
+      delete p;
+      return ctx->fail(SUGG_E_SHAPE, "kernel %d has %d optimisations (max %d)", k, B, SUGG_MAX_OPTS);
+    }
+    p->Bmax = std::max(p->Bmax, B);
+    p->row_off[k + 1] = p->row_off[k] + ((int64_t)1 << B);
+    p->opt_off[k + 1] = p->opt_off[k] + B;
+  }
+  p->N = p->row_off[K];
+  const int64_t nid = p->opt_off[K];
+  if (nid > 0 && !opt_ids) {
+    delete p;
+    return ctx->fail(SUGG_E_ARG, "null opt_ids");
+  }
+  p->opt_ids.assign(opt_ids, opt_ids + nid);
+  p->opt_pairs.assign(D, 0);
+  for (int k = 0; k < K; ++k) {
+    for (int64_t i = p->opt_off[k]; i < p->opt_off[k + 1]; ++i) {
+      const int o = p->opt_ids[i];
+      if (o < 0 || o >= D || (i > p->opt_off[k] && o <= p->opt_ids[i - 1])) {
+        delete p;
+        return ctx->fail(SUGG_E_SHAPE, "kernel %d: optimisation ids must ascend strictly within [0, %d)", k, D);
+      }
+      p->opt_pairs[o] += (int64_t)1 << (p->nopts[k] - 1);
+    }
+  }
+  // item size: enough items to spread over the chip, at most 256 rows packed
+  const int cus = cu_count(ctx->device);
+  int target = 256;
+  while (target > 64 && p->N / target < 2 * cus) target >>= 1;
+  std::vector<Item> items;
+  std::vector<int32_t> ik;
+  build_items(p->nopts, p->row_off, target, items, ik, p->max_item_rows, p->max_item_kernels);
+  // a batch whose kernels all have the same B gets arithmetic item geometry
+  p->uni_B = -1;
+  p->uni_nk = 0;
+  if (K > 0 && std::all_of(p->nopts.begin(), p->nopts.end(), [&](int32_t b) { return b == p->nopts[0]; })) {
+    p->uni_B = p->nopts[0];
+    p->uni_nk = items[0].nk;
+  }
+  p->n_items = (int)items.size();
+  p->stat_chunks = colstats_chunks(std::max<int64_t>(p->N, 1));
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(p->d_items, items.data(), sizeof(Item) * items.size());
+  std::vector<KRec> recs(ik.size());
+  for (size_t i = 0; i < ik.size(); ++i) {
+    const int k = ik[i];
+    KRec& r = recs[i];
+    std::memset(&r, 0, sizeof r);
+    r.row_off = p->row_off[k];
+    r.kid = k;
+    for (int b = 0; b < p->nopts[k]; ++b) r.opt[b] = (uint8_t)p->opt_ids[p->opt_off[k] + b];
+  }
+  if (e == hipSuccess) e = upload(p->d_recs, recs.data(), sizeof(KRec) * recs.size());
+  if (e == hipSuccess) e = upload(p->d_queue, nullptr, 64);
+  if (e == hipSuccess) e = hipMemset(p->d_queue, 0, 64);
+  if (e == hipSuccess) e = upload(p->d_stat_partial, nullptr, sizeof(double) * 2 * E * p->stat_chunks);
+  if (e != hipSuccess) {
+    delete p;
+    return ctx->hip(e, "plan upload");
+  }
+  *out = p;
+  return SUGG_OK;
+}
+
+void sugg_plan_destroy(sugg_plan* plan) {
+  if (!plan) return;
+  int cur = -1;
+  if (hipGetDevice(&cur) == hipSuccess && cur != plan->device) (void)hipSetDevice(plan->device);
+  delete plan;
+}
+
+int64_t sugg_plan_rows(const sugg_plan* plan) { return plan ? plan->N : -1; }
+int32_t sugg_plan_max_opts(const sugg_plan* plan) { return plan ? plan->Bmax : -1; }
+
+int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                           int32_t mode, void* z_out, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (mode & ~(SUGG_FIT_STATS | SUGG_APPLY) || mode == 0) return ctx->fail(SUGG_E_ARG, "bad mode %d", mode);
+  if (plan->N > 0 && (!counters || !cycles)) return ctx->fail(SUGG_E_ARG, "null counters or cycles");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  sugg_plan* p = const_cast<sugg_plan*>(plan);
+  int rc = SUGG_OK;
+  if (mode & SUGG_FIT_STATS) {
+    if (p->N == 0) return ctx->fail(SUGG_E_SHAPE, "statistics need at least one row");
+    rc = ctx->ensure_model(p->E, (ctx->has_model && ctx->E == p->E) ? ctx->D : 0);
+    if (rc) return rc;
+    if (p->dtype == SUGG_F32)
+      rc = ctx->hip(launch_colstats<float>((const float*)counters, (const float*)cycles, p->N, p->E, p->d_stat_partial,
+                                           p->stat_chunks, ctx->mu64, ctx->sig64, ctx->mu32, ctx->isg32,
+                                           ctx->d_status, stream), "column statistics");
+    else
+      rc = ctx->hip(launch_colstats<double>((const double*)counters, (const double*)cycles, p->N, p->E,
+                                            p->d_stat_partial, p->stat_chunks, ctx->mu64, ctx->sig64, ctx->mu64,
+                                            ctx->isg64, ctx->d_status, stream), "column statistics");
+    if (rc) return rc;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(inv_kernel, dim3((p->E + 255) / 256), dim3(256), 0, stream, ctx->sig64, ctx->isg64, p->E);
+    hipLaunchKernelGGL(stats_to_f32_kernel, dim3((p->E + 255) / 256), dim3(256), 0, stream, ctx->mu64, ctx->sig64,
+                       ctx->mu32, ctx->isg32, p->E);
+    rc = ctx->hip(hipGetLastError(), "statistics");
+    if (rc) return rc;
+    ctx->has_stats = true;
+    // new statistics invalidate fitted weights
+    ctx->has_model = false;
+  }
+  if (mode & SUGG_APPLY) {
+    if (!ctx->has_stats) return ctx->fail(SUGG_E_STATE, "no column statistics");
+    if (ctx->E != p->E) return ctx->fail(SUGG_E_SHAPE, "plan E=%d, statistics E=%d", p->E, ctx->E);
+    if (z_out) {
+      if (p->dtype == SUGG_F32)
+        rc = ctx->hip(launch_standardize<float>((const float*)counters, (const float*)cycles, p->N, p->E, ctx->mu32,
+                                                ctx->isg32, (float*)z_out, ctx->d_status, stream), "standardize");
+      else
+        rc = ctx->hip(launch_standardize<double>((const double*)counters, (const double*)cycles, p->N, p->E,
+                                                 ctx->mu64, ctx->isg64, (double*)z_out, ctx->d_status, stream),
+                      "standardize");
+    }
+  }
+  return rc;
+}
+
+int32_t sugg_fit(sugg_ctx* ctx, const sugg_plan* train, const void* counters, const void* cycles, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!train || train->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (train->N == 0) return ctx->fail(SUGG_E_SHAPE, "empty training batch");
+  if (!counters || !cycles) return ctx->fail(SUGG_E_ARG, "null counters or cycles");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  sugg_plan* p = const_cast<sugg_plan*>(train);
+  if (p->dtype == SUGG_F32) return run_fit<float>(ctx, p, (const float*)counters, (const float*)cycles, stream);
+  return run_fit<double>(ctx, p, (const double*)counters, (const double*)cycles, stream);
+}
+
+int32_t sugg_predict(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles, void* grid_out,
+                     void* table_out, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (plan->N > 0 && (!counters || !cycles || !table_out)) return ctx->fail(SUGG_E_ARG, "null counters, cycles or table");
+  int rc = check_model_for(ctx, plan);
+  if (rc) return rc;
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  if (plan->dtype == SUGG_F32)
+    return run_path<float>(ctx, plan, (const float*)counters, (const float*)cycles, (float*)grid_out,
+                           (float*)table_out, nullptr, nullptr, nullptr, 0, stream);
+  return run_path<double>(ctx, plan, (const double*)counters, (const double*)cycles, (double*)grid_out,
+                          (double*)table_out, nullptr, nullptr, nullptr, 0, stream);
+}
+
+int32_t sugg_suggest(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles, void* table_out,
+                     int32_t* idx_out, void* score_out, int32_t* count_out, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (plan->K > 0 && (!counters || !cycles || !idx_out || !score_out || !count_out))
+    return ctx->fail(SUGG_E_ARG, "null argument");
+  int rc = check_model_for(ctx, plan);
+  if (rc) return rc;
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  const int n = ctx->params.n_suggest;
+  if (plan->dtype == SUGG_F32)
+    return run_path<float>(ctx, plan, (const float*)counters, (const float*)cycles, nullptr, (float*)table_out,
+                           idx_out, (float*)score_out, count_out, n, stream);
+  return run_path<double>(ctx, plan, (const double*)counters, (const double*)cycles, nullptr, (double*)table_out,
+                          idx_out, (double*)score_out, count_out, n, stream);
+}
+
+int32_t sugg_rank_suggest(sugg_ctx* ctx, int32_t dtype, const void* scores, const int64_t* seg_off, int32_t nseg,
+                          int32_t skip_head, int32_t n, double tau, int32_t* idx_out, void* score_out,
+                          int32_t* count_out, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (dtype != SUGG_F32 && dtype != SUGG_F64) return ctx->fail(SUGG_E_ARG, "bad dtype %d", dtype);
+  if (nseg < 0 || skip_head < 0) return ctx->fail(SUGG_E_ARG, "negative nseg or skip_head");
+  if (n < 1 || n > SUGG_MAX_SUGGEST) return ctx->fail(SUGG_E_ARG, "n must be in [1, %d]", SUGG_MAX_SUGGEST);
+  if (std::isnan(tau)) return ctx->fail(SUGG_E_ARG, "tau is NaN");
+  if (nseg == 0) return SUGG_OK;
+  if (!scores || !seg_off || !idx_out || !score_out || !count_out) return ctx->fail(SUGG_E_ARG, "null argument");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  if (dtype == SUGG_F32)
+    return ctx->hip(launch_rank<float>((const float*)scores, seg_off, nseg, skip_head, n, (float)tau, idx_out,
+                                       (float*)score_out, count_out, stream), "rank");
+  return ctx->hip(launch_rank<double>((const double*)scores, seg_off, nseg, skip_head, n, tau, idx_out,
+                                      (double*)score_out, count_out, stream), "rank");
+}
+
+int32_t sugg_sync(sugg_ctx* ctx, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  int rc = ctx->hip(hipStreamSynchronize(stream), "stream synchronize");
+  if (rc) return rc;
+  int32_t st = 0;
+  rc = ctx->hip(hipMemcpy(&st, ctx->d_status, sizeof st, hipMemcpyDeviceToHost), "status read");
+  if (rc) return rc;
+  if (st) {
+    rc = ctx->hip(hipMemset(ctx->d_status, 0, sizeof(int32_t)), "status clear");
+    if (rc) return rc;
+  }
+  if (st & kStatusBadCounter) return ctx->fail(SUGG_E_BAD_COUNTER, "a counter or cycle count is <= 0, NaN or Inf");
+  if (st & kStatusSingular) return ctx->fail(SUGG_E_SINGULAR, "a regression system is not positive definite");
+  return SUGG_OK;
+}
+
+int32_t sugg_plan_set_launch(sugg_plan* plan, int32_t waves, int32_t unroll, int32_t grid) {
+  if (!plan) return SUGG_E_ARG;
+  if (waves < 1 || waves > 8 || (unroll != 1 && unroll != 2 && unroll != 4) || grid < 0) return SUGG_E_ARG;
+  plan->cfg.waves = waves;
+  plan->cfg.unroll = unroll;
+  plan->cfg.grid = grid;
+  return SUGG_OK;
+}
+
+int32_t sugg_plan_get_launch(const sugg_plan* plan, int32_t* waves, int32_t* unroll, int32_t* grid) {
+  if (!plan || !waves || !unroll || !grid) return SUGG_E_ARG;
+  *waves = plan->cfg.waves;
+  *unroll = plan->cfg.unroll;
+  *grid = plan->cfg.grid;
+  return SUGG_OK;
+}
+
+int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, const void* cycles, int32_t reps,
+                      float* times_ms, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (plan->K == 0) return SUGG_OK;
+  if (!counters || !cycles || reps < 1) return ctx->fail(SUGG_E_ARG, "null input or reps < 1");
+  int rc = check_model_for(ctx, plan);
+  if (rc) return rc;
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  const size_t ts = plan->dtype == SUGG_F32 ? 4 : 8;
+  const int n = ctx->params.n_suggest;
+  void *table = nullptr, *idx = nullptr, *score = nullptr, *count = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&table, ts * plan->N);
+  if (e == hipSuccess) e = hipMalloc(&idx, sizeof(int32_t) * plan->K * n);
+  if (e == hipSuccess) e = hipMalloc(&score, ts * plan->K * n);
+  if (e == hipSuccess) e = hipMalloc(&count, sizeof(int32_t) * plan->K);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const PathLaunch keep = plan->cfg;
+  PathLaunch best = keep;
+  float best_ms = 1e30f;
+  int ci = 0;
+  for (int w : kTuneWaves) {
+    for (int u : kTuneUnroll) {
+      if (e != hipSuccess) break;
+      plan->cfg = PathLaunch{w, u, 0};
+      float ms = 0.f;
+      for (int rep = -1; rep < reps && e == hipSuccess; ++rep) {   // rep -1 warms up
+        if (rep == 0) e = hipEventRecord(e0, stream);
+        if (e != hipSuccess) break;
+        rc = plan->dtype == SUGG_F32
+                 ? run_path<float>(ctx, plan, (const float*)counters, (const float*)cycles, nullptr, (float*)table,
+                                   (int32_t*)idx, (float*)score, (int32_t*)count, n, stream)
+                 : run_path<double>(ctx, plan, (const double*)counters, (const double*)cycles, nullptr,
+                                    (double*)table, (int32_t*)idx, (double*)score, (int32_t*)count, n, stream);
+        if (rc) e = hipErrorUnknown;
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      if (times_ms) times_ms[ci] = ms;
+      if (e == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best = plan->cfg;
+      }
+      ++ci;
+    }
+  }
+  plan->cfg = e == hipSuccess ? best : keep;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(table);
+  (void)hipFree(idx);
+  (void)hipFree(score);
+  (void)hipFree(count);
+  if (rc) return rc;
+  return ctx->hip(e, "autotune");
+}
+
+int32_t sugg_capture_begin(sugg_ctx* ctx, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!stream) return ctx->fail(SUGG_E_ARG, "capture needs a non-default stream");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  return ctx->hip(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed), "begin capture");
+}
+
+int32_t sugg_capture_end(sugg_ctx* ctx, hipStream_t stream, sugg_graph** out) {
+  if (!ctx || !out) return SUGG_E_ARG;
+  *out = nullptr;
+  sugg_graph* g = new (std::nothrow) sugg_graph();
+  if (!g) return ctx->fail(SUGG_E_BUDGET, "out of host memory");
+  g->device = ctx->device;
+  int rc = ctx->hip(hipStreamEndCapture(stream, &g->graph), "end capture");
+  if (!rc) rc = ctx->hip(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0), "instantiate graph");
+  if (rc) {
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return SUGG_OK;
+}
+
+int32_t sugg_graph_launch(sugg_ctx* ctx, sugg_graph* graph, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!graph || graph->device != ctx->device) return ctx->fail(SUGG_E_ARG, "graph missing or from another device");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  return ctx->hip(hipGraphLaunch(graph->exec, stream), "graph launch");
+}
+
+void sugg_graph_destroy(sugg_graph* graph) { delete graph; }
+
+int32_t sugg_model_shape(const sugg_ctx* ctx, int32_t* E, int32_t* D) {
+  if (!ctx || !E || !D) return SUGG_E_ARG;
+  *E = ctx->has_stats ? ctx->E : 0;
+  *D = ctx->has_model ? ctx->D : 0;
+  return SUGG_OK;
+}
+
+int32_t sugg_model_get(sugg_ctx* ctx, double* mu, double* sigma, double* W, int64_t* counts) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!ctx->has_stats) return ctx->fail(SUGG_E_STATE, "no model");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  int rc = ctx->hip(hipDeviceSynchronize(), "synchronize");
+  if (rc) return rc;
+  if (mu && (rc = ctx->hip(hipMemcpy(mu, ctx->mu64, sizeof(double) * ctx->E, hipMemcpyDeviceToHost), "copy")))
+    return rc;
+  if (sigma && (rc = ctx->hip(hipMemcpy(sigma, ctx->sig64, sizeof(double) * ctx->E, hipMemcpyDeviceToHost), "copy")))
+    return rc;
+  if (ctx->has_model) {
+    if (W && (rc = ctx->hip(hipMemcpy(W, ctx->W64, sizeof(double) * ctx->D * (ctx->E + 1), hipMemcpyDeviceToHost),
+                            "copy")))
+      return rc;
+    if (counts) std::copy(ctx->counts.begin(), ctx->counts.end(), counts);
+  }
+  return SUGG_OK;
+}
+
+int32_t sugg_model_set(sugg_ctx* ctx, int32_t E, int32_t D, const double* mu, const double* sigma, const double* W,
+                       const int64_t* counts) {
+  if (!ctx) return SUGG_E_ARG;
+  if (E < 1 || E > SUGG_MAX_EVENTS || D < 0 || D > SUGG_MAX_GLOBAL_OPTS) return ctx->fail(SUGG_E_SHAPE, "bad E or D");
+  if (!mu || !sigma || (D > 0 && (!W || !counts))) return ctx->fail(SUGG_E_ARG, "null argument");
+  for (int j = 0; j < E; ++j)
+    if (!(sigma[j] > 0.0) || !std::isfinite(mu[j])) return ctx->fail(SUGG_E_ARG, "bad statistics at column %d", j);
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  int rc = ctx->ensure_model(E, D);
+  if (rc) return rc;
+  std::vector<double> isg(E), w64(W ? W : mu, W ? W + (size_t)D * (E + 1) : mu);
+  std::vector<float> mu32(E), isg32(E), w32((size_t)D * (E + 1));
+  for (int j = 0; j < E; ++j) {
+    isg[j] = 1.0 / sigma[j];
+    mu32[j] = (float)mu[j];
+    isg32[j] = (float)isg[j];
+  }
+  for (int o = 0; o < D; ++o)
+    for (int j = 0; j <= E; ++j) {
+      const double v = W[(size_t)o * (E + 1) + j];
+      w32[(size_t)o * (E + 1) + j] = counts[o] > 0 ? (float)v : 0.0f;
+    }
+  hipError_t e = hipMemcpy(ctx->mu64, mu, sizeof(double) * E, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->sig64, sigma, sizeof(double) * E, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->isg64, isg.data(), sizeof(double) * E, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->mu32, mu32.data(), sizeof(float) * E, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->isg32, isg32.data(), sizeof(float) * E, hipMemcpyHostToDevice);
+  if (e == hipSuccess && D > 0) e = hipMemcpy(ctx->W64, W, sizeof(double) * D * (E + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess && D > 0) e = hipMemcpy(ctx->W32, w32.data(), sizeof(float) * D * (E + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return ctx->hip(e, "model upload");
+  for (int o = 0; o < D; ++o) ctx->counts[o] = counts[o];
+  ctx->has_stats = true;
+  ctx->has_model = D > 0;
+  return SUGG_OK;
+}
+
+}  // extern "C"

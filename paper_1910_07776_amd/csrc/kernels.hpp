@@ -1,0 +1,125 @@
+// Host-side launch interface of the HIP kernels (internal to libsugg).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace sugg {
+
+// One kernel of a work item: where its rows start, its index in the batch and
+// its global optimisation ids (ascending; bit b of a version <-> opt[b]).
+struct alignas(16) KRec {
+  int64_t row_off;
+  int32_t kid;
+  int32_t pad;
+  uint8_t opt[16];
+};
+
+// Arguments of the fused scoring kernel (predict / suggest).
+template <typename T>
+struct PathArgs {
+  const T* counters;       // [N, E]
+  const T* cycles;         // [N]
+  int32_t E;
+  int32_t D;
+  const Item* items;       // work list
+  const KRec* recs;        // kernels of the items, item after item
+  int32_t n_items;
+  int32_t K;
+  int32_t uni_B;           // >= 0: all kernels have uni_B optimisations and item i
+  int32_t uni_nk;          //       holds kernels [i*uni_nk, (i+1)*uni_nk) (items unused)
+  int32_t* queue;          // [2] next item, finished workgroups; zero at launch, re-armed by the kernel
+  const T* mu;             // [E]
+  const T* isg;            // [E] 1 / sigma
+  const T* W;              // [D, E+1]
+  T* grid;                 // [N, grid_ld] or null
+  int32_t grid_ld;
+  T* table;                // [N] or null
+  int32_t* idx_out;        // [K, n] or null (no ranking)
+  T* score_out;
+  int32_t* count_out;
+  int32_t n;
+  T tau;
+  int32_t* status;
+};
+
+struct PathLaunch {
+  int waves;       // waves per workgroup (1..8)
+  int unroll;      // rows per lane group per iteration (1, 2, 4)
+  int grid;        // workgroups (persistent); 0 = occupancy-derived
+};
+
+// Fused normalise -> candidate predict -> compose [-> rank].
+template <typename T>
+hipError_t launch_path(const PathArgs<T>& a, int max_item_rows, int max_item_kernels,
+                       int max_B, const PathLaunch& cfg, hipStream_t s);
+
+// Generic segmented top-n.
+template <typename T>
+hipError_t launch_rank(const T* scores, const int64_t* seg_off, int32_t nseg, int32_t skip_head,
+                       int32_t n, T tau, int32_t* idx_out, T* score_out, int32_t* count_out,
+                       hipStream_t s);
+
+// FP64 column statistics of x = ln(c / cyc) over all N rows.
+template <typename T>
+hipError_t launch_colstats(const T* counters, const T* cycles, int64_t N, int32_t E,
+                           double* partial, int32_t nchunks, double* mu64, double* sig64,
+                           T* mu_t, T* isg_t, int32_t* status, hipStream_t s);
+int colstats_chunks(int64_t N);
+
+// z = (x - mu) / sigma in the plan dtype.
+template <typename T>
+hipError_t launch_standardize(const T* counters, const T* cycles, int64_t N, int32_t E, const T* mu,
+                              const T* isg, T* z, int32_t* status, hipStream_t s);
+
+// FP64 z and ln(cycles) for the regression.
+template <typename T>
+hipError_t launch_zfeat64(const T* counters, const T* cycles, int64_t N, int32_t E,
+                          const double* mu64, const double* sig64, double* z64, double* lcyc64,
+                          hipStream_t s);
+
+// One chunk of one optimisation's training pairs.
+struct GramWork {
+  int32_t opt;
+  int32_t list_begin;   // into the per-optimisation (kernel, bit) list
+  int32_t list_end;
+  int32_t pad;
+  int64_t s_begin;      // sample range within the optimisation's pair space
+  int64_t s_end;
+};
+
+struct GramArgs {
+  const double* z64;        // [N, E]
+  const double* lcyc64;     // [N]
+  int32_t E;
+  const GramWork* work;
+  int32_t n_work;
+  const int64_t* pair_base; // [list] first pair index of each (kernel, bit) entry
+  const int64_t* pair_row0; // [list] row_off of the kernel
+  const int32_t* pair_bit;  // [list] local bit
+  double* partial;          // [n_work, E*E + 2E + 2]
+};
+
+hipError_t launch_gram(const GramArgs& a, hipStream_t s);
+
+// Sum the chunks of every optimisation (work items sorted by opt) and solve.
+struct SolveArgs {
+  const double* partial;
+  const int32_t* opt_work_begin;  // [D+1] range of work items per optimisation
+  int32_t E;
+  int32_t D;
+  double lambda;
+  double* reduced;    // [D, E*E + 2E + 2] workspace: summed partials
+  double* A;          // [D, (E+1)^2] workspace when the system does not fit in LDS
+  double* W64;        // [D, E+1]
+  float* W32;         // [D, E+1]
+  int32_t* status;
+};
+
+hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+}  // namespace sugg

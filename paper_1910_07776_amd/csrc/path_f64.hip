@@ -1,0 +1,12 @@
+// Instantiation of the fused scoring kernel for double counters.
+#include "path_impl.hpp"
+
+namespace sugg {
+
+template <>
+hipError_t launch_path<double>(const PathArgs<double>& a, int max_item_rows, int max_item_kernels, int max_B,
+                            const PathLaunch& cfg, hipStream_t s) {
+  return launch_path_impl<double>(a, max_item_rows, max_item_kernels, max_B, cfg, s);
+}
+
+}  // namespace sugg

@@ -1,0 +1,402 @@
+// The fused scoring kernel: normalise -> predict -> compose -> rank.
+//
+// Section 2's three tiers applied to a ragged batch of kernels in one
+// launch.  Workgroup g first takes item g; when the grid is smaller than the
+// work list, workgroups then pull further items from an atomic counter
+// (persistent mode).  An item is a few whole kernels of equal B, or one large
+// kernel.  For every item:
+//
+//  rows     Sixteen lanes share one counter row (one DPP row): each lane owns
+//           VPL columns and loads them with 16-byte vector loads (the 16 lanes
+//           cover 256 contiguous bytes).  Tier 1's feature, the log of counter
+//           over cycles, is standardised as z = (ln c - ln cyc - mu) / sigma;
+//           in FP32 the hardware base-2 logarithm is used and the ln 2 factor
+//           is folded into 1/sigma, so an element costs one log and one FMA.
+//           The weights of each optimisation sit in LDS; a 4-step DPP
+//           rotate-add sums the 16 partial dot products.  Only the predictions
+//           the composed table needs are formed: row S predicts adding b for
+//           every b above its highest set bit, which gives every subset S'
+//           exactly one incoming edge e[S'] = P(S' without its top bit, top
+//           bit).  With a grid output every b not in S is predicted.
+//  compose  L[S] = sum over bits b of S, ascending, of e[S & (2^(b+1) - 1)]
+//           (the prediction for adding b to S & (2^b - 1)), from LDS.
+//  rank     Tier 3: per kernel, candidates S >= 1 with L > tau, best first
+//           (score descending, S ascending); per-lane best-first lists are
+//           merged with a butterfly of bitonic merges across lanes, and for
+//           kernels with more than 64 versions across waves through LDS.
+//
+// Each row's arithmetic, and each kernel's composition and ranking, depend
+// only on that kernel's data, never on its position in the batch, so ragged
+// batches give bit-identical results to single-kernel batches.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace sugg {
+
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) VecN {
+  T v[VW];
+};
+
+// Natural log for FP64; base-2 hardware log for FP32 (callers scale by ln 2).
+template <typename T> __device__ __forceinline__ T dlog(T x);
+template <> __device__ __forceinline__ float dlog<float>(float x) { return logf(x); }
+template <> __device__ __forceinline__ double dlog<double>(double x) { return log(x); }
+template <typename T> __device__ __forceinline__ T feat_log(T x);
+template <> __device__ __forceinline__ float feat_log<float>(float x) { return __builtin_amdgcn_logf(x); }
+template <> __device__ __forceinline__ double feat_log<double>(double x) { return log(x); }
+template <typename T> __device__ __forceinline__ T feat_log_unit();
+template <> __device__ __forceinline__ float feat_log_unit<float>() { return 0.69314718055994530942f; }
+template <> __device__ __forceinline__ double feat_log_unit<double>() { return 1.0; }
+
+// Dynamic LDS layout of the fused kernel (host and device agree on it).
+struct PathSmem {
+  int ep;        // padded weight row length
+  size_t W, Wb, e, L, kro, kid, kop, xw, total;
+};
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+template <typename T, int VPL, int KT>
+__host__ __device__ inline PathSmem path_smem(int D, int max_rows, int max_nk, int max_B, int nwaves) {
+  PathSmem s;
+  s.ep = kRowLanes * VPL;
+  size_t o = 0;
+  s.W = o;   o += sizeof(T) * (size_t)D * s.ep;
+  s.Wb = o;  o += sizeof(T) * (size_t)D;
+  o = align_up(o, 16);
+  s.e = o;   o += sizeof(T) * (size_t)max_rows;
+  s.L = o;   o += sizeof(T) * (size_t)max_rows;
+  o = align_up(o, 16);
+  s.kro = o; o += sizeof(int64_t) * (size_t)max_nk;
+  s.kid = o; o += sizeof(int32_t) * (size_t)max_nk;
+  s.kop = o; o += sizeof(int32_t) * (size_t)(max_nk * (max_B > 0 ? max_B : 1));
+  o = align_up(o, 16);
+  s.xw = o;  o += sizeof(Entry<T>) * (size_t)KT * nwaves;
+  s.total = align_up(o, 16);
+  return s;
+}
+
+template <typename T, int KT>
+__device__ __forceinline__ void write_list(const Entry<T> (&L)[KT], int k, int n, int32_t* idx_out,
+                                           T* score_out, int32_t* count_out) {
+  int cnt = 0;
+#pragma unroll
+  for (int i = 0; i < KT; ++i) {
+    if (i < n) {
+      const bool ok = L[i].s >= 0;
+      idx_out[(int64_t)k * n + i] = ok ? L[i].s : -1;
+      score_out[(int64_t)k * n + i] = ok ? L[i].v : qnan<T>();
+      cnt += ok ? 1 : 0;
+    }
+  }
+  count_out[k] = cnt;
+}
+
+// FULL: E == 16 * VPL (every lane column is a real column, no bounds checks).
+template <typename T, int VPL, int VW, int U, int KT, bool FULL>
+__global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const int max_rows,
+                                                   const int max_nk, const int max_B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NCH = VPL / VW;
+  const int E = a.E, D = a.D;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, nwaves = nthr >> 6;
+  const int lane = tid & 63, l16 = lane & 15, grp = lane >> 4;
+  const PathSmem ly = path_smem<T, VPL, KT>(D, max_rows, max_nk, max_B, nwaves);
+  T* Wl = reinterpret_cast<T*>(smem + ly.W);
+  T* Wb = reinterpret_cast<T*>(smem + ly.Wb);
+  T* eb = reinterpret_cast<T*>(smem + ly.e);
+  T* Lb = reinterpret_cast<T*>(smem + ly.L);
+  int64_t* kro = reinterpret_cast<int64_t*>(smem + ly.kro);
+  int32_t* kid = reinterpret_cast<int32_t*>(smem + ly.kid);
+  int32_t* kop = reinterpret_cast<int32_t*>(smem + ly.kop);
+  Entry<T>* xw = reinterpret_cast<Entry<T>*>(smem + ly.xw);
+  __shared__ int s_next;
+  const bool dynamic = (int)gridDim.x < a.n_items;
+
+  const int EP = ly.ep;
+  for (int i = tid; i < D * EP; i += nthr) {
+    const int o = i / EP, j = i - o * EP;
+    Wl[i] = (FULL || j < E) ? a.W[(int64_t)o * (E + 1) + j] : T(0);
+  }
+  for (int o = tid; o < D; o += nthr) Wb[o] = a.W[(int64_t)o * (E + 1) + E];
+
+  // this lane's columns: chunk ch covers columns (l16 + 16 ch) * VW + [0, VW);
+  // z = fma(log(c) - log(cyc), s, m) with s = unit / sigma, m = -mu / sigma
+  T s_r[NCH][VW], m_r[NCH][VW];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      const int col = (l16 + kRowLanes * ch) * VW + v;
+      const bool ok = FULL || col < E;
+      const T isg = ok ? a.isg[col] : T(0);
+      s_r[ch][v] = isg * feat_log_unit<T>();
+      m_r[ch][v] = ok ? -a.mu[col] * isg : T(0);
+    }
+  const bool want_grid = a.grid != nullptr;
+  bool bad = false;
+
+  int it = blockIdx.x;
+  while (it < a.n_items) {
+    if (dynamic && tid == 0) s_next = (int)gridDim.x + atomicAdd(a.queue, 1);
+    Item item;
+    if (a.uni_B >= 0) {
+      // every kernel has uni_B optimisations and items take uni_nk adjacent
+      // kernels in batch order: the item needs no lookup
+      item.first = it * a.uni_nk;
+      item.nk = min(a.uni_nk, a.K - item.first);
+      item.B = a.uni_B;
+      item.R = item.nk << a.uni_B;
+      item.row0 = (int64_t)item.first << a.uni_B;
+    } else {
+      item = a.items[it];
+    }
+    const int B = item.B, nk = item.nk, R = item.R;
+    const uint32_t mask = (1u << B) - 1u;
+    const bool contig = item.row0 >= 0;
+    for (int i = tid; i < nk; i += nthr) {
+      const KRec& rec = a.recs[item.first + i];
+      kid[i] = rec.kid;
+      kro[i] = rec.row_off;
+    }
+    for (int i = tid; i < nk * B; i += nthr) {
+      const int kk = i / B, b = i - kk * B;
+      kop[i] = a.recs[item.first + kk].opt[b];
+    }
+
+    // ---- rows: Tier 1 features and Tier 2 predictions ----------------------
+    // Rows past the item are clamped to its last row (read, never written).
+    auto row_addr = [&](int r) -> int64_t {
+      r = r < R ? r : R - 1;
+      return contig ? item.row0 + r : kro[r >> B] + (r & mask);
+    };
+    auto load = [&](int base, T (&c)[U][NCH][VW], T (&cy)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t grow = row_addr(base + u * 4 + grp);
+        const T* rp = a.counters + grow * E;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          const int c0 = (l16 + kRowLanes * ch) * VW;
+          if (FULL || c0 < E) {
+            const VecN<T, VW> q = *reinterpret_cast<const VecN<T, VW>*>(rp + c0);
+#pragma unroll
+            for (int v = 0; v < VW; ++v) c[u][ch][v] = q.v[v];
+          } else {
+#pragma unroll
+            for (int v = 0; v < VW; ++v) c[u][ch][v] = T(1);
+          }
+        }
+        cy[u] = a.cycles[grow];
+      }
+    };
+    auto compute = [&](int base, const T (&c)[U][NCH][VW], const T (&cy)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r0 = base + u * 4;          // row of lane group 0 (uniform)
+        if (r0 >= R) break;
+        const int r = r0 + grp;
+        const bool live = r < R;
+        const T lc = feat_log<T>(cy[u]);
+        T z[NCH][VW];
+        T chk = lc;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+          for (int v = 0; v < VW; ++v) {
+            const T x = feat_log<T>(c[u][ch][v]) - lc;
+            chk += x;
+            z[ch][v] = fma(x, s_r[ch][v], m_r[ch][v]);
+          }
+        // a non-positive, non-normal or non-finite counter or cycle count
+        // makes the checksum NaN or infinite
+        bad |= live && !__builtin_isfinite(chk);
+        const uint32_t S0 = (uint32_t)r0 & mask;
+        const int hlo = (want_grid || S0 == 0) ? 0 : msb(S0) + 1;
+        const int kk = live ? (r >> B) : 0;
+        const uint32_t S = (uint32_t)r & mask;
+        const int ms = msb(S);
+        for (int h = hlo; h < B; ++h) {
+          const int o = kop[kk * B + h];
+          const T* wrow = Wl + o * EP;
+          T part = T(0);
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch) {
+            const VecN<T, VW> w = *reinterpret_cast<const VecN<T, VW>*>(wrow + (l16 + kRowLanes * ch) * VW);
+#pragma unroll
+            for (int v = 0; v < VW; ++v) part = fma(z[ch][v], w.v[v], part);
+          }
+          const T p = row_sum16(part) + Wb[o];
+          if (l16 == 0 && live) {
+            if (want_grid) a.grid[row_addr(r) * a.grid_ld + h] = ((S >> h) & 1u) ? qnan<T>() : p;
+            if (h > ms) eb[r | (1 << h)] = p;
+          }
+        }
+        if (want_grid && l16 == 0 && live) {
+          const int64_t grow = row_addr(r);
+          for (int b = B; b < a.grid_ld; ++b) a.grid[grow * a.grid_ld + b] = qnan<T>();
+        }
+      }
+    };
+
+    // two register buffers: the next rows load while the current ones compute
+    const int step = nwaves * 4 * U;
+    const int b0 = wave * 4 * U;
+    T ca[U][NCH][VW], cb[U][NCH][VW];
+    T cya[U], cyb[U];
+    if (contig && b0 < R) load(b0, ca, cya);   // needs no metadata: before the barrier
+    __syncthreads();
+    if (!contig && b0 < R) load(b0, ca, cya);
+    for (int base = b0; base < R; base += 2 * step) {
+      if (base + step < R) load(base + step, cb, cyb);
+      compute(base, ca, cya);
+      if (base + step >= R) break;
+      if (base + 2 * step < R) load(base + 2 * step, ca, cya);
+      compute(base + step, cb, cyb);
+    }
+    __syncthreads();
+
+    // ---- compose the subset table -----------------------------------------
+    for (int r = tid; r < R; r += nthr) {
+      const uint32_t S = (uint32_t)r & mask;
+      const int kb = r & ~(int)mask;
+      T L = T(0);
+      for (int b = 0; b < B; ++b)
+        if ((S >> b) & 1u) L += eb[kb | (int)(S & ((2u << b) - 1u))];
+      Lb[r] = L;
+      if (a.table) a.table[(contig ? item.row0 + r : kro[r >> B] + S)] = L;
+    }
+    __syncthreads();
+
+    // ---- Tier 3 ranking -----------------------------------------------------
+    if (a.idx_out) {
+      if (B <= 6) {
+        const int G = 1 << B;
+        for (int c0 = wave * kWave; c0 < R; c0 += nwaves * kWave) {
+          Entry<T> lst[KT];
+#pragma unroll
+          for (int i = 0; i < KT; ++i) lst[i] = empty_entry<T>();
+          const int r = c0 + lane;
+          if (r < R) {
+            const int S = r & (int)mask;
+            const T v = Lb[r];
+            if (S != 0 && v > a.tau) { lst[0].v = v; lst[0].s = S; }
+          }
+          group_merge<T, KT>(lst, G);
+          if (r < R && (r & (int)mask) == 0)
+            write_list<T, KT>(lst, kid[r >> B], a.n, a.idx_out, a.score_out, a.count_out);
+        }
+      } else {
+        for (int kk = 0; kk < nk; ++kk) {
+          Entry<T> lst[KT];
+#pragma unroll
+          for (int i = 0; i < KT; ++i) lst[i] = empty_entry<T>();
+          for (int S = tid; S < (1 << B); S += nthr) {
+            const T v = Lb[(kk << B) + S];
+            if (S != 0 && v > a.tau) {
+              Entry<T> e;
+              e.v = v;
+              e.s = S;
+              list_insert<T, KT>(lst, e);
+            }
+          }
+          group_merge<T, KT>(lst, kWave);
+          if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < KT; ++i) xw[wave * KT + i] = lst[i];
+          __syncthreads();
+          if (tid == 0) {
+            for (int w = 1; w < nwaves; ++w) {
+              Entry<T> o[KT];
+#pragma unroll
+              for (int i = 0; i < KT; ++i) o[i] = xw[w * KT + i];
+              list_merge<T, KT>(lst, o);
+            }
+            write_list<T, KT>(lst, kid[kk], a.n, a.idx_out, a.score_out, a.count_out);
+          }
+          __syncthreads();
+        }
+      }
+    }
+    __syncthreads();
+    it = dynamic ? s_next : a.n_items;
+    __syncthreads();
+  }
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(a.status, (int)kStatusBadCounter);
+  // In persistent mode the last workgroup to finish re-arms the work counter
+  // (queue[0] = next item, queue[1] = finished workgroups), so a launch needs
+  // no reset node before it and can be replayed from a graph.
+  if (dynamic && tid == 0) {
+    __threadfence();
+    if (atomicAdd(a.queue + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(a.queue, 0);
+      atomicExch(a.queue + 1, 0);
+    }
+  }
+}
+
+template <typename T, int VPL, int VW, int U, int KT, bool FULL>
+hipError_t launch_path_t(const PathArgs<T>& a, int max_rows, int max_nk, int max_B,
+                         const PathLaunch& cfg, hipStream_t s) {
+  const int nw = cfg.waves;
+  const PathSmem ly = path_smem<T, VPL, KT>(a.D, max_rows, max_nk, max_B, nw);
+  auto kern = path_kernel<T, VPL, VW, U, KT, FULL>;
+  if (ly.total > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)ly.total);
+    if (e != hipSuccess) return e;
+  }
+  int grid = cfg.grid;
+  if (grid <= 0) {
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kern), nw * 64, ly.total);
+    if (e != hipSuccess) return e;
+    grid = cus * (per > 0 ? per : 1);
+  }
+  if (grid > a.n_items) grid = a.n_items;
+  if (grid <= 0) return hipSuccess;
+  (void)hipGetLastError();  // report only this launch's status
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(nw * 64), ly.total, s, a, max_rows, max_nk, max_B);
+  return hipGetLastError();
+}
+
+template <typename T, int VPL, int VW, int KT, bool FULL>
+hipError_t dispatch_u(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c, hipStream_t s) {
+  if (c.unroll >= 4) return launch_path_t<T, VPL, VW, 4, KT, FULL>(a, mr, mk, mb, c, s);
+  if (c.unroll == 2) return launch_path_t<T, VPL, VW, 2, KT, FULL>(a, mr, mk, mb, c, s);
+  return launch_path_t<T, VPL, VW, 1, KT, FULL>(a, mr, mk, mb, c, s);
+}
+
+template <typename T, int VPL, int KT>
+hipError_t dispatch_vw(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c, hipStream_t s) {
+  constexpr int VEC = 16 / sizeof(T);
+  const bool vec_ok = (a.E % VEC) == 0 && (reinterpret_cast<uintptr_t>(a.counters) % 16) == 0;
+  if (vec_ok) {
+    if (a.E == kRowLanes * VPL) return dispatch_u<T, VPL, VEC, KT, true>(a, mr, mk, mb, c, s);
+    return dispatch_u<T, VPL, VEC, KT, false>(a, mr, mk, mb, c, s);
+  }
+  return dispatch_u<T, VPL, 1, KT, false>(a, mr, mk, mb, c, s);
+}
+
+template <typename T, int KT>
+hipError_t dispatch_vpl(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c, hipStream_t s) {
+  if (a.E <= 16 * 4) return dispatch_vw<T, 4, KT>(a, mr, mk, mb, c, s);
+  if (a.E <= 16 * 8) return dispatch_vw<T, 8, KT>(a, mr, mk, mb, c, s);
+  return dispatch_vw<T, 16, KT>(a, mr, mk, mb, c, s);
+}
+
+template <typename T>
+hipError_t launch_path_impl(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c,
+                            hipStream_t s) {
+  if (a.n <= 4) return dispatch_vpl<T, 4>(a, mr, mk, mb, c, s);
+  return dispatch_vpl<T, 8>(a, mr, mk, mb, c, s);
+}
+
+}  // namespace sugg

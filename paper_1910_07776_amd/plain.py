@@ -1,0 +1,279 @@
+"""Python binding of the plain scoring path (argument marshalling only).
+
+Every function passes torch tensors' device pointers and torch's current HIP
+stream to libsugg; all arithmetic runs in the library's HIP kernels.
+
+    ctx  = Context(device=0)
+    plan = Plan(ctx, nopts, opt_ids, E=128, D=6)          # host structure
+    fit(ctx, train_plan, train_counters, train_cycles)    # Tier 2 training
+    idx, score, count, table = suggest(ctx, plan, counters, cycles)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+TAU = math.log(1.05)
+_DT = {torch.float32: A.SUGG_F32, torch.float64: A.SUGG_F64}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """A library context: fitted model, parameters, device status word."""
+
+    def __init__(self, device: int = 0, lam: float = 1e-2, tau: float = TAU, n_suggest: int = 3):
+        L = A.lib()
+        h = C.c_void_p()
+        p = A.Params(lam, tau, n_suggest, 0)
+        A.check(None, L.sugg_create(C.byref(h), int(device), C.byref(p)))
+        self.h = h
+        self.device = torch.device("cuda", int(device))
+
+    def close(self):
+        if getattr(self, "h", None):
+            A.lib().sugg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self):
+        p = A.Params()
+        A.check(self.h, A.lib().sugg_get_params(self.h, C.byref(p)))
+        return {"lam": p.lambda_, "tau": p.tau, "n_suggest": p.n_suggest}
+
+    def set_params(self, lam=None, tau=None, n_suggest=None):
+        cur = self.params
+        p = A.Params(cur["lam"] if lam is None else lam, cur["tau"] if tau is None else tau,
+                     cur["n_suggest"] if n_suggest is None else n_suggest, 0)
+        A.check(self.h, A.lib().sugg_set_params(self.h, C.byref(p)))
+
+    # model checkpoint
+    def model_get(self):
+        E, D = C.c_int32(), C.c_int32()
+        A.check(self.h, A.lib().sugg_model_shape(self.h, C.byref(E), C.byref(D)))
+        E, D = E.value, D.value
+        mu, sg = np.zeros(E), np.zeros(E)
+        W = np.zeros((D, E + 1))
+        cnt = np.zeros(D, dtype=np.int64)
+        f = A.lib().sugg_model_get
+        A.check(self.h, f(self.h, mu.ctypes.data_as(A._PD), sg.ctypes.data_as(A._PD),
+                          W.ctypes.data_as(A._PD), cnt.ctypes.data_as(A._PI64)))
+        return {"mu": mu, "sigma": sg, "W": W, "counts": cnt}
+
+    def model_set(self, m):
+        mu = np.ascontiguousarray(m["mu"], dtype=np.float64)
+        sg = np.ascontiguousarray(m["sigma"], dtype=np.float64)
+        W = np.ascontiguousarray(np.nan_to_num(m["W"]), dtype=np.float64)
+        cnt = np.ascontiguousarray(m["counts"], dtype=np.int64)
+        A.check(self.h, A.lib().sugg_model_set(self.h, len(mu), W.shape[0], mu.ctypes.data_as(A._PD),
+                                               sg.ctypes.data_as(A._PD), W.ctypes.data_as(A._PD),
+                                               cnt.ctypes.data_as(A._PI64)))
+
+
+class Plan:
+    """Structure of a batch: per-kernel optimisation counts and global ids."""
+
+    def __init__(self, ctx: Context, nopts, opt_ids, E: int, D: int, dtype=torch.float32):
+        self.ctx = ctx
+        self.nopts = np.ascontiguousarray(nopts, dtype=np.int32)
+        self.opt_ids = np.ascontiguousarray(opt_ids, dtype=np.int32)
+        self.K, self.E, self.D, self.dtype = len(self.nopts), int(E), int(D), dtype
+        if dtype not in _DT:
+            raise TypeError(f"unsupported dtype {dtype}")
+        h = C.c_void_p()
+        L = A.lib()
+        A.check(ctx.h, L.sugg_plan_create(ctx.h, self.K, self.E, self.D, _DT[dtype],
+                                          self.nopts.ctypes.data_as(A._PI32),
+                                          self.opt_ids.ctypes.data_as(A._PI32), C.byref(h)))
+        self.h = h
+        self.N = int(L.sugg_plan_rows(h))
+        self.Bmax = int(L.sugg_plan_max_opts(h))
+        self.row_off = np.concatenate([[0], np.cumsum(np.left_shift(1, self.nopts.astype(np.int64)))])
+
+    def close(self):
+        if getattr(self, "h", None):
+            A.lib().sugg_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, waves: int, unroll: int, grid: int = 0):
+        A.check(self.ctx.h, A.lib().sugg_plan_set_launch(self.h, waves, unroll, grid))
+
+    def get_launch(self):
+        w, u, g = C.c_int32(), C.c_int32(), C.c_int32()
+        A.check(self.ctx.h, A.lib().sugg_plan_get_launch(self.h, C.byref(w), C.byref(u), C.byref(g)))
+        return {"waves": w.value, "unroll": u.value, "grid": g.value}
+
+    def check_inputs(self, counters, cycles):
+        for name, t, shape in (("counters", counters, (self.N, self.E)), ("cycles", cycles, (self.N,))):
+            if not isinstance(t, torch.Tensor) or t.device != self.ctx.device:
+                raise ValueError(f"{name} must be a tensor on {self.ctx.device}")
+            if t.dtype != self.dtype or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous {self.dtype} of shape {shape}")
+
+
+def load_features(ctx: Context, plan: Plan, counters, cycles, fit_stats: bool = False,
+                  apply: bool = True):
+    """Tier 1 features; returns the standardised features (N x E) when apply."""
+    plan.check_inputs(counters, cycles)
+    mode = (A.SUGG_FIT_STATS if fit_stats else 0) | (A.SUGG_APPLY if apply else 0)
+    z = torch.empty((plan.N, plan.E), dtype=plan.dtype, device=ctx.device) if apply else None
+    A.check(ctx.h, A.lib().sugg_load_features(ctx.h, plan.h, _ptr(counters), _ptr(cycles), mode,
+                                              _ptr(z), _stream()))
+    return z
+
+
+def fit(ctx: Context, plan: Plan, counters, cycles):
+    """Tier 2 training on every before/after pair of the plan's kernels."""
+    plan.check_inputs(counters, cycles)
+    A.check(ctx.h, A.lib().sugg_fit(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _stream()))
+
+
+def predict(ctx: Context, plan: Plan, counters, cycles, grid: bool = False):
+    """Returns (table [N], grid [N, Bmax] or None)."""
+    plan.check_inputs(counters, cycles)
+    table = torch.empty(plan.N, dtype=plan.dtype, device=ctx.device)
+    g = torch.empty((plan.N, plan.Bmax), dtype=plan.dtype, device=ctx.device) if grid else None
+    A.check(ctx.h, A.lib().sugg_predict(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(g),
+                                        _ptr(table), _stream()))
+    return table, g
+
+
+def suggest(ctx: Context, plan: Plan, counters, cycles, table: bool = True, out=None):
+    """The fused path; returns (idx [K, n], score [K, n], count [K], table [N] or None).
+    ``out`` may hold preallocated tensors with the same keys."""
+    plan.check_inputs(counters, cycles)
+    n = ctx.params["n_suggest"]
+    if out is None:
+        out = {"idx": torch.empty((plan.K, n), dtype=torch.int32, device=ctx.device),
+               "score": torch.empty((plan.K, n), dtype=plan.dtype, device=ctx.device),
+               "count": torch.empty(plan.K, dtype=torch.int32, device=ctx.device),
+               "table": torch.empty(plan.N, dtype=plan.dtype, device=ctx.device) if table else None}
+    A.check(ctx.h, A.lib().sugg_suggest(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(out["table"]),
+                                        _ptr(out["idx"]), _ptr(out["score"]), _ptr(out["count"]), _stream()))
+    return out["idx"], out["score"], out["count"], out["table"]
+
+
+def rank_suggest(ctx: Context, scores, seg_off, n: int = 3, tau: float = TAU, skip_head: int = 0):
+    """Tier 3 over segments scores[seg_off[i]:seg_off[i+1]]; returns (idx, score, count)."""
+    if scores.dtype not in _DT or not scores.is_contiguous() or scores.device != ctx.device:
+        raise ValueError("scores must be a contiguous float32/float64 tensor on the context device")
+    if seg_off.dtype != torch.int64 or not seg_off.is_contiguous() or seg_off.device != ctx.device:
+        raise ValueError("seg_off must be a contiguous int64 tensor on the context device")
+    nseg = seg_off.numel() - 1
+    idx = torch.empty((max(nseg, 0), n), dtype=torch.int32, device=ctx.device)
+    sc = torch.empty((max(nseg, 0), n), dtype=scores.dtype, device=ctx.device)
+    cnt = torch.empty(max(nseg, 0), dtype=torch.int32, device=ctx.device)
+    A.check(ctx.h, A.lib().sugg_rank_suggest(ctx.h, _DT[scores.dtype], _ptr(scores), _ptr(seg_off),
+                                             max(nseg, 0), skip_head, n, float(tau), _ptr(idx), _ptr(sc),
+                                             _ptr(cnt), _stream()))
+    return idx, sc, cnt
+
+
+TUNE_WAVES = (2, 4, 8)
+TUNE_UNROLL = (1, 2, 4)
+
+
+def autotune(ctx: Context, plan: Plan, counters, cycles, reps: int = 5, cache=None):
+    """Time every launch shape of the plan's scoring kernel on these inputs
+    and keep the fastest.  ``cache`` (a tuning.TuneCache) is consulted first
+    and updated afterwards.  Returns the chosen shape and the timings."""
+    from . import tuning
+    key = tuning.plan_key(plan, ctx.params["n_suggest"])
+    if cache is not None and key in cache:
+        cfg = cache[key]
+        plan.set_launch(cfg["waves"], cfg["unroll"], 0)
+        return cfg
+    plan.check_inputs(counters, cycles)
+    times = (C.c_float * (len(TUNE_WAVES) * len(TUNE_UNROLL)))()
+    A.check(ctx.h, A.lib().sugg_autotune(ctx.h, plan.h, _ptr(counters), _ptr(cycles), int(reps), times,
+                                         _stream()))
+    cfg = plan.get_launch()
+    cfg["times_ms"] = {f"w{w}u{u}": float(times[i * len(TUNE_UNROLL) + j])
+                       for i, w in enumerate(TUNE_WAVES) for j, u in enumerate(TUNE_UNROLL)}
+    if cache is not None:
+        cache[key] = cfg
+    return cfg
+
+
+class Graph:
+    """Scoring passes recorded once and replayed (hipGraph).
+
+        g = Graph(ctx)
+        with g.capture():
+            suggest(ctx, plan, counters, cycles, out=bufs)   # recorded, not run
+        g.launch()                                           # replays in place
+    """
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.h = None
+        self.stream = torch.cuda.Stream(device=ctx.device)
+
+    class _Cap:
+        def __init__(self, g):
+            self.g = g
+
+        def __enter__(self):
+            g = self.g
+            g.stream.wait_stream(torch.cuda.current_stream(g.ctx.device))
+            self.sctx = torch.cuda.stream(g.stream)
+            self.sctx.__enter__()
+            A.check(g.ctx.h, A.lib().sugg_capture_begin(g.ctx.h, C.c_void_p(g.stream.cuda_stream)))
+            return g
+
+        def __exit__(self, et, ev, tb):
+            g = self.g
+            h = C.c_void_p()
+            rc = A.lib().sugg_capture_end(g.ctx.h, C.c_void_p(g.stream.cuda_stream), C.byref(h))
+            self.sctx.__exit__(et, ev, tb)
+            if et is None:
+                A.check(g.ctx.h, rc)
+                g.h = h
+            return False
+
+    def capture(self):
+        if self.h is not None:
+            raise RuntimeError("graph already captured")
+        return Graph._Cap(self)
+
+    def launch(self):
+        A.check(self.ctx.h, A.lib().sugg_graph_launch(self.ctx.h, self.h, _stream()))
+
+    def close(self):
+        if self.h is not None:
+            A.lib().sugg_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sync(ctx: Context):
+    """Wait for the current stream and raise any device-detected data error."""
+    A.check(ctx.h, A.lib().sugg_sync(ctx.h, _stream()))

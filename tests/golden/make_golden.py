@@ -17,6 +17,9 @@ from synthgen import make_batch  # noqa: E402
 from oracle import plain as P  # noqa: E402
 
 
+RAGGED_TRAIN0 = 1_000_000
+
+
 def digest(*arrays) -> str:
     h = hashlib.sha256()
     for a in arrays:
@@ -39,6 +42,14 @@ def main():
     } for f in folds]
     with open(os.path.join(HERE, "oracle_outputs.json"), "w") as fh:
         json.dump(out, fh, indent=1)
+    # the oracle's model fitted on the ragged training draw of 16,384 kernels
+    # (4-10 optimisations of 10, 128 events, FP32 counters)
+    tr = make_batch(1910, range(RAGGED_TRAIN0, RAGGED_TRAIN0 + 16384), 128, 10, brange=(4, 10))
+    m = P.fit(tr, 10)
+    with open(os.path.join(HERE, "ragged16384_model.json"), "w") as fh:
+        json.dump({"train_ids": [RAGGED_TRAIN0, RAGGED_TRAIN0 + 16384], "E": 128, "D": 10,
+                   "mu": m["mu"].tolist(), "sigma": m["sigma"].tolist(), "W": m["W"].tolist(),
+                   "counts": m["counts"].tolist(), "rows": int(tr.N)}, fh)
 
 
 if __name__ == "__main__":
