@@ -69,14 +69,30 @@ def main():
     ap.add_argument("--warmup", type=int, default=320)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--ragged-only", action="store_true",
+                    help="only the 16,384-kernel ragged measurement (for profiling it alone)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="only run N device-to-device copies of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(args.copy_calib):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copies": args.copy_calib}), flush=True)
+        return
     from synthgen import make_batch
     from paper_1910_07776_amd import plain as G
+    if args.ragged_only:
+        ctx = G.Context(0)
+        print(json.dumps({"ragged_16384": ragged_extra(G, ctx, torch.device("cuda", 0))}), flush=True)
+        return
 
     steps = max(N_BATCHES, (args.steps + N_BATCHES - 1) // N_BATCHES * N_BATCHES)
     warm = (args.warmup + N_BATCHES - 1) // N_BATCHES

@@ -58,7 +58,7 @@ enum {
 };
 
 enum { SUGG_F32 = 0, SUGG_F64 = 1 };          /* dtype of counters and results */
-enum { SUGG_FIT_STATS = 1, SUGG_APPLY = 2 };  /* sugg_load_features modes */
+enum { SUGG_FIT_STATS = 1, SUGG_APPLY = 2, SUGG_BASELINE = 4 };  /* sugg_load_features modes */
 
 #define SUGG_MAX_OPTS 12      /* max optimisations per kernel (4096 versions) */
 #define SUGG_MAX_EVENTS 256   /* max counter events per row */
@@ -68,6 +68,7 @@ enum { SUGG_FIT_STATS = 1, SUGG_APPLY = 2 };  /* sugg_load_features modes */
 typedef struct sugg_ctx sugg_ctx;
 typedef struct sugg_plan sugg_plan;
 typedef struct sugg_graph sugg_graph;
+typedef struct sugg_mlp sugg_mlp;
 
 typedef struct {
   double lambda;      /* ridge penalty on the feature weights (intercept unpenalised) */
@@ -118,6 +119,8 @@ SUGG_API int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* count
  *   computed in FP64 whatever the dtype.
  * mode SUGG_APPLY: requires statistics; z_out (nullable) receives the
  *   standardised features z = (x - mu) / sigma, N x E, plan dtype.
+ * SUGG_APPLY | SUGG_BASELINE: z_out is K x E and holds only each kernel's
+ *   baseline version (S = 0): the learned surrogate's input.
  * FIT_STATS | APPLY does both. */
 SUGG_API int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* counters,
                                     const void* cycles, int32_t mode, void* z_out, hipStream_t stream);
@@ -181,6 +184,49 @@ SUGG_API int32_t sugg_capture_begin(sugg_ctx* ctx, hipStream_t stream);
 SUGG_API int32_t sugg_capture_end(sugg_ctx* ctx, hipStream_t stream, sugg_graph** out);
 SUGG_API int32_t sugg_graph_launch(sugg_ctx* ctx, sugg_graph* graph, hipStream_t stream);
 SUGG_API void sugg_graph_destroy(sugg_graph* graph);
+
+/* ---- Learned surrogate ------------------------------------------------------
+ * An extension of the paper's Tier 2 (which predicts one optimisation at a
+ * time): an MLP in -> hidden -> hidden -> out with exact-erf GELU after both
+ * hidden layers, mapping a kernel's standardised baseline counter vector to
+ * the composed log-speedups of all its 2^B optimisation subsets, trained on
+ * tables from sugg_predict.  BF16 weights and activations, FP32 accumulation
+ * on the matrix cores, FP32 master weights.
+ *
+ * Parameters live in one caller-owned FP32 device buffer of
+ * sugg_mlp_param_count() floats: W1 [hidden x in], b1 [hidden],
+ * W2 [hidden x hidden], b2 [hidden], W3 [out x hidden], b3 [out] (row-major,
+ * weight rows are output units).  Gradients and Adam moments use the same
+ * layout.  x is [batch x in], y and targets [batch x out], FP32 row-major,
+ * device memory.  Widths must be multiples of 8 in [8, 4096]; batch <=
+ * max_batch.  The object owns the BF16 working copies and the activations
+ * kept for the backward; calls on one object must not overlap. */
+SUGG_API int32_t sugg_mlp_create(sugg_ctx* ctx, int32_t in, int32_t hidden, int32_t out, int32_t max_batch,
+                                 sugg_mlp** out_mlp);
+SUGG_API void sugg_mlp_destroy(sugg_mlp* mlp);
+SUGG_API int64_t sugg_mlp_param_count(const sugg_mlp* mlp);
+/* y = MLP(x); keep != 0 saves what sugg_mlp_backward needs. */
+SUGG_API int32_t sugg_mlp_forward(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, const float* x, int32_t batch,
+                                  float* y, int32_t keep, hipStream_t stream);
+/* Forward with targets: loss (device scalar) = mean over batch and outputs of
+ * (y - target)^2; keeps activations and dY = 2 (y - target) / (batch * out).
+ * y is nullable. */
+SUGG_API int32_t sugg_mlp_loss(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, const float* x,
+                               const float* target, int32_t batch, float* y, float* loss, hipStream_t stream);
+/* Hand-written backward of the last keeping forward of this batch: grads of
+ * every parameter for the output gradient dy [batch x out] (nullable: the dY
+ * left by sugg_mlp_loss).  Errors with SUGG_E_STATE without such a forward. */
+SUGG_API int32_t sugg_mlp_backward(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, const float* dy, int32_t batch,
+                                   float* grads, hipStream_t stream);
+/* Adam (Kingma and Ba) with bias correction at step >= 1, in place on params,
+ * m and v. */
+SUGG_API int32_t sugg_mlp_adam(sugg_ctx* ctx, sugg_mlp* mlp, float* params, const float* grads, float* m, float* v,
+                               int32_t step, float lr, float beta1, float beta2, float eps, hipStream_t stream);
+/* sugg_mlp_loss + sugg_mlp_backward + sugg_mlp_adam (beta 0.9 / 0.999,
+ * eps 1e-8); grads is the caller's gradient buffer. */
+SUGG_API int32_t sugg_mlp_train_step(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float* grads, float* m, float* v,
+                                     int32_t step, float lr, const float* x, const float* target, int32_t batch,
+                                     float* loss, hipStream_t stream);
 
 /* Model checkpoint (host arrays, synchronous).  W is D x (E+1), row o =
  * feature weights of optimisation o followed by its intercept; counts[o] is

@@ -16,7 +16,7 @@ ERRORS = {
     -5: "SUGG_E_SINGULAR", -6: "SUGG_E_BUDGET", -7: "SUGG_E_HIP", -8: "SUGG_E_STATE",
 }
 SUGG_F32, SUGG_F64 = 0, 1
-SUGG_FIT_STATS, SUGG_APPLY = 1, 2
+SUGG_FIT_STATS, SUGG_APPLY, SUGG_BASELINE = 1, 2, 4
 SUGG_MAX_OPTS = 12
 SUGG_MAX_EVENTS = 256
 SUGG_MAX_GLOBAL_OPTS = 64
@@ -66,6 +66,14 @@ SIGNATURES = {
     "sugg_capture_end": (_I32, [_P, _P, C.POINTER(_P)]),
     "sugg_graph_launch": (_I32, [_P, _P, _P]),
     "sugg_graph_destroy": (None, [_P]),
+    "sugg_mlp_create": (_I32, [_P, _I32, _I32, _I32, _I32, C.POINTER(_P)]),
+    "sugg_mlp_destroy": (None, [_P]),
+    "sugg_mlp_param_count": (_I64, [_P]),
+    "sugg_mlp_forward": (_I32, [_P, _P, _P, _P, _I32, _P, _I32, _P]),
+    "sugg_mlp_loss": (_I32, [_P, _P, _P, _P, _P, _I32, _P, _P, _P]),
+    "sugg_mlp_backward": (_I32, [_P, _P, _P, _P, _I32, _P, _P]),
+    "sugg_mlp_adam": (_I32, [_P, _P, _P, _P, _P, _P, _I32, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
+    "sugg_mlp_train_step": (_I32, [_P, _P, _P, _P, _P, _P, _I32, C.c_float, _P, _P, _I32, _P, _P]),
     "sugg_model_shape": (_I32, [_P, _PI32, _PI32]),
     "sugg_model_get": (_I32, [_P, _PD, _PD, _PD, _PI64]),
     "sugg_model_set": (_I32, [_P, _I32, _I32, _PD, _PD, _PD, _PI64]),

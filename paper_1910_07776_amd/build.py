@@ -47,7 +47,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
     srcs = sources()
-    with ThreadPoolExecutor(min(8, len(srcs))) as ex:
+    with ThreadPoolExecutor(min(int(os.environ.get("MAX_JOBS", "8")), len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]

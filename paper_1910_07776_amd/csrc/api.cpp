@@ -16,69 +16,7 @@
 
 using namespace sugg;
 
-namespace {
-
-template <typename P>
-void dfree(P*& p) {
-  if (p) (void)hipFree((void*)p);
-  p = nullptr;
-}
-
-}  // namespace
-
-struct sugg_ctx {
-  int device = 0;
-  sugg_params params{};
-  std::string err;
-  int32_t* d_status = nullptr;
-  // model
-  int E = 0, D = 0;
-  bool has_stats = false, has_model = false;
-  double *mu64 = nullptr, *sig64 = nullptr, *isg64 = nullptr, *W64 = nullptr;
-  float *mu32 = nullptr, *isg32 = nullptr, *W32 = nullptr;
-  std::vector<int64_t> counts;
-  int fail(int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    err = buf;
-    return code;
-  }
-  int hip(hipError_t e, const char* what) {
-    if (e == hipSuccess) return SUGG_OK;
-    return fail(SUGG_E_HIP, "%s: %s", what, hipGetErrorString(e));
-  }
-  void free_model() {
-    dfree(mu64); dfree(sig64); dfree(isg64); dfree(W64);
-    dfree(mu32); dfree(isg32); dfree(W32);
-    E = D = 0;
-    has_stats = has_model = false;
-    counts.clear();
-  }
-  // (re)allocate model buffers for shape (e, d); keeps them when unchanged
-  int ensure_model(int e, int d) {
-    if (e == E && d == D && mu64) return SUGG_OK;
-    free_model();
-    hipError_t r = hipSuccess;
-    if (r == hipSuccess) r = hipMalloc((void**)&mu64, sizeof(double) * e);
-    if (r == hipSuccess) r = hipMalloc((void**)&sig64, sizeof(double) * e);
-    if (r == hipSuccess) r = hipMalloc((void**)&isg64, sizeof(double) * e);
-    if (r == hipSuccess) r = hipMalloc((void**)&mu32, sizeof(float) * e);
-    if (r == hipSuccess) r = hipMalloc((void**)&isg32, sizeof(float) * e);
-    if (r == hipSuccess && d > 0) r = hipMalloc((void**)&W64, sizeof(double) * (size_t)d * (e + 1));
-    if (r == hipSuccess && d > 0) r = hipMalloc((void**)&W32, sizeof(float) * (size_t)d * (e + 1));
-    if (r != hipSuccess) {
-      free_model();
-      return hip(r, "model allocation");
-    }
-    E = e;
-    D = d;
-    counts.assign(d, 0);
-    return SUGG_OK;
-  }
-};
+#include "ctx.hpp"
 
 struct sugg_graph {
   hipGraph_t graph = nullptr;
@@ -101,6 +39,7 @@ struct sugg_plan {
   // device structure
   Item* d_items = nullptr;
   KRec* d_recs = nullptr;
+  int64_t* d_row_off = nullptr;
   int32_t* d_queue = nullptr;
   int n_items = 0, max_item_rows = 1, max_item_kernels = 1;
   int uni_B = -1, uni_nk = 0;
@@ -123,7 +62,7 @@ struct sugg_plan {
   int n_gwork = 0;
 
   ~sugg_plan() {
-    dfree(d_items); dfree(d_recs);
+    dfree(d_items); dfree(d_recs); dfree(d_row_off);
     dfree(d_queue); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
     dfree(d_solveA); dfree(d_reduced); dfree(d_gwork); dfree(d_pair_base); dfree(d_pair_row0); dfree(d_pair_bit);
     dfree(d_opt_work_begin);
@@ -145,13 +84,6 @@ hipError_t upload(V*& dst, const void* src, size_t bytes) {
   if (e != hipSuccess) return e;
   if (src) e = hipMemcpy((void*)dst, src, bytes, hipMemcpyHostToDevice);
   return e;
-}
-
-bool device_ok(sugg_ctx* ctx) {
-  int cur = -1;
-  if (hipGetDevice(&cur) != hipSuccess) return false;
-  if (cur != ctx->device) return hipSetDevice(ctx->device) == hipSuccess;
-  return true;
 }
 
 int check_params(sugg_ctx* ctx, const sugg_params& p) {
@@ -514,6 +446,7 @@ int32_t sugg_plan_create(sugg_ctx* ctx, int32_t K, int32_t E, int32_t D, int32_t
   p->stat_chunks = colstats_chunks(std::max<int64_t>(p->N, 1));
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = upload(p->d_items, items.data(), sizeof(Item) * items.size());
+  if (e == hipSuccess) e = upload(p->d_row_off, p->row_off.data(), sizeof(int64_t) * (K + 1));
   std::vector<KRec> recs(ik.size());
   for (size_t i = 0; i < ik.size(); ++i) {
     const int k = ik[i];
@@ -549,7 +482,9 @@ int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* cou
                            int32_t mode, void* z_out, hipStream_t stream) {
   if (!ctx) return SUGG_E_ARG;
   if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
-  if (mode & ~(SUGG_FIT_STATS | SUGG_APPLY) || mode == 0) return ctx->fail(SUGG_E_ARG, "bad mode %d", mode);
+  if (mode & ~(SUGG_FIT_STATS | SUGG_APPLY | SUGG_BASELINE) || mode == 0 ||
+      ((mode & SUGG_BASELINE) && !(mode & SUGG_APPLY)))
+    return ctx->fail(SUGG_E_ARG, "bad mode %d", mode);
   if (plan->N > 0 && (!counters || !cycles)) return ctx->fail(SUGG_E_ARG, "null counters or cycles");
   if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
   sugg_plan* p = const_cast<sugg_plan*>(plan);
@@ -580,7 +515,17 @@ int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* cou
   if (mode & SUGG_APPLY) {
     if (!ctx->has_stats) return ctx->fail(SUGG_E_STATE, "no column statistics");
     if (ctx->E != p->E) return ctx->fail(SUGG_E_SHAPE, "plan E=%d, statistics E=%d", p->E, ctx->E);
-    if (z_out) {
+    if (z_out && (mode & SUGG_BASELINE)) {
+      if (p->dtype == SUGG_F32)
+        rc = ctx->hip(launch_standardize_rows<float>((const float*)counters, (const float*)cycles, p->d_row_off, p->K,
+                                                     p->E, ctx->mu32, ctx->isg32, (float*)z_out, ctx->d_status, stream),
+                      "standardize");
+      else
+        rc = ctx->hip(launch_standardize_rows<double>((const double*)counters, (const double*)cycles, p->d_row_off,
+                                                      p->K, p->E, ctx->mu64, ctx->isg64, (double*)z_out, ctx->d_status,
+                                                      stream),
+                      "standardize");
+    } else if (z_out) {
       if (p->dtype == SUGG_F32)
         rc = ctx->hip(launch_standardize<float>((const float*)counters, (const float*)cycles, p->N, p->E, ctx->mu32,
                                                 ctx->isg32, (float*)z_out, ctx->d_status, stream), "standardize");

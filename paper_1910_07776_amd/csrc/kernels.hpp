@@ -51,7 +51,11 @@ struct PathLaunch {
   int grid;        // workgroups (persistent); 0 = occupancy-derived
 };
 
-// Fused normalise -> candidate predict -> compose [-> rank].
+// Fused normalise -> candidate predict -> compose [-> rank]; VPL = columns
+// per lane (E <= 16 * VPL), instantiated for VPL 4, 8, 16.
+template <typename T, int VPL>
+hipError_t launch_path_vpl(const PathArgs<T>& a, int max_item_rows, int max_item_kernels, int max_B,
+                           const PathLaunch& cfg, hipStream_t s);
 template <typename T>
 hipError_t launch_path(const PathArgs<T>& a, int max_item_rows, int max_item_kernels,
                        int max_B, const PathLaunch& cfg, hipStream_t s);
@@ -73,6 +77,11 @@ int colstats_chunks(int64_t N);
 template <typename T>
 hipError_t launch_standardize(const T* counters, const T* cycles, int64_t N, int32_t E, const T* mu,
                               const T* isg, T* z, int32_t* status, hipStream_t s);
+
+// z of the rows listed in rows[nrows] (e.g. each kernel's baseline version).
+template <typename T>
+hipError_t launch_standardize_rows(const T* counters, const T* cycles, const int64_t* rows, int64_t nrows, int32_t E,
+                                   const T* mu, const T* isg, T* z, int32_t* status, hipStream_t s);
 
 // FP64 z and ln(cycles) for the regression.
 template <typename T>
@@ -121,5 +130,45 @@ struct SolveArgs {
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+// ---- surrogate MLP --------------------------------------------------------
+enum GemmEpilogue : int {
+  kEpiWgrad = 0,       // FP32 split-K partial of a weight gradient
+  kEpiFwdHidden = 1,   // + bias, keep pre-activation, GELU, BF16 row-major and transposed
+  kEpiFwdOut = 2,      // + bias -> Y; with targets: squared error partials and dY
+  kEpiBwdHidden = 3    // * GELU'(pre-activation) -> BF16 row-major and transposed
+};
+
+// C[M x N] = A[M x K] . Bt[N x K]^T, BF16 operands, FP32 accumulation.
+struct GemmArgs {
+  const __bf16* A;
+  int lda;
+  const __bf16* Bt;
+  int ldb;
+  int M, N, K;
+  int k_per_split;       // K range of one split (grid z), multiple of 32
+  const float* bias;     // [N]
+  float* Cf;             // FP32 output (pre-activation, Y or split partials)
+  int ldcf;
+  __bf16* Cb;            // BF16 row-major output
+  int ldcb;
+  __bf16* Ct;            // BF16 transposed output [N x M]
+  int ldct;
+  const float* gact;     // pre-activation for GELU'
+  int ldg;
+  const float* target;   // [M x N] targets
+  int ldt;
+  float* loss_part;      // one partial per output tile
+  float scale;           // dY = scale * (Y - T)
+};
+
+hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s);
+hipError_t launch_pack(const float* src, int rows, int cols, __bf16* dst, int ldd, __bf16* dst_t, int ldt,
+                       hipStream_t s);
+hipError_t launch_splitk_sum(const float* part, int64_t n, int splits, float* out, hipStream_t s);
+hipError_t launch_rowsum(const __bf16* x, int rows, int cols, int ld, float* out, hipStream_t s);
+hipError_t launch_loss_sum(const float* part, int n, float scale, float* loss, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t s);
 
 }  // namespace sugg

@@ -1,0 +1,290 @@
+// C entry points of the surrogate MLP (declared in include/sugg.h): workspace
+// object, forward (inference or training), MSE, hand-written backward, Adam
+// and the fused training step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+
+#include "ctx.hpp"
+
+using namespace sugg;
+
+struct sugg_mlp {
+  sugg_ctx* ctx = nullptr;   // identity only
+  int device = 0;
+  int in = 0, hid = 0, out = 0, bm = 0;   // bm: max batch, multiple of 8
+  int64_t off_w1 = 0, off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0, nparam = 0;
+  // BF16 working weights: row-major [out][in] and, where the backward needs
+  // it, transposed [in][out]
+  __bf16 *w1 = nullptr, *w2 = nullptr, *w2t = nullptr, *w3 = nullptr, *w3t = nullptr;
+  // activations (row-major [batch][features]; transposed [features][bm])
+  __bf16 *xb = nullptr, *xt = nullptr, *h1 = nullptr, *h1t = nullptr, *h2 = nullptr, *h2t = nullptr;
+  __bf16 *dy = nullptr, *dyt = nullptr, *da2 = nullptr, *da2t = nullptr, *da1t = nullptr;
+  float *a1 = nullptr, *a2 = nullptr, *part = nullptr, *loss_part = nullptr, *ybuf = nullptr;
+  int64_t part_n = 0;
+  int kept_batch = -1;    // batch of the last forward that kept activations
+  bool have_dy = false;   // dY of that batch is in dy/dyt (from sugg_mlp_loss)
+  ~sugg_mlp() {
+    dfree(w1); dfree(w2); dfree(w2t); dfree(w3); dfree(w3t);
+    dfree(xb); dfree(xt); dfree(h1); dfree(h1t); dfree(h2); dfree(h2t);
+    dfree(dy); dfree(dyt); dfree(da2); dfree(da2t); dfree(da1t);
+    dfree(a1); dfree(a2); dfree(part); dfree(loss_part); dfree(ybuf);
+  }
+};
+
+namespace {
+
+int splits_for(int M, int N, int K) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int s = std::max(1, 256 / std::max(1, tiles));
+  s = std::min(s, std::max(1, K / 256));
+  return s;
+}
+
+GemmArgs gemm(const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, int N, int K) {
+  GemmArgs g{};
+  g.A = A;
+  g.lda = lda;
+  g.Bt = Bt;
+  g.ldb = ldb;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.k_per_split = (K + 31) / 32 * 32;
+  return g;
+}
+
+// weight gradient dW[M x N] = A[M x K] . Bt[N x K]^T with K split across workgroups
+hipError_t wgrad(sugg_mlp* m, const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, int N, int K, float* dW,
+                 hipStream_t s) {
+  GemmArgs g = gemm(A, lda, Bt, ldb, M, N, K);
+  const int sp = splits_for(M, N, K);
+  g.k_per_split = ((K + sp - 1) / sp + 31) / 32 * 32;
+  const int used = (K + g.k_per_split - 1) / g.k_per_split;
+  g.Cf = m->part;
+  hipError_t e = launch_gemm(g, kEpiWgrad, used, s);
+  if (e != hipSuccess) return e;
+  return launch_splitk_sum(m->part, (int64_t)M * N, used, dW, s);
+}
+
+int check_mlp(sugg_ctx* ctx, sugg_mlp* m, int batch) {
+  if (!m || m->ctx != ctx) return ctx->fail(SUGG_E_ARG, "mlp missing or from another context");
+  if (batch < 1 || batch > m->bm) return ctx->fail(SUGG_E_SHAPE, "batch %d outside [1, %d]", batch, m->bm);
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  return SUGG_OK;
+}
+
+// forward pass; target (nullable) adds the squared-error loss and dY
+int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int B, float* y, bool keep,
+            const float* target, float* loss, hipStream_t s) {
+  const int in = m->in, hid = m->hid, out = m->out, bm = m->bm;
+  hipError_t e = launch_pack(params + m->off_w1, hid, in, m->w1, in, nullptr, 0, s);
+  if (e == hipSuccess) e = launch_pack(params + m->off_w2, hid, hid, m->w2, hid, m->w2t, hid, s);
+  if (e == hipSuccess) e = launch_pack(params + m->off_w3, out, hid, m->w3, hid, m->w3t, out, s);
+  if (e == hipSuccess) e = launch_pack(x, B, in, m->xb, in, keep ? m->xt : nullptr, bm, s);
+  if (e != hipSuccess) return ctx->hip(e, "mlp pack");
+  GemmArgs g = gemm(m->xb, in, m->w1, in, B, hid, in);
+  g.bias = params + m->off_b1;
+  g.Cf = keep ? m->a1 : nullptr;
+  g.ldcf = hid;
+  g.Cb = m->h1;
+  g.ldcb = hid;
+  g.Ct = keep ? m->h1t : nullptr;
+  g.ldct = bm;
+  e = launch_gemm(g, kEpiFwdHidden, 1, s);
+  if (e != hipSuccess) return ctx->hip(e, "mlp layer 1");
+  g = gemm(m->h1, hid, m->w2, hid, B, hid, hid);
+  g.bias = params + m->off_b2;
+  g.Cf = keep ? m->a2 : nullptr;
+  g.ldcf = hid;
+  g.Cb = m->h2;
+  g.ldcb = hid;
+  g.Ct = keep ? m->h2t : nullptr;
+  g.ldct = bm;
+  e = launch_gemm(g, kEpiFwdHidden, 1, s);
+  if (e != hipSuccess) return ctx->hip(e, "mlp layer 2");
+  g = gemm(m->h2, hid, m->w3, hid, B, out, hid);
+  g.bias = params + m->off_b3;
+  g.Cf = y;
+  g.ldcf = out;
+  if (target) {
+    g.target = target;
+    g.ldt = out;
+    g.Cb = m->dy;
+    g.ldcb = out;
+    g.Ct = m->dyt;
+    g.ldct = bm;
+    g.loss_part = m->loss_part;
+    g.scale = 2.0f / ((float)B * (float)out);
+  }
+  e = launch_gemm(g, kEpiFwdOut, 1, s);
+  if (e != hipSuccess) return ctx->hip(e, "mlp layer 3");
+  if (target) {
+    const int tiles = ((B + 63) / 64) * ((out + 63) / 64);
+    e = launch_loss_sum(m->loss_part, tiles, 1.0f / ((float)B * (float)out), loss, s);
+    if (e != hipSuccess) return ctx->hip(e, "mlp loss");
+  }
+  m->kept_batch = keep ? B : -1;
+  m->have_dy = keep && target;
+  return SUGG_OK;
+}
+
+int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grads, hipStream_t s) {
+  (void)params;
+  const int in = m->in, hid = m->hid, out = m->out, bm = m->bm;
+  hipError_t e = wgrad(m, m->dyt, bm, m->h2t, bm, out, hid, B, grads + m->off_w3, s);
+  if (e == hipSuccess) e = launch_rowsum(m->dyt, out, B, bm, grads + m->off_b3, s);
+  if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 3");
+  GemmArgs g = gemm(m->dy, out, m->w3t, out, B, hid, out);
+  g.gact = m->a2;
+  g.ldg = hid;
+  g.Cb = m->da2;
+  g.ldcb = hid;
+  g.Ct = m->da2t;
+  g.ldct = bm;
+  e = launch_gemm(g, kEpiBwdHidden, 1, s);
+  if (e == hipSuccess) e = wgrad(m, m->da2t, bm, m->h1t, bm, hid, hid, B, grads + m->off_w2, s);
+  if (e == hipSuccess) e = launch_rowsum(m->da2t, hid, B, bm, grads + m->off_b2, s);
+  if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 2");
+  g = gemm(m->da2, hid, m->w2t, hid, B, hid, hid);
+  g.gact = m->a1;
+  g.ldg = hid;
+  g.Ct = m->da1t;
+  g.ldct = bm;
+  e = launch_gemm(g, kEpiBwdHidden, 1, s);
+  if (e == hipSuccess) e = wgrad(m, m->da1t, bm, m->xt, bm, hid, in, B, grads + m->off_w1, s);
+  if (e == hipSuccess) e = launch_rowsum(m->da1t, hid, B, bm, grads + m->off_b1, s);
+  if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 1");
+  return SUGG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sugg_mlp_create(sugg_ctx* ctx, int32_t in, int32_t hidden, int32_t out, int32_t max_batch, sugg_mlp** res) {
+  if (!ctx || !res) return SUGG_E_ARG;
+  *res = nullptr;
+  if (in < 8 || hidden < 8 || out < 8 || in % 8 || hidden % 8 || out % 8 || in > 4096 || hidden > 4096 || out > 4096)
+    return ctx->fail(SUGG_E_SHAPE, "layer widths must be multiples of 8 in [8, 4096]");
+  if (max_batch < 1 || max_batch > (1 << 20)) return ctx->fail(SUGG_E_SHAPE, "max_batch outside [1, 2^20]");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  sugg_mlp* m = new (std::nothrow) sugg_mlp();
+  if (!m) return ctx->fail(SUGG_E_BUDGET, "out of host memory");
+  m->ctx = ctx;
+  m->device = ctx->device;
+  m->in = in;
+  m->hid = hidden;
+  m->out = out;
+  m->bm = (max_batch + 7) / 8 * 8;
+  m->off_w1 = 0;
+  m->off_b1 = m->off_w1 + (int64_t)hidden * in;
+  m->off_w2 = m->off_b1 + hidden;
+  m->off_b2 = m->off_w2 + (int64_t)hidden * hidden;
+  m->off_w3 = m->off_b2 + hidden;
+  m->off_b3 = m->off_w3 + (int64_t)out * hidden;
+  m->nparam = m->off_b3 + out;
+  const size_t bm = m->bm, bf = sizeof(__bf16);
+  int64_t part = 0;
+  for (auto mn : {std::pair<int, int>(out, hidden), {hidden, hidden}, {hidden, in}})
+    part = std::max(part, (int64_t)splits_for(mn.first, mn.second, m->bm) * mn.first * mn.second);
+  m->part_n = part;
+  hipError_t e = hipSuccess;
+  auto A = [&](auto*& p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc((void**)&p, std::max<size_t>(bytes, 16));
+  };
+  A(m->w1, bf * hidden * in);
+  A(m->w2, bf * hidden * hidden);
+  A(m->w2t, bf * hidden * hidden);
+  A(m->w3, bf * out * hidden);
+  A(m->w3t, bf * out * hidden);
+  A(m->xb, bf * bm * in);
+  A(m->xt, bf * bm * in);
+  A(m->h1, bf * bm * hidden);
+  A(m->h1t, bf * bm * hidden);
+  A(m->h2, bf * bm * hidden);
+  A(m->h2t, bf * bm * hidden);
+  A(m->dy, bf * bm * out);
+  A(m->dyt, bf * bm * out);
+  A(m->da2, bf * bm * hidden);
+  A(m->da2t, bf * bm * hidden);
+  A(m->da1t, bf * bm * hidden);
+  A(m->a1, sizeof(float) * bm * hidden);
+  A(m->a2, sizeof(float) * bm * hidden);
+  A(m->part, sizeof(float) * part);
+  A(m->loss_part, sizeof(float) * ((bm + 63) / 64) * ((out + 63) / 64));
+  A(m->ybuf, sizeof(float) * bm * out);
+  if (e != hipSuccess) {
+    delete m;
+    return ctx->hip(e, "mlp workspace");
+  }
+  *res = m;
+  return SUGG_OK;
+}
+
+void sugg_mlp_destroy(sugg_mlp* mlp) {
+  if (!mlp) return;
+  int cur = -1;
+  if (hipGetDevice(&cur) == hipSuccess && cur != mlp->device) (void)hipSetDevice(mlp->device);
+  delete mlp;
+}
+
+int64_t sugg_mlp_param_count(const sugg_mlp* mlp) { return mlp ? mlp->nparam : -1; }
+
+int32_t sugg_mlp_forward(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, const float* x, int32_t batch,
+                         float* y, int32_t keep, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  int rc = check_mlp(ctx, mlp, batch);
+  if (rc) return rc;
+  if (!params || !x || !y) return ctx->fail(SUGG_E_ARG, "null argument");
+  return forward(ctx, mlp, params, x, batch, y, keep != 0, nullptr, nullptr, stream);
+}
+
+int32_t sugg_mlp_loss(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, const float* x, const float* target,
+                      int32_t batch, float* y, float* loss, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  int rc = check_mlp(ctx, mlp, batch);
+  if (rc) return rc;
+  if (!params || !x || !target || !loss) return ctx->fail(SUGG_E_ARG, "null argument");
+  return forward(ctx, mlp, params, x, batch, y ? y : mlp->ybuf, true, target, loss, stream);
+}
+
+int32_t sugg_mlp_backward(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, const float* dy, int32_t batch,
+                          float* grads, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  int rc = check_mlp(ctx, mlp, batch);
+  if (rc) return rc;
+  if (!params || !grads) return ctx->fail(SUGG_E_ARG, "null argument");
+  if (mlp->kept_batch != batch) return ctx->fail(SUGG_E_STATE, "backward needs a forward of this batch that kept activations");
+  if (dy) {
+    hipError_t e = launch_pack(dy, batch, mlp->out, mlp->dy, mlp->out, mlp->dyt, mlp->bm, stream);
+    if (e != hipSuccess) return ctx->hip(e, "mlp pack dY");
+  } else if (!mlp->have_dy) {
+    return ctx->fail(SUGG_E_STATE, "no dY: pass dy or run sugg_mlp_loss first");
+  }
+  return backward(ctx, mlp, params, batch, grads, stream);
+}
+
+int32_t sugg_mlp_adam(sugg_ctx* ctx, sugg_mlp* mlp, float* params, const float* grads, float* m, float* v,
+                      int32_t step, float lr, float beta1, float beta2, float eps, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!mlp || mlp->ctx != ctx) return ctx->fail(SUGG_E_ARG, "mlp missing or from another context");
+  if (!params || !grads || !m || !v) return ctx->fail(SUGG_E_ARG, "null argument");
+  if (step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return ctx->fail(SUGG_E_ARG, "bad Adam hyper-parameters");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  return ctx->hip(launch_adam(params, grads, m, v, mlp->nparam, lr, beta1, beta2, eps, step, stream), "adam");
+}
+
+int32_t sugg_mlp_train_step(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float* grads, float* m, float* v,
+                            int32_t step, float lr, const float* x, const float* target, int32_t batch, float* loss,
+                            hipStream_t stream) {
+  int rc = sugg_mlp_loss(ctx, mlp, params, x, target, batch, nullptr, loss, stream);
+  if (rc) return rc;
+  rc = backward(ctx, mlp, params, batch, grads, stream);
+  if (rc) return rc;
+  return sugg_mlp_adam(ctx, mlp, params, grads, m, v, step, lr, 0.9f, 0.999f, 1e-8f, stream);
+}
+
+}  // extern "C"

@@ -95,7 +95,8 @@ __device__ __forceinline__ void write_list(const Entry<T> (&L)[KT], int k, int n
 }
 
 // FULL: E == 16 * VPL (every lane column is a real column, no bounds checks).
-template <typename T, int VPL, int VW, int U, int KT, bool FULL>
+// GRID: the per-optimisation grid is written (every b not in S predicted).
+template <typename T, int VPL, int VW, int U, int KT, bool FULL, bool GRID>
 __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const int max_rows,
                                                    const int max_nk, const int max_B) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -136,7 +137,6 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
       s_r[ch][v] = isg * feat_log_unit<T>();
       m_r[ch][v] = ok ? -a.mu[col] * isg : T(0);
     }
-  const bool want_grid = a.grid != nullptr;
   bool bad = false;
 
   int it = blockIdx.x;
@@ -173,11 +173,16 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
       r = r < R ? r : R - 1;
       return contig ? item.row0 + r : kro[r >> B] + (r & mask);
     };
+    // adjacent kernels: rows addressed by 32-bit offsets from the item's first row
+    const T* ibase = a.counters + (contig ? item.row0 : 0) * E;
+    const T* icyc = a.cycles + (contig ? item.row0 : 0);
     auto load = [&](int base, T (&c)[U][NCH][VW], T (&cy)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t grow = row_addr(base + u * 4 + grp);
-        const T* rp = a.counters + grow * E;
+        int rr = base + u * 4 + grp;
+        rr = rr < R ? rr : R - 1;
+        const int64_t grow = contig ? 0 : kro[rr >> B] + (rr & mask);
+        const T* rp = contig ? ibase + (uint32_t)(rr * E) : a.counters + grow * E;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
           const int c0 = (l16 + kRowLanes * ch) * VW;
@@ -190,7 +195,7 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
             for (int v = 0; v < VW; ++v) c[u][ch][v] = T(1);
           }
         }
-        cy[u] = a.cycles[grow];
+        cy[u] = contig ? icyc[rr] : a.cycles[grow];
       }
     };
     auto compute = [&](int base, const T (&c)[U][NCH][VW], const T (&cy)[U]) {
@@ -215,7 +220,7 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
         // makes the checksum NaN or infinite
         bad |= live && !__builtin_isfinite(chk);
         const uint32_t S0 = (uint32_t)r0 & mask;
-        const int hlo = (want_grid || S0 == 0) ? 0 : msb(S0) + 1;
+        const int hlo = (GRID || S0 == 0) ? 0 : msb(S0) + 1;
         const int kk = live ? (r >> B) : 0;
         const uint32_t S = (uint32_t)r & mask;
         const int ms = msb(S);
@@ -231,11 +236,11 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
           }
           const T p = row_sum16(part) + Wb[o];
           if (l16 == 0 && live) {
-            if (want_grid) a.grid[row_addr(r) * a.grid_ld + h] = ((S >> h) & 1u) ? qnan<T>() : p;
+            if (GRID) a.grid[row_addr(r) * a.grid_ld + h] = ((S >> h) & 1u) ? qnan<T>() : p;
             if (h > ms) eb[r | (1 << h)] = p;
           }
         }
-        if (want_grid && l16 == 0 && live) {
+        if (GRID && l16 == 0 && live) {
           const int64_t grow = row_addr(r);
           for (int b = B; b < a.grid_ld; ++b) a.grid[grow * a.grid_ld + b] = qnan<T>();
         }
@@ -338,12 +343,12 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
   }
 }
 
-template <typename T, int VPL, int VW, int U, int KT, bool FULL>
+template <typename T, int VPL, int VW, int U, int KT, bool FULL, bool GRID>
 hipError_t launch_path_t(const PathArgs<T>& a, int max_rows, int max_nk, int max_B,
                          const PathLaunch& cfg, hipStream_t s) {
   const int nw = cfg.waves;
   const PathSmem ly = path_smem<T, VPL, KT>(a.D, max_rows, max_nk, max_B, nw);
-  auto kern = path_kernel<T, VPL, VW, U, KT, FULL>;
+  auto kern = path_kernel<T, VPL, VW, U, KT, FULL, GRID>;
   if (ly.total > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)ly.total);
@@ -367,36 +372,37 @@ hipError_t launch_path_t(const PathArgs<T>& a, int max_rows, int max_nk, int max
   return hipGetLastError();
 }
 
-template <typename T, int VPL, int VW, int KT, bool FULL>
+template <typename T, int VPL, int VW, int KT, bool FULL, bool GRID>
 hipError_t dispatch_u(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c, hipStream_t s) {
-  if (c.unroll >= 4) return launch_path_t<T, VPL, VW, 4, KT, FULL>(a, mr, mk, mb, c, s);
-  if (c.unroll == 2) return launch_path_t<T, VPL, VW, 2, KT, FULL>(a, mr, mk, mb, c, s);
-  return launch_path_t<T, VPL, VW, 1, KT, FULL>(a, mr, mk, mb, c, s);
+  if (c.unroll >= 4) return launch_path_t<T, VPL, VW, 4, KT, FULL, GRID>(a, mr, mk, mb, c, s);
+  if (c.unroll == 2) return launch_path_t<T, VPL, VW, 2, KT, FULL, GRID>(a, mr, mk, mb, c, s);
+  return launch_path_t<T, VPL, VW, 1, KT, FULL, GRID>(a, mr, mk, mb, c, s);
 }
 
-template <typename T, int VPL, int KT>
-hipError_t dispatch_vw(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c, hipStream_t s) {
+template <typename T, int VPL, int VW, int KT, bool FULL>
+hipError_t dispatch_g(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c, hipStream_t s) {
+  if (a.grid) return dispatch_u<T, VPL, VW, KT, FULL, true>(a, mr, mk, mb, c, s);
+  return dispatch_u<T, VPL, VW, KT, FULL, false>(a, mr, mk, mb, c, s);
+}
+
+// All launch variants for one column count per lane (one translation unit
+// each, so the variants compile in parallel).
+template <typename T, int VPL>
+hipError_t launch_path_vpl(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c, hipStream_t s) {
   constexpr int VEC = 16 / sizeof(T);
   const bool vec_ok = (a.E % VEC) == 0 && (reinterpret_cast<uintptr_t>(a.counters) % 16) == 0;
-  if (vec_ok) {
-    if (a.E == kRowLanes * VPL) return dispatch_u<T, VPL, VEC, KT, true>(a, mr, mk, mb, c, s);
-    return dispatch_u<T, VPL, VEC, KT, false>(a, mr, mk, mb, c, s);
+  if (a.n <= 4) {
+    if (vec_ok) {
+      if (a.E == kRowLanes * VPL) return dispatch_g<T, VPL, VEC, 4, true>(a, mr, mk, mb, c, s);
+      return dispatch_g<T, VPL, VEC, 4, false>(a, mr, mk, mb, c, s);
+    }
+    return dispatch_g<T, VPL, 1, 4, false>(a, mr, mk, mb, c, s);
   }
-  return dispatch_u<T, VPL, 1, KT, false>(a, mr, mk, mb, c, s);
-}
-
-template <typename T, int KT>
-hipError_t dispatch_vpl(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c, hipStream_t s) {
-  if (a.E <= 16 * 4) return dispatch_vw<T, 4, KT>(a, mr, mk, mb, c, s);
-  if (a.E <= 16 * 8) return dispatch_vw<T, 8, KT>(a, mr, mk, mb, c, s);
-  return dispatch_vw<T, 16, KT>(a, mr, mk, mb, c, s);
-}
-
-template <typename T>
-hipError_t launch_path_impl(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c,
-                            hipStream_t s) {
-  if (a.n <= 4) return dispatch_vpl<T, 4>(a, mr, mk, mb, c, s);
-  return dispatch_vpl<T, 8>(a, mr, mk, mb, c, s);
+  if (vec_ok) {
+    if (a.E == kRowLanes * VPL) return dispatch_g<T, VPL, VEC, 8, true>(a, mr, mk, mb, c, s);
+    return dispatch_g<T, VPL, VEC, 8, false>(a, mr, mk, mb, c, s);
+  }
+  return dispatch_g<T, VPL, 1, 8, false>(a, mr, mk, mb, c, s);
 }
 
 }  // namespace sugg

@@ -165,6 +165,40 @@ hipError_t launch_standardize(const T* counters, const T* cycles, int64_t N, int
   return hipGetLastError();
 }
 
+// ---- standardised features of selected rows ------------------------------
+// z[i][j] for row rows[i] (the baseline versions of a batch: rows = row_off).
+template <typename T>
+__global__ void standardize_rows_kernel(const T* __restrict__ c, const T* __restrict__ cyc,
+                                        const int64_t* __restrict__ rows, int64_t nrows, int E,
+                                        const T* __restrict__ mu, const T* __restrict__ isg, T* __restrict__ z,
+                                        int32_t* status) {
+  const int64_t total = nrows * E;
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = i / E;
+    const int j = (int)(i - q * E);
+    const int64_t r = rows[q];
+    const T x = dlog<T>(c[r * E + j]) - dlog<T>(cyc[r]);
+    bad |= !__builtin_isfinite(x);
+    z[i] = (x - mu[j]) * isg[j];
+  }
+  if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(status, (int)kStatusBadCounter);
+}
+
+template <typename T>
+hipError_t launch_standardize_rows(const T* counters, const T* cycles, const int64_t* rows, int64_t nrows, int32_t E,
+                                   const T* mu, const T* isg, T* z, int32_t* status, hipStream_t s) {
+  const int64_t total = nrows * E;
+  if (total <= 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  (void)hipGetLastError();  // report only this launch's status
+  hipLaunchKernelGGL(standardize_rows_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, counters, cycles, rows,
+                     nrows, (int)E, mu, isg, z, status);
+  return hipGetLastError();
+}
+
 // ---- FP64 features for the regression ------------------------------------
 template <typename T>
 __global__ void zfeat64_kernel(const T* __restrict__ c, const T* __restrict__ cyc, int64_t N, int E,
@@ -244,6 +278,8 @@ hipError_t launch_rank(const T* scores, const int64_t* seg_off, int32_t nseg, in
                                          double*, T*, T*, int32_t*, hipStream_t);                         \
   template hipError_t launch_standardize<T>(const T*, const T*, int64_t, int32_t, const T*, const T*, T*, \
                                             int32_t*, hipStream_t);                                       \
+  template hipError_t launch_standardize_rows<T>(const T*, const T*, const int64_t*, int64_t, int32_t, const T*, \
+                                                 const T*, T*, int32_t*, hipStream_t);                         \
   template hipError_t launch_zfeat64<T>(const T*, const T*, int64_t, int32_t, const double*,              \
                                         const double*, double*, double*, hipStream_t);                    \
   template hipError_t launch_rank<T>(const T*, const int64_t*, int32_t, int32_t, int32_t, T, int32_t*, T*, \

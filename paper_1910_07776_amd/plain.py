@@ -135,11 +135,14 @@ class Plan:
 
 
 def load_features(ctx: Context, plan: Plan, counters, cycles, fit_stats: bool = False,
-                  apply: bool = True):
-    """Tier 1 features; returns the standardised features (N x E) when apply."""
+                  apply: bool = True, baseline: bool = False):
+    """Tier 1 features; returns the standardised features when apply: N x E,
+    or K x E of the baseline versions only when baseline."""
     plan.check_inputs(counters, cycles)
-    mode = (A.SUGG_FIT_STATS if fit_stats else 0) | (A.SUGG_APPLY if apply else 0)
-    z = torch.empty((plan.N, plan.E), dtype=plan.dtype, device=ctx.device) if apply else None
+    mode = (A.SUGG_FIT_STATS if fit_stats else 0) | (A.SUGG_APPLY if apply else 0) | \
+        (A.SUGG_BASELINE if baseline else 0)
+    rows = plan.K if baseline else plan.N
+    z = torch.empty((rows, plan.E), dtype=plan.dtype, device=ctx.device) if apply else None
     A.check(ctx.h, A.lib().sugg_load_features(ctx.h, plan.h, _ptr(counters), _ptr(cycles), mode,
                                               _ptr(z), _stream()))
     return z
