@@ -178,6 +178,7 @@ def main():
 
     if not args.no_extra:
         out["ragged_16384"] = ragged_extra(G, ctx, dev)
+        out["surrogate"] = surrogate_extra(G, dev)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -240,6 +241,108 @@ def ragged_extra(G, ctx, dev):
             "predictions_per_s": entries / (ms / 1e3), "suggestions_per_s": te.K / (ms / 1e3),
             "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_pass": by, "fit_ms": fit_ms,
             "autotuned": {"waves": tune["waves"], "unroll": tune["unroll"]}, "tune_ms": tune["times_ms"]}
+
+
+def surrogate_extra(G, dev):
+    """The learned surrogate (MLP 128-512-512-64, BF16 matrix cores): trained
+    on 1M kernels labelled by the plain path until its speedup MAPE on 64K
+    held-out kernels is within 1.02x of the plain composed table's, then
+    surrogate vs plain throughput on 65,536 further kernels."""
+    import torch
+    from synthgen import make_batch
+    from synthgen.torch_world import TorchWorld
+    from paper_1910_07776_amd import surrogate as Sg
+    ctx = G.Context(0)
+    tr = make_batch(1910, range(10 ** 6, 10 ** 6 + 2048), E, D)
+    p = G.Plan(ctx, tr.nopts, tr.opt_ids, E, D)
+    G.fit(ctx, p, torch.from_numpy(tr.counters).to(dev), torch.from_numpy(tr.cycles).to(dev))
+    tw = TorchWorld(1910, E, D)
+    log("surrogate: labelling 1M training kernels with the plain path")
+    t0 = time.perf_counter()
+    data = Sg.build_dataset(ctx, tw, 1 << 20, chunk=65536, chunk_base=0)
+    val = Sg.build_dataset(ctx, tw, 65536, chunk=65536, chunk_base=5000, with_truth=True)
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t0
+    plain_val = Sg.mape(val["Y"], val["T"])
+    mlp = Sg.MLP(ctx, E, 512, 1 << B, max_batch=4096, seed=0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hist = Sg.train(mlp, data["X"], data["Y"], epochs=50, lr=1e-3, val=(val["X"], val["T"]),
+                    target_mape=1.02 * plain_val, check_every=2,
+                    log=lambda r: log(f"surrogate epoch {r['epoch']}: loss {r['loss']:.5f} "
+                                      f"val MAPE {r.get('val_mape', float('nan')):.4f}"))
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    steps = mlp.step
+    flop_step = 3 * 2 * 4096 * (E * 512 + 512 * 512 + 512 * (1 << B))   # forward + backward
+    del data
+
+    # offline comparison on 65,536 held-out kernels of 6 optimisations
+    K = 65536
+    counters, cycles, truth = tw.chunk(9000, K)
+    plan = G.Plan(ctx, np.full(K, B, np.int32), np.tile(np.arange(B, dtype=np.int32), K), E, D)
+    n = ctx.params["n_suggest"]
+    outp = {"idx": torch.empty((K, n), dtype=torch.int32, device=dev), "score": torch.empty((K, n), device=dev),
+            "count": torch.empty(K, dtype=torch.int32, device=dev), "table": torch.empty(K << B, device=dev)}
+    G.autotune(ctx, plan, counters, cycles, reps=3)
+    inf = Sg.MLP(ctx, E, 512, 1 << B, max_batch=K, params=mlp.params.cpu().numpy())
+    z0 = torch.empty((K, E), device=dev)
+    ys = torch.empty((K, 1 << B), device=dev)
+    seg = torch.arange(0, K + 1, dtype=torch.int64, device=dev) * (1 << B)
+
+    def plain_pass():
+        G.suggest(ctx, plan, counters, cycles, out=outp)
+
+    def sur_pass():
+        zz = G.load_features(ctx, plan, counters, cycles, baseline=True)
+        inf(zz, y=ys)
+        return G.rank_suggest(ctx, ys.view(-1), seg, n=n, tau=G.TAU, skip_head=1)
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    plain_ms = timed(plain_pass)
+    sur_ms = timed(sur_pass)
+    # the forward alone (matrix-core roofline)
+    zz = G.load_features(ctx, plan, counters, cycles, baseline=True)
+    fwd_ms = timed(lambda: inf(zz, y=ys))
+    G.sync(ctx)
+    entries = K * ((1 << B) - 1)
+    T = truth.float()
+    m_plain = Sg.mape(outp["table"].view(K, 1 << B), T)
+    m_sur = Sg.mape(ys, T)
+    fwd_flop = 2 * K * (E * 512 + 512 * 512 + 512 * (1 << B))
+    res = {
+        "network": f"{E}-512-512-{1 << B} GELU, BF16 weights/activations, FP32 accumulate",
+        "train_kernels": 1 << 20, "label_s": label_s, "epochs": len(hist), "steps": steps,
+        "train_ms": train_ms, "train_samples_per_s": steps * 4096 / (train_ms / 1e3),
+        "train_tflops": steps * flop_step / (train_ms / 1e3) / 1e12,
+        "val_mape_plain": plain_val, "val_mape_surrogate": hist[-1].get("val_mape"),
+        "matched_mape": bool(hist[-1].get("val_mape", 1e9) <= 1.02 * plain_val),
+        "test_kernels": K, "test_mape_plain": m_plain, "test_mape_surrogate": m_sur,
+        "plain_ms": plain_ms, "surrogate_ms": sur_ms,
+        "plain_predictions_per_s": entries / (plain_ms / 1e3),
+        "surrogate_predictions_per_s": entries / (sur_ms / 1e3),
+        "surrogate_suggestions_per_s": K / (sur_ms / 1e3),
+        "forward_ms": fwd_ms, "forward_tflops": fwd_flop / (fwd_ms / 1e3) / 1e12,
+        "forward_mfma_frac": fwd_flop / (fwd_ms / 1e3) / 2.5e15,
+    }
+    log(f"surrogate: {res['surrogate_predictions_per_s']:.3e} vs plain {res['plain_predictions_per_s']:.3e} "
+        f"predictions/s; MAPE {m_sur:.4f} vs {m_plain:.4f}; forward {res['forward_tflops']:.1f} TFLOP/s")
+    inf.close()
+    mlp.close()
+    ctx.close()
+    return res
 
 
 if __name__ == "__main__":

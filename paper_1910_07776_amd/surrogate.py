@@ -160,3 +160,102 @@ class SurrogateFn(torch.autograd.Function):
         grads = torch.empty_like(params)
         fctx.mlp.backward_raw(params.detach(), dy.contiguous().float(), fctx.B, grads)
         return None, grads, None
+
+
+# ---------------------------------------------------------------- training --
+def subset_bits(B: int, device) -> torch.Tensor:
+    """[2^B, B] 0/1 matrix: bit b of subset S."""
+    S = torch.arange(1 << B, device=device)
+    return ((S[:, None] >> torch.arange(B, device=device)) & 1).float()
+
+
+def label_chunk(ctx, plan, counters, cycles, B: int, with_additive: bool = False):
+    """Plain-method labels of a uniform batch (every kernel B optimisations):
+    X = standardised baseline counters [K, E], Y = composed tables [K, 2^B]
+    (sugg_predict), and optionally the baseline-only additive table
+    sum_{b in S} P(baseline, b) from the grid's baseline rows."""
+    from .plain import load_features, predict
+    table, grid = predict(ctx, plan, counters, cycles, grid=with_additive)
+    X = load_features(ctx, plan, counters, cycles, baseline=True)
+    Y = table.view(plan.K, 1 << B)
+    add = None
+    if with_additive:
+        g0 = grid[torch.as_tensor(plan.row_off[:-1], device=grid.device)][:, :B]
+        add = g0 @ subset_bits(B, grid.device).T
+    return X, Y, add
+
+
+def build_dataset(ctx, tw, n_kernels: int, chunk: int = 65536, chunk_base: int = 0, with_truth: bool = False,
+                  with_additive: bool = False):
+    """Draw n_kernels kernels of the TorchWorld tw in chunks and label them
+    with the plain path.  Returns a dict of device tensors X, Y (and T, the
+    generator's true log-speedups; A, the additive baseline-only table)."""
+    from .plain import Plan
+    B, E, dev = tw.B, tw.E, ctx.device
+    out = {"X": torch.empty((n_kernels, E), device=dev), "Y": torch.empty((n_kernels, 1 << B), device=dev)}
+    if with_truth:
+        out["T"] = torch.empty((n_kernels, 1 << B), device=dev)
+    if with_additive:
+        out["A"] = torch.empty((n_kernels, 1 << B), device=dev)
+    plans = {}
+    for i, c0 in enumerate(range(0, n_kernels, chunk)):
+        K = min(chunk, n_kernels - c0)
+        if K not in plans:
+            plans[K] = Plan(ctx, np.full(K, B, np.int32), np.tile(np.arange(B, dtype=np.int32), K), E, tw.D)
+        counters, cycles, truth = tw.chunk(chunk_base + i, K)
+        X, Y, add = label_chunk(ctx, plans[K], counters, cycles, B, with_additive)
+        out["X"][c0:c0 + K] = X
+        out["Y"][c0:c0 + K] = Y
+        if with_truth:
+            out["T"][c0:c0 + K] = truth.float()
+        if with_additive:
+            out["A"][c0:c0 + K] = add
+        del counters, cycles
+    return out
+
+
+def predict_table(mlp: MLP, X: torch.Tensor, batch: int | None = None) -> torch.Tensor:
+    """Surrogate table for every row of X, in batches of the MLP's capacity."""
+    batch = batch or mlp.max_batch
+    Y = torch.empty((X.shape[0], mlp.out), device=X.device)
+    for i in range(0, X.shape[0], batch):
+        mlp(X[i:i + batch].contiguous(), y=Y[i:i + batch])
+    return Y
+
+
+def mape(pred: torch.Tensor, truth: torch.Tensor) -> float:
+    """Mean absolute percentage error of predicted speedups e^pred against
+    e^truth over every kernel and subset S != 0 (column 0 is the baseline)."""
+    p, t = pred[:, 1:].double(), truth[:, 1:].double()
+    return float((torch.abs(torch.exp(p) - torch.exp(t)) / torch.exp(t)).mean().item())
+
+
+def train(mlp: MLP, X: torch.Tensor, Y: torch.Tensor, epochs: int, batch: int = 4096, lr: float = 1e-3,
+          seed: int = 0, val=None, target_mape=None, check_every: int = 5, log=None):
+    """Adam on the MSE of log-speedups over shuffled mini-batches.  Stops early
+    once val = (X, T) gives a MAPE <= target_mape.  Returns a history list."""
+    dev = X.device
+    n = X.shape[0]
+    steps = max(1, n // batch)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    xb = torch.empty((batch, X.shape[1]), device=dev)
+    yb = torch.empty((batch, Y.shape[1]), device=dev)
+    hist = []
+    for ep in range(1, epochs + 1):
+        perm = torch.randperm(n, generator=g, device=dev)
+        tot = torch.zeros((), device=dev)
+        for s in range(steps):
+            idx = perm[s * batch:(s + 1) * batch]
+            torch.index_select(X, 0, idx, out=xb)
+            torch.index_select(Y, 0, idx, out=yb)
+            tot += mlp.train_step(xb, yb, lr)[0]
+        rec = {"epoch": ep, "loss": float(tot.item()) / steps}
+        if val is not None and (ep % check_every == 0 or ep == epochs):
+            rec["val_mape"] = mape(predict_table(mlp, val[0]), val[1])
+        hist.append(rec)
+        if log:
+            log(rec)
+        if target_mape is not None and rec.get("val_mape", 1e9) <= target_mape:
+            break
+    return hist

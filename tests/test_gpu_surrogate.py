@@ -128,3 +128,30 @@ def test_fused_step_equals_separate_calls_and_overfits(S, ctx):
         b.backward_raw(b.params, None, 95, b.grads)   # no kept forward of that batch
     a.close()
     b.close()
+
+
+def test_trained_surrogate_gains_over_baseline_only_method(S, ctx):
+    """What the trained network gains over the method without it: from the
+    same input (a kernel's baseline profile only), the surrogate's speedup
+    MAPE against the generator's truth beats the sum of the plain models'
+    single-optimisation predictions for the baseline version.  The plain
+    composed table, which needs all 64 profiled versions, is reported."""
+    plain, sur = S
+    from synthgen import make_batch
+    from synthgen.torch_world import TorchWorld
+    tr = make_batch(1910, range(10 ** 6, 10 ** 6 + 2048), 128, 6)
+    p = plain.Plan(ctx, tr.nopts, tr.opt_ids, 128, 6)
+    plain.fit(ctx, p, torch.from_numpy(tr.counters).cuda(), torch.from_numpy(tr.cycles).cuda())
+    tw = TorchWorld(1910, 128, 6)
+    data = sur.build_dataset(ctx, tw, 131072, chunk=65536, chunk_base=0)
+    val = sur.build_dataset(ctx, tw, 16384, chunk=16384, chunk_base=5000, with_truth=True, with_additive=True)
+    plain.sync(ctx)
+    mlp = sur.MLP(ctx, 128, 512, 64, max_batch=4096, seed=1)
+    hist = sur.train(mlp, data["X"], data["Y"], epochs=12, lr=1e-3, val=(val["X"], val["T"]), check_every=12)
+    m_sur = hist[-1]["val_mape"]
+    m_add = sur.mape(val["A"], val["T"])
+    m_plain = sur.mape(val["Y"], val["T"])
+    print(f"MAPE surrogate {m_sur:.4f}  additive-from-baseline {m_add:.4f}  plain chain {m_plain:.4f}")
+    assert hist[-1]["loss"] < hist[0]["loss"]
+    assert m_sur < m_add
+    mlp.close()
