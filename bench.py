@@ -179,6 +179,7 @@ def main():
     if not args.no_extra:
         out["ragged_16384"] = ragged_extra(G, ctx, dev)
         out["surrogate"] = surrogate_extra(G, dev)
+        out["serving"] = serving_extra(G, dev)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -341,6 +342,81 @@ def surrogate_extra(G, dev):
         f"predictions/s; MAPE {m_sur:.4f} vs {m_plain:.4f}; forward {res['forward_tflops']:.1f} TFLOP/s")
     inf.close()
     mlp.close()
+    ctx.close()
+    return res
+
+
+def serving_extra(G, dev, n_queries: int = 3000):
+    """Profiling queries of 1-4096 kernels (log-uniform), B ~ U{6..10}, Poisson
+    arrivals at 50 % and 80 % of the measured surrogate capacity, HBM budget
+    8 GB: surrogate + judge + plain fallback, and the plain path alone on the
+    80 % trace.  Inputs are resident (one pool of 4096 kernels per B)."""
+    import torch
+    from synthgen import make_batch
+    from synthgen.torch_world import TorchWorld
+    from paper_1910_07776_amd import serve, surrogate as Sg
+    ctx = G.Context(0)
+    Dg = 10
+    tr = make_batch(1910, range(10 ** 6, 10 ** 6 + 4096), E, Dg, brange=(4, 10))
+    G.fit(ctx, G.Plan(ctx, tr.nopts, tr.opt_ids, E, Dg), torch.from_numpy(tr.counters).to(dev),
+          torch.from_numpy(tr.cycles).to(dev))
+    del tr
+    nets, pools, train_info = {}, {}, {}
+    for Bq in range(6, 11):
+        tw = TorchWorld(1910, E, Dg, B=Bq)
+        ntr = {6: 1 << 18, 7: 1 << 18, 8: 1 << 17, 9: 1 << 16, 10: 1 << 15}[Bq]
+        chunk = max(1024, (1 << 22) >> Bq)
+        data = Sg.build_dataset(ctx, tw, ntr, chunk=chunk, chunk_base=0)
+        val = Sg.build_dataset(ctx, tw, 8192, chunk=min(chunk, 8192), chunk_base=5000, with_truth=True)
+        mlp = Sg.MLP(ctx, E, 512, 1 << Bq, max_batch=4096, seed=Bq)
+        hist = Sg.train(mlp, data["X"], data["Y"], epochs=4, lr=1e-3, val=(val["X"], val["T"]), check_every=4)
+        train_info[Bq] = {"train_kernels": ntr, "val_mape_surrogate": hist[-1]["val_mape"],
+                          "val_mape_plain": Sg.mape(val["Y"], val["T"])}
+        log(f"serving: B={Bq} surrogate MAPE {hist[-1]['val_mape']:.4f} "
+            f"(plain {train_info[Bq]['val_mape_plain']:.4f})")
+        nets[Bq] = mlp
+        del data, val
+        c, cy, _ = tw.chunk(7000, 4096)
+        pools[Bq] = (c, cy)
+    srv = serve.Server(ctx, nets, n=3, tol=0.1, budget_bytes=8 << 30)
+    rng = np.random.default_rng(11)
+    qs = []
+    for _ in range(n_queries):
+        Bq = int(rng.integers(6, 11))
+        K = int(np.floor(np.exp(rng.uniform(0, np.log(4096)))))
+        k0 = int(rng.integers(0, 4096 - K + 1))
+        c, cy = pools[Bq]
+        plan = srv.plan(Bq, K, E, Dg)
+        rows = slice(k0 << Bq, (k0 + K) << Bq)
+        out = {"idx": torch.empty((K, 3), dtype=torch.int32, device=dev), "score": torch.empty((K, 3), device=dev),
+               "count": torch.empty(K, dtype=torch.int32, device=dev), "table": None}
+        qs.append((plan, c[rows], cy[rows], out, serve.Server.footprint(K, Bq, E)))
+    # closed loop: service capacity
+    for q in qs[:50]:
+        srv.answer(*q[:4])
+    torch.cuda.synchronize()
+    srv.fallbacks.zero_()
+    srv.kernels_total = 0
+    t0 = time.perf_counter()
+    for q in qs:
+        srv.answer(*q[:4])
+    torch.cuda.synchronize()
+    busy = time.perf_counter() - t0
+    cap = len(qs) / busy
+    fallback_rate = float(srv.fallbacks.item()) / max(1, srv.kernels_total)
+    res = {"queries": len(qs), "capacity_qps": cap, "fallback_rate": fallback_rate,
+           "kernels_per_s_closed_loop": srv.kernels_total / busy, "nets": train_info}
+    for frac in (0.5, 0.8):
+        arr = serve.poisson_arrivals(len(qs), frac * cap, seed=int(frac * 100))
+        st = serve.run_loop(srv, qs, arr)
+        res[f"surrogate_at_{int(frac * 100)}pct"] = st
+        log(f"serving {int(frac * 100)}%: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms")
+        if frac == 0.8:
+            stp = serve.run_loop(srv, qs, arr, plain_only=True)
+            res["plain_only_same_trace"] = stp
+            log(f"plain only, same trace: p50 {stp['p50_ms']:.3f} ms p99 {stp['p99_ms']:.3f} ms")
+    for m in nets.values():
+        m.close()
     ctx.close()
     return res
 

@@ -166,6 +166,27 @@ SUGG_API int32_t sugg_suggest(sugg_ctx* ctx, const sugg_plan* plan, const void* 
                               const void* cycles, void* table_out, int32_t* idx_out,
                               void* score_out, int32_t* count_out, hipStream_t stream);
 
+/* sugg_suggest restricted to the kernels with kmask[k] != 0 (device int32
+ * [K]): only their rows are read and only their table entries and
+ * suggestion lists are written; the other kernels' outputs are left as they
+ * are.  Used to re-score kernels whose learned-surrogate answer was rejected. */
+SUGG_API int32_t sugg_suggest_subset(sugg_ctx* ctx, const sugg_plan* plan, const void* counters,
+                                     const void* cycles, const int32_t* kmask, void* table_out,
+                                     int32_t* idx_out, void* score_out, int32_t* count_out, hipStream_t stream);
+
+/* Judge: the plain composed log-speedup (sugg_predict's table value) of C
+ * given subsets per kernel, reading only the versions on each subset's
+ * ascending chain (popcount(S) rows).  cand [K x C] device int32 subset
+ * bitmasks (< 0: none); out [K x C] plan dtype: the table value, bit-identical
+ * to sugg_predict's; 0 for S = 0; NaN for none or S >= 2^B_k.  1 <= C <= 64.
+ * With ref [K x C] (e.g. a learned surrogate's values of the same subsets)
+ * and flag_out [K] (both device, or both null): flag_out[k] = 1 when some
+ * candidate S >= 1 of kernel k has |ref - out| > tol (or a non-finite
+ * difference), else 0. */
+SUGG_API int32_t sugg_judge(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                            const int32_t* cand, int32_t C, void* out, const void* ref, double tol,
+                            int32_t* flag_out, hipStream_t stream);
+
 /* Waits for the stream, then returns and clears the device status word:
  * SUGG_E_BAD_COUNTER or SUGG_E_SINGULAR if a kernel flagged one since the
  * last sync, else SUGG_OK. */

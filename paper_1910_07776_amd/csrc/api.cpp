@@ -40,6 +40,9 @@ struct sugg_plan {
   Item* d_items = nullptr;
   KRec* d_recs = nullptr;
   int64_t* d_row_off = nullptr;
+  int64_t* d_opt_off = nullptr;
+  int32_t* d_opt_ids = nullptr;
+  int32_t* d_nopts = nullptr;
   int32_t* d_queue = nullptr;
   int n_items = 0, max_item_rows = 1, max_item_kernels = 1;
   int uni_B = -1, uni_nk = 0;
@@ -62,7 +65,7 @@ struct sugg_plan {
   int n_gwork = 0;
 
   ~sugg_plan() {
-    dfree(d_items); dfree(d_recs); dfree(d_row_off);
+    dfree(d_items); dfree(d_recs); dfree(d_row_off); dfree(d_opt_off); dfree(d_opt_ids); dfree(d_nopts);
     dfree(d_queue); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
     dfree(d_solveA); dfree(d_reduced); dfree(d_gwork); dfree(d_pair_base); dfree(d_pair_row0); dfree(d_pair_bit);
     dfree(d_opt_work_begin);
@@ -162,6 +165,12 @@ __global__ void stats_to_f32_kernel(const double* mu, const double* sig, float* 
   }
 }
 
+int ensure_stat_ws(sugg_ctx* ctx, sugg_plan* p) {
+  if (p->d_stat_partial) return SUGG_OK;
+  return ctx->hip(hipMalloc((void**)&p->d_stat_partial, sizeof(double) * 2 * p->E * p->stat_chunks),
+                  "statistics workspace");
+}
+
 int prepare_fit(sugg_ctx* ctx, sugg_plan* p) {
   if (p->fit_ready) return SUGG_OK;
   const int E = p->E, D = p->D;
@@ -223,6 +232,7 @@ int prepare_fit(sugg_ctx* ctx, sugg_plan* p) {
 template <typename T>
 int run_fit(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, hipStream_t s) {
   int rc = prepare_fit(ctx, p);
+  if (!rc) rc = ensure_stat_ws(ctx, p);
   if (rc) return rc;
   rc = ctx->ensure_model(p->E, p->D);
   if (rc) return rc;
@@ -293,11 +303,13 @@ constexpr int kTuneUnroll[] = {1, 2, 4};
 
 template <typename T>
 int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* grid, T* table,
-             int32_t* idx, T* score, int32_t* count, int n, hipStream_t s) {
+             int32_t* idx, T* score, int32_t* count, int n, hipStream_t s, const int32_t* kmask = nullptr) {
   if (p->K == 0) return SUGG_OK;
   if (path_lds_bound(sizeof(T), ctx->D, p->E, p->max_item_rows, p->max_item_kernels, p->Bmax) > kLdsPerWorkgroup)
     return ctx->fail(SUGG_E_BUDGET, "model of %d optimisations x %d events does not fit in LDS", ctx->D, p->E);
   PathArgs<T> a;
+  a.judge = nullptr;
+  a.kmask = kmask;
   a.counters = c;
   a.cycles = cyc;
   a.E = p->E;
@@ -323,6 +335,39 @@ int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* gri
   a.status = ctx->d_status;
   return ctx->hip(launch_path<T>(a, p->max_item_rows, p->max_item_kernels, std::max(1, p->Bmax), p->cfg, s),
                   "scoring kernel");
+}
+
+}  // namespace
+
+namespace {
+
+template <typename T>
+int run_judge(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, const int32_t* cand, int32_t C,
+                     T* out, const T* ref, double tol, int32_t* flag, hipStream_t s) {
+  JudgeArgs<T> j;
+  j.counters = c;
+  j.cycles = cyc;
+  j.E = p->E;
+  j.D = ctx->D;
+  j.W = model_W<T>(ctx);
+  j.mu = model_mu<T>(ctx);
+  j.isg = model_isg<T>(ctx);
+  j.row_off = p->d_row_off;
+  j.nopts = p->d_nopts;
+  j.opt_off = p->d_opt_off;
+  j.opt_ids = p->d_opt_ids;
+  j.K = p->K;
+  j.C = C;
+  j.cand = cand;
+  j.out = out;
+  j.ref = ref;
+  j.tol = tol;
+  j.flag = flag;
+  j.status = ctx->d_status;
+  PathArgs<T> a{};
+  a.judge = &j;
+  a.E = p->E;
+  return ctx->hip(launch_path<T>(a, 1, 1, 1, p->cfg, s), "judge");
 }
 
 }  // namespace
@@ -447,6 +492,9 @@ int32_t sugg_plan_create(sugg_ctx* ctx, int32_t K, int32_t E, int32_t D, int32_t
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = upload(p->d_items, items.data(), sizeof(Item) * items.size());
   if (e == hipSuccess) e = upload(p->d_row_off, p->row_off.data(), sizeof(int64_t) * (K + 1));
+  if (e == hipSuccess) e = upload(p->d_opt_off, p->opt_off.data(), sizeof(int64_t) * (K + 1));
+  if (e == hipSuccess) e = upload(p->d_opt_ids, p->opt_ids.data(), sizeof(int32_t) * nid);
+  if (e == hipSuccess) e = upload(p->d_nopts, p->nopts.data(), sizeof(int32_t) * K);
   std::vector<KRec> recs(ik.size());
   for (size_t i = 0; i < ik.size(); ++i) {
     const int k = ik[i];
@@ -459,7 +507,6 @@ int32_t sugg_plan_create(sugg_ctx* ctx, int32_t K, int32_t E, int32_t D, int32_t
   if (e == hipSuccess) e = upload(p->d_recs, recs.data(), sizeof(KRec) * recs.size());
   if (e == hipSuccess) e = upload(p->d_queue, nullptr, 64);
   if (e == hipSuccess) e = hipMemset(p->d_queue, 0, 64);
-  if (e == hipSuccess) e = upload(p->d_stat_partial, nullptr, sizeof(double) * 2 * E * p->stat_chunks);
   if (e != hipSuccess) {
     delete p;
     return ctx->hip(e, "plan upload");
@@ -492,6 +539,7 @@ int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* cou
   if (mode & SUGG_FIT_STATS) {
     if (p->N == 0) return ctx->fail(SUGG_E_SHAPE, "statistics need at least one row");
     rc = ctx->ensure_model(p->E, (ctx->has_model && ctx->E == p->E) ? ctx->D : 0);
+    if (!rc) rc = ensure_stat_ws(ctx, p);
     if (rc) return rc;
     if (p->dtype == SUGG_F32)
       rc = ctx->hip(launch_colstats<float>((const float*)counters, (const float*)cycles, p->N, p->E, p->d_stat_partial,
@@ -579,6 +627,46 @@ int32_t sugg_suggest(sugg_ctx* ctx, const sugg_plan* plan, const void* counters,
                            idx_out, (float*)score_out, count_out, n, stream);
   return run_path<double>(ctx, plan, (const double*)counters, (const double*)cycles, nullptr, (double*)table_out,
                           idx_out, (double*)score_out, count_out, n, stream);
+}
+
+int32_t sugg_suggest_subset(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                            const int32_t* kmask, void* table_out, int32_t* idx_out, void* score_out,
+                            int32_t* count_out, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (plan->K > 0 && (!counters || !cycles || !kmask || !idx_out || !score_out || !count_out))
+    return ctx->fail(SUGG_E_ARG, "null argument");
+  int rc = check_model_for(ctx, plan);
+  if (rc) return rc;
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  const int n = ctx->params.n_suggest;
+  if (plan->dtype == SUGG_F32)
+    return run_path<float>(ctx, plan, (const float*)counters, (const float*)cycles, nullptr, (float*)table_out,
+                           idx_out, (float*)score_out, count_out, n, stream, kmask);
+  return run_path<double>(ctx, plan, (const double*)counters, (const double*)cycles, nullptr, (double*)table_out,
+                          idx_out, (double*)score_out, count_out, n, stream, kmask);
+}
+
+int32_t sugg_judge(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                   const int32_t* cand, int32_t C, void* out, const void* ref, double tol, int32_t* flag_out,
+                   hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (C < 1 || C > 64) return ctx->fail(SUGG_E_ARG, "candidates per kernel must be in [1, 64]");
+  if (plan->K == 0) return SUGG_OK;
+  if (!counters || !cycles || !cand || !out) return ctx->fail(SUGG_E_ARG, "null argument");
+  if ((ref == nullptr) != (flag_out == nullptr) || (flag_out && !(tol >= 0.0)))
+    return ctx->fail(SUGG_E_ARG, "ref and flag_out go together, with tol >= 0");
+  int rc = check_model_for(ctx, plan);
+  if (rc) return rc;
+  if (path_lds_bound(plan->dtype == SUGG_F32 ? 4 : 8, ctx->D, plan->E, 1, 1, 1) > kLdsPerWorkgroup)
+    return ctx->fail(SUGG_E_BUDGET, "model does not fit in LDS");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  if (plan->dtype == SUGG_F32)
+    return run_judge<float>(ctx, plan, (const float*)counters, (const float*)cycles, cand, C, (float*)out,
+                            (const float*)ref, tol, flag_out, stream);
+  return run_judge<double>(ctx, plan, (const double*)counters, (const double*)cycles, cand, C, (double*)out,
+                           (const double*)ref, tol, flag_out, stream);
 }
 
 int32_t sugg_rank_suggest(sugg_ctx* ctx, int32_t dtype, const void* scores, const int64_t* seg_off, int32_t nseg,

@@ -17,9 +17,35 @@ struct alignas(16) KRec {
   uint8_t opt[16];
 };
 
+// Arguments of the judge: plain composed log-speedups of given subsets.
+template <typename T>
+struct JudgeArgs {
+  const T* counters;
+  const T* cycles;
+  int32_t E;
+  int32_t D;
+  const T* W;              // [D, E+1]
+  const T* mu;
+  const T* isg;
+  const int64_t* row_off;  // [K+1]
+  const int32_t* nopts;    // [K]
+  const int64_t* opt_off;  // [K+1]
+  const int32_t* opt_ids;
+  int32_t K;
+  int32_t C;               // candidates per kernel
+  const int32_t* cand;     // [K, C] subset bitmasks, < 0 = none
+  T* out;                  // [K, C]; 0 for S = 0, NaN for none
+  const T* ref;            // [K, C] reference values (with flag)
+  double tol;
+  int32_t* flag;           // [K] or null: 1 where some candidate differs from ref by > tol
+  int32_t* status;
+};
+
 // Arguments of the fused scoring kernel (predict / suggest).
 template <typename T>
 struct PathArgs {
+  const JudgeArgs<T>* judge;   // non-null: run the judge instead (same dispatch)
+  const int32_t* kmask;        // [K] or null: only kernels with kmask != 0 are scored and written
   const T* counters;       // [N, E]
   const T* cycles;         // [N]
   int32_t E;

@@ -25,7 +25,6 @@ namespace sugg {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kTile = 64;     // workgroup output tile (4 waves of 32 x 32)
 constexpr int kKStep = 32;    // K per LDS stage (two MFMAs of K 16)
 constexpr int kLdsRow = kKStep + 8;   // padded LDS row (bf16 elements)
 
@@ -48,78 +47,105 @@ __device__ __forceinline__ bf16x8 load8(const __bf16* p, int ld, int row, int ro
   return v;
 }
 
-template <int EPI>
+// Workgroup of 4 waves in a 2 x 2 arrangement; each wave computes TM x TN
+// MFMA tiles of 32 x 32, so the workgroup tile is (64 TM) x (64 TN).
+template <int EPI, int TM, int TN>
 __global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs g) {
-  __shared__ __align__(16) __bf16 As[2][kTile * kLdsRow];
-  __shared__ __align__(16) __bf16 Bs[2][kTile * kLdsRow];
+  constexpr int WGM = 64 * TM, WGN = 64 * TN;
+  __shared__ __align__(16) __bf16 As[2][WGM * kLdsRow];
+  __shared__ __align__(16) __bf16 Bs[2][WGN * kLdsRow];
   __shared__ float red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+  const int m0 = blockIdx.y * WGM, n0 = blockIdx.x * WGN;
   const int split = blockIdx.z;
   const int kb = split * g.k_per_split;
   const int ke = min(g.K, kb + g.k_per_split);
-  // staging: thread t moves 8 elements of tile row t/4, K offset (t%4)*8
+  // staging: thread t moves 8 elements of tile rows t/4 + 64 i, K offset (t%4)*8
   const int lr = tid >> 2, lk = (tid & 3) * 8;
 
-  floatx16 acc;
+  floatx16 acc[TM][TN];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
-  bf16x8 ra = load8(g.A, g.lda, m0 + lr, g.M, kb + lk, ke);
-  bf16x8 rb = load8(g.Bt, g.ldb, n0 + lr, g.N, kb + lk, ke);
+  bf16x8 ra[TM], rb[TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) ra[i] = load8(g.A, g.lda, m0 + lr + 64 * i, g.M, kb + lk, ke);
+#pragma unroll
+  for (int i = 0; i < TN; ++i) rb[i] = load8(g.Bt, g.ldb, n0 + lr + 64 * i, g.N, kb + lk, ke);
   int buf = 0;
   for (int k0 = kb; k0 < ke; k0 += kKStep) {
-    *reinterpret_cast<bf16x8*>(&As[buf][lr * kLdsRow + lk]) = ra;
-    *reinterpret_cast<bf16x8*>(&Bs[buf][lr * kLdsRow + lk]) = rb;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) *reinterpret_cast<bf16x8*>(&As[buf][(lr + 64 * i) * kLdsRow + lk]) = ra[i];
+#pragma unroll
+    for (int i = 0; i < TN; ++i) *reinterpret_cast<bf16x8*>(&Bs[buf][(lr + 64 * i) * kLdsRow + lk]) = rb[i];
     __syncthreads();
     if (k0 + kKStep < ke) {
-      ra = load8(g.A, g.lda, m0 + lr, g.M, k0 + kKStep + lk, ke);
-      rb = load8(g.Bt, g.ldb, n0 + lr, g.N, k0 + kKStep + lk, ke);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) ra[i] = load8(g.A, g.lda, m0 + lr + 64 * i, g.M, k0 + kKStep + lk, ke);
+#pragma unroll
+      for (int i = 0; i < TN; ++i) rb[i] = load8(g.Bt, g.ldb, n0 + lr + 64 * i, g.N, k0 + kKStep + lk, ke);
     }
 #pragma unroll
     for (int s = 0; s < kKStep; s += 16) {
       const int kk = s + (lane >> 5) * 8;
-      const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&As[buf][(wm * 32 + (lane & 31)) * kLdsRow + kk]);
-      const bf16x8 fb = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn * 32 + (lane & 31)) * kLdsRow + kk]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc, 0, 0, 0);
+      bf16x8 fa[TM], fb[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+        fa[a] = *reinterpret_cast<const bf16x8*>(&As[buf][(wm * 32 * TM + a * 32 + (lane & 31)) * kLdsRow + kk]);
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        fb[b] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn * 32 * TN + b * 32 + (lane & 31)) * kLdsRow + kk]);
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
     buf ^= 1;
   }
 
-  // epilogue: lane holds C[row(r)][col] with col = lane % 32,
-  // row(r) = (r / 4) * 8 + (lane / 32) * 4 + r % 4 inside the wave's 32 x 32 tile
-  const int col = n0 + wn * 32 + (lane & 31);
+  // epilogue: lane holds C[row(r)][col] of each 32 x 32 tile with
+  // col = lane % 32, row(r) = (r / 4) * 8 + (lane / 32) * 4 + r % 4
   float sse = 0.0f;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int row = m0 + wm * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-    if (row >= g.M || col >= g.N) continue;
-    const float v = acc[r];
-    if (EPI == kEpiWgrad) {
-      g.Cf[(int64_t)split * g.M * g.N + (int64_t)row * g.N + col] = v;
-    } else if (EPI == kEpiFwdHidden) {
-      const float a = v + g.bias[col];
-      if (g.Cf) g.Cf[(int64_t)row * g.ldcf + col] = a;
-      const float h = gelu_f(a);
-      if (g.Cb) g.Cb[(int64_t)row * g.ldcb + col] = to_bf16(h);
-      if (g.Ct) g.Ct[(int64_t)col * g.ldct + row] = to_bf16(h);
-    } else if (EPI == kEpiFwdOut) {
-      const float y = v + g.bias[col];
-      if (g.Cf) g.Cf[(int64_t)row * g.ldcf + col] = y;
-      if (g.target) {
-        const float d = y - g.target[(int64_t)row * g.ldt + col];
-        sse = fmaf(d, d, sse);
-        const float dy = g.scale * d;
-        g.Cb[(int64_t)row * g.ldcb + col] = to_bf16(dy);
-        g.Ct[(int64_t)col * g.ldct + row] = to_bf16(dy);
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int col = n0 + wn * 32 * TN + b * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 32 * TM + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        if (row >= g.M || col >= g.N) continue;
+        const float v = acc[a][b][r];
+        if (EPI == kEpiWgrad) {
+          g.Cf[(int64_t)split * g.M * g.N + (int64_t)row * g.N + col] = v;
+        } else if (EPI == kEpiFwdHidden) {
+          const float z = v + g.bias[col];
+          if (g.Cf) g.Cf[(int64_t)row * g.ldcf + col] = z;
+          const float h = gelu_f(z);
+          if (g.Cb) g.Cb[(int64_t)row * g.ldcb + col] = to_bf16(h);
+          if (g.Ct) g.Ct[(int64_t)col * g.ldct + row] = to_bf16(h);
+        } else if (EPI == kEpiFwdOut) {
+          const float y = v + g.bias[col];
+          if (g.Cf) g.Cf[(int64_t)row * g.ldcf + col] = y;
+          if (g.target) {
+            const float d = y - g.target[(int64_t)row * g.ldt + col];
+            sse = fmaf(d, d, sse);
+            const float dy = g.scale * d;
+            g.Cb[(int64_t)row * g.ldcb + col] = to_bf16(dy);
+            g.Ct[(int64_t)col * g.ldct + row] = to_bf16(dy);
+          }
+        } else {  // kEpiBwdHidden
+          const float d = v * gelu_grad_f(g.gact[(int64_t)row * g.ldg + col]);
+          if (g.Cb) g.Cb[(int64_t)row * g.ldcb + col] = to_bf16(d);
+          if (g.Ct) g.Ct[(int64_t)col * g.ldct + row] = to_bf16(d);
+        }
       }
-    } else {  // kEpiBwdHidden
-      const float d = v * gelu_grad_f(g.gact[(int64_t)row * g.ldg + col]);
-      if (g.Cb) g.Cb[(int64_t)row * g.ldcb + col] = to_bf16(d);
-      if (g.Ct) g.Ct[(int64_t)col * g.ldct + row] = to_bf16(d);
     }
-  }
   if (EPI == kEpiFwdOut && g.target) {
     // fixed-order reduction of the tile's squared errors
 #pragma unroll
@@ -130,15 +156,32 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs g) {
   }
 }
 
+template <int EPI, int TM, int TN>
+void launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s) {
+  const dim3 grid((g.N + 64 * TN - 1) / (64 * TN), (g.M + 64 * TM - 1) / (64 * TM), splits);
+  hipLaunchKernelGGL((gemm_nt_kernel<EPI, TM, TN>), grid, dim3(256), 0, s, g);
+}
+
+template <int EPI>
+void launch_gemm_e(const GemmArgs& g, int splits, hipStream_t s) {
+  // largest tile that still gives at least 256 workgroups; the loss partials
+  // of a training forward are laid out per 64 x 64 tile
+  const int64_t t22 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * splits;
+  const int64_t t21 = (int64_t)((g.N + 63) / 64) * ((g.M + 127) / 128) * splits;
+  if (EPI == kEpiFwdOut && g.target) launch_gemm_t<EPI, 1, 1>(g, splits, s);
+  else if (t22 >= 256) launch_gemm_t<EPI, 2, 2>(g, splits, s);
+  else if (t21 >= 256) launch_gemm_t<EPI, 2, 1>(g, splits, s);
+  else launch_gemm_t<EPI, 1, 1>(g, splits, s);
+}
+
 hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  const dim3 grid((g.N + kTile - 1) / kTile, (g.M + kTile - 1) / kTile, splits);
   (void)hipGetLastError();  // report only this launch's status
   switch (epi) {
-    case kEpiWgrad: hipLaunchKernelGGL(gemm_nt_kernel<kEpiWgrad>, grid, dim3(256), 0, s, g); break;
-    case kEpiFwdHidden: hipLaunchKernelGGL(gemm_nt_kernel<kEpiFwdHidden>, grid, dim3(256), 0, s, g); break;
-    case kEpiFwdOut: hipLaunchKernelGGL(gemm_nt_kernel<kEpiFwdOut>, grid, dim3(256), 0, s, g); break;
-    default: hipLaunchKernelGGL(gemm_nt_kernel<kEpiBwdHidden>, grid, dim3(256), 0, s, g); break;
+    case kEpiWgrad: launch_gemm_e<kEpiWgrad>(g, splits, s); break;
+    case kEpiFwdHidden: launch_gemm_e<kEpiFwdHidden>(g, splits, s); break;
+    case kEpiFwdOut: launch_gemm_e<kEpiFwdOut>(g, splits, s); break;
+    default: launch_gemm_e<kEpiBwdHidden>(g, splits, s); break;
   }
   return hipGetLastError();
 }

@@ -50,6 +50,37 @@ template <typename T> __device__ __forceinline__ T feat_log_unit();
 template <> __device__ __forceinline__ float feat_log_unit<float>() { return 0.69314718055994530942f; }
 template <> __device__ __forceinline__ double feat_log_unit<double>() { return 1.0; }
 
+// Row arithmetic shared by every kernel that predicts from a counter row, so
+// that they all produce bit-identical predictions.  A lane holds NCH chunks of
+// VW columns of one row; 16 lanes (a DPP row) hold the whole row.
+template <typename T, int NCH, int VW>
+__device__ __forceinline__ T row_features(const T (&c)[NCH][VW], T cyc, const T (&s)[NCH][VW],
+                                          const T (&m)[NCH][VW], T (&z)[NCH][VW]) {
+  const T lc = feat_log<T>(cyc);
+  T chk = lc;
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      const T x = feat_log<T>(c[ch][v]) - lc;
+      chk += x;
+      z[ch][v] = fma(x, s[ch][v], m[ch][v]);
+    }
+  return chk;   // NaN or infinite when a counter or the cycle count is bad
+}
+
+template <typename T, int NCH, int VW>
+__device__ __forceinline__ T row_dot(const T (&z)[NCH][VW], const T* wrow, int l16) {
+  T part = T(0);
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const VecN<T, VW> w = *reinterpret_cast<const VecN<T, VW>*>(wrow + (l16 + kRowLanes * ch) * VW);
+#pragma unroll
+    for (int v = 0; v < VW; ++v) part = fma(z[ch][v], w.v[v], part);
+  }
+  return row_sum16(part);
+}
+
 // Dynamic LDS layout of the fused kernel (host and device agree on it).
 struct PathSmem {
   int ep;        // padded weight row length
@@ -114,7 +145,7 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
   int32_t* kid = reinterpret_cast<int32_t*>(smem + ly.kid);
   int32_t* kop = reinterpret_cast<int32_t*>(smem + ly.kop);
   Entry<T>* xw = reinterpret_cast<Entry<T>*>(smem + ly.xw);
-  __shared__ int s_next;
+  __shared__ int s_next, s_any;
   const bool dynamic = (int)gridDim.x < a.n_items;
 
   const int EP = ly.ep;
@@ -157,10 +188,13 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
     const int B = item.B, nk = item.nk, R = item.R;
     const uint32_t mask = (1u << B) - 1u;
     const bool contig = item.row0 >= 0;
+    if (tid == 0) s_any = a.kmask ? 0 : 1;
+    __syncthreads();
     for (int i = tid; i < nk; i += nthr) {
       const KRec& rec = a.recs[item.first + i];
       kid[i] = rec.kid;
       kro[i] = rec.row_off;
+      if (a.kmask && a.kmask[rec.kid]) s_any = 1;
     }
     for (int i = tid; i < nk * B; i += nthr) {
       const int kk = i / B, b = i - kk * B;
@@ -205,17 +239,8 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
         if (r0 >= R) break;
         const int r = r0 + grp;
         const bool live = r < R;
-        const T lc = feat_log<T>(cy[u]);
         T z[NCH][VW];
-        T chk = lc;
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-          for (int v = 0; v < VW; ++v) {
-            const T x = feat_log<T>(c[u][ch][v]) - lc;
-            chk += x;
-            z[ch][v] = fma(x, s_r[ch][v], m_r[ch][v]);
-          }
+        const T chk = row_features<T, NCH, VW>(c[u], cy[u], s_r, m_r, z);
         // a non-positive, non-normal or non-finite counter or cycle count
         // makes the checksum NaN or infinite
         bad |= live && !__builtin_isfinite(chk);
@@ -226,15 +251,7 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
         const int ms = msb(S);
         for (int h = hlo; h < B; ++h) {
           const int o = kop[kk * B + h];
-          const T* wrow = Wl + o * EP;
-          T part = T(0);
-#pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) {
-            const VecN<T, VW> w = *reinterpret_cast<const VecN<T, VW>*>(wrow + (l16 + kRowLanes * ch) * VW);
-#pragma unroll
-            for (int v = 0; v < VW; ++v) part = fma(z[ch][v], w.v[v], part);
-          }
-          const T p = row_sum16(part) + Wb[o];
+          const T p = row_dot<T, NCH, VW>(z, Wl + o * EP, l16) + Wb[o];
           if (l16 == 0 && live) {
             if (GRID) a.grid[row_addr(r) * a.grid_ld + h] = ((S >> h) & 1u) ? qnan<T>() : p;
             if (h > ms) eb[r | (1 << h)] = p;
@@ -252,8 +269,14 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
     const int b0 = wave * 4 * U;
     T ca[U][NCH][VW], cb[U][NCH][VW];
     T cya[U], cyb[U];
-    if (contig && b0 < R) load(b0, ca, cya);   // needs no metadata: before the barrier
+    if (contig && b0 < R && !a.kmask) load(b0, ca, cya);   // needs no metadata: before the barrier
     __syncthreads();
+    if (!s_any) {   // masked run: no selected kernel in this item
+      it = dynamic ? s_next : a.n_items;
+      __syncthreads();
+      continue;
+    }
+    if (contig && b0 < R && a.kmask) load(b0, ca, cya);
     if (!contig && b0 < R) load(b0, ca, cya);
     for (int base = b0; base < R; base += 2 * step) {
       if (base + step < R) load(base + step, cb, cyb);
@@ -272,7 +295,7 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
       for (int b = 0; b < B; ++b)
         if ((S >> b) & 1u) L += eb[kb | (int)(S & ((2u << b) - 1u))];
       Lb[r] = L;
-      if (a.table) a.table[(contig ? item.row0 + r : kro[r >> B] + S)] = L;
+      if (a.table && (!a.kmask || a.kmask[kid[r >> B]])) a.table[(contig ? item.row0 + r : kro[r >> B] + S)] = L;
     }
     __syncthreads();
 
@@ -291,7 +314,7 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
             if (S != 0 && v > a.tau) { lst[0].v = v; lst[0].s = S; }
           }
           group_merge<T, KT>(lst, G);
-          if (r < R && (r & (int)mask) == 0)
+          if (r < R && (r & (int)mask) == 0 && (!a.kmask || a.kmask[kid[r >> B]]))
             write_list<T, KT>(lst, kid[r >> B], a.n, a.idx_out, a.score_out, a.count_out);
         }
       } else {
@@ -320,7 +343,7 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
               for (int i = 0; i < KT; ++i) o[i] = xw[w * KT + i];
               list_merge<T, KT>(lst, o);
             }
-            write_list<T, KT>(lst, kid[kk], a.n, a.idx_out, a.score_out, a.count_out);
+            if (!a.kmask || a.kmask[kid[kk]]) write_list<T, KT>(lst, kid[kk], a.n, a.idx_out, a.score_out, a.count_out);
           }
           __syncthreads();
         }
@@ -385,10 +408,114 @@ hipError_t dispatch_g(const PathArgs<T>& a, int mr, int mk, int mb, const PathLa
   return dispatch_u<T, VPL, VW, KT, FULL, false>(a, mr, mk, mb, c, s);
 }
 
+// Judge: the plain composed log-speedup of given subsets only.  One wave per
+// (kernel, candidate); the chain terms (one per bit b of S, from version
+// S & (2^b - 1)) are spread over the four 16-lane groups and summed in
+// ascending b, with the fused kernel's row arithmetic, so the value equals the
+// fused kernel's table entry bit for bit.
+template <typename T, int VPL, int VW>
+__global__ void __launch_bounds__(256) judge_kernel(const JudgeArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NCH = VPL / VW;
+  const int E = a.E, D = a.D, EP = kRowLanes * VPL;
+  const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, grp = lane >> 4;
+  T* Wl = reinterpret_cast<T*>(smem);
+  T* Wb = Wl + D * EP;
+  for (int i = tid; i < D * EP; i += blockDim.x) {
+    const int o = i / EP, j = i - o * EP;
+    Wl[i] = j < E ? a.W[(int64_t)o * (E + 1) + j] : T(0);
+  }
+  for (int o = tid; o < D; o += blockDim.x) Wb[o] = a.W[(int64_t)o * (E + 1) + E];
+  T s_r[NCH][VW], m_r[NCH][VW];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      const int col = (l16 + kRowLanes * ch) * VW + v;
+      const bool ok = col < E;
+      const T isg = ok ? a.isg[col] : T(0);
+      s_r[ch][v] = isg * feat_log_unit<T>();
+      m_r[ch][v] = ok ? -a.mu[col] * isg : T(0);
+    }
+  __syncthreads();   // the only barrier: waves below work independently
+  const int64_t job = (int64_t)blockIdx.x * 4 + (tid >> 6);
+  if (job >= (int64_t)a.K * a.C) return;
+  const int k = (int)(job / a.C);
+  const int32_t S = a.cand[job];
+  const int B = a.nopts[k];
+  if (S <= 0 || S >= (1 << B)) {
+    if (lane == 0) a.out[job] = S == 0 ? T(0) : qnan<T>();
+    return;   // no candidate: nothing to disagree with
+  }
+  const int nt = __popc((uint32_t)S);
+  const int64_t r0 = a.row_off[k];
+  bool bad = false;
+  T L = T(0);   // meaningful in lane 0
+  for (int t0 = 0; t0 < nt; t0 += 4) {   // uniform per wave
+    const int t = t0 + grp;
+    uint32_t rest = (uint32_t)S;          // drop the t lowest set bits
+    for (int i = 0; i < t && rest; ++i) rest &= rest - 1;
+    const int b = t < nt ? __ffs(rest) - 1 : 0;
+    const uint32_t Sp = t < nt ? ((uint32_t)S & ((1u << b) - 1u)) : 0u;
+    const T* rp = a.counters + (r0 + Sp) * E;
+    T c[NCH][VW];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int cc = (l16 + kRowLanes * ch) * VW;
+      if (cc < E) {
+        const VecN<T, VW> q = *reinterpret_cast<const VecN<T, VW>*>(rp + cc);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) c[ch][v] = q.v[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < VW; ++v) c[ch][v] = T(1);
+      }
+    }
+    T z[NCH][VW];
+    const T chk = row_features<T, NCH, VW>(c, a.cycles[r0 + Sp], s_r, m_r, z);
+    bad |= t < nt && !__builtin_isfinite(chk);
+    const int o = a.opt_ids[a.opt_off[k] + b];
+    const T p = row_dot<T, NCH, VW>(z, Wl + o * EP, l16) + Wb[o];
+    // terms t0 .. t0+3 sit in lanes 0, 16, 32, 48: add them in ascending order
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const T pg = __shfl(p, g * 16, kWave);
+      if (t0 + g < nt) L += pg;
+    }
+  }
+  if (lane == 0) {
+    a.out[job] = L;
+    // fallback test: the reference (surrogate) value of this subset differs
+    // from the plain value by more than tol
+    if (a.flag && !(fabs((double)a.ref[job] - (double)L) <= a.tol)) atomicOr(a.flag + k, 1);
+  }
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(a.status, (int)kStatusBadCounter);
+}
+
+template <typename T, int VPL>
+hipError_t launch_judge_vpl(const JudgeArgs<T>& a, hipStream_t s) {
+  constexpr int VEC = 16 / sizeof(T);
+  const int64_t jobs = (int64_t)a.K * a.C;
+  if (jobs <= 0) return hipSuccess;
+  const size_t smem = sizeof(T) * ((size_t)a.D * kRowLanes * VPL + a.D);
+  const dim3 grid((unsigned)((jobs + 3) / 4));
+  if (a.flag) {
+    const hipError_t e = launch_fill_i32(a.flag, 0, a.K, s);
+    if (e != hipSuccess) return e;
+  }
+  (void)hipGetLastError();  // report only this launch's status
+  if ((a.E % VEC) == 0 && (reinterpret_cast<uintptr_t>(a.counters) % 16) == 0)
+    hipLaunchKernelGGL((judge_kernel<T, VPL, VEC>), grid, dim3(256), smem, s, a);
+  else
+    hipLaunchKernelGGL((judge_kernel<T, VPL, 1>), grid, dim3(256), smem, s, a);
+  return hipGetLastError();
+}
+
 // All launch variants for one column count per lane (one translation unit
 // each, so the variants compile in parallel).
 template <typename T, int VPL>
 hipError_t launch_path_vpl(const PathArgs<T>& a, int mr, int mk, int mb, const PathLaunch& c, hipStream_t s) {
+  if (a.judge) return launch_judge_vpl<T, VPL>(*a.judge, s);
   constexpr int VEC = 16 / sizeof(T);
   const bool vec_ok = (a.E % VEC) == 0 && (reinterpret_cast<uintptr_t>(a.counters) % 16) == 0;
   if (a.n <= 4) {

@@ -179,6 +179,35 @@ def suggest(ctx: Context, plan: Plan, counters, cycles, table: bool = True, out=
     return out["idx"], out["score"], out["count"], out["table"]
 
 
+def suggest_subset(ctx: Context, plan: Plan, counters, cycles, kmask, out):
+    """Re-score only the kernels with kmask[k] != 0 (int32 [K] device tensor),
+    writing their entries of ``out`` (as returned by ``suggest``)."""
+    plan.check_inputs(counters, cycles)
+    if kmask.dtype != torch.int32 or kmask.numel() != plan.K or kmask.device != ctx.device:
+        raise ValueError("kmask must be an int32 tensor of K entries on the context device")
+    A.check(ctx.h, A.lib().sugg_suggest_subset(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(kmask),
+                                               _ptr(out["table"]), _ptr(out["idx"]), _ptr(out["score"]),
+                                               _ptr(out["count"]), _stream()))
+    return out
+
+
+def judge(ctx: Context, plan: Plan, counters, cycles, cand, out=None, ref=None, tol: float = 0.1, flag=None):
+    """Plain composed log-speedups of candidate subsets cand [K, C] (int32,
+    < 0 = none), reading only each subset's chain of versions.  With ref
+    (values to check, [K, C]) and flag (int32 [K]): flag[k] = 1 where some
+    candidate differs from ref by more than tol."""
+    plan.check_inputs(counters, cycles)
+    if cand.dtype != torch.int32 or cand.dim() != 2 or cand.shape[0] != plan.K or not cand.is_contiguous():
+        raise ValueError("cand must be a contiguous int32 [K, C] tensor")
+    if out is None:
+        out = torch.empty(tuple(cand.shape), dtype=plan.dtype, device=ctx.device)
+    if (ref is None) != (flag is None):
+        raise ValueError("ref and flag go together")
+    A.check(ctx.h, A.lib().sugg_judge(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(cand), cand.shape[1],
+                                      _ptr(out), _ptr(ref), float(tol), _ptr(flag), _stream()))
+    return out
+
+
 def rank_suggest(ctx: Context, scores, seg_off, n: int = 3, tau: float = TAU, skip_head: int = 0):
     """Tier 3 over segments scores[seg_off[i]:seg_off[i+1]]; returns (idx, score, count)."""
     if scores.dtype not in _DT or not scores.is_contiguous() or scores.device != ctx.device:

@@ -6,7 +6,8 @@ World parameters (mu, bias, w, gamma, delta) are the NumPy world's
 generator on the device seeded per chunk, so a chunk is reproducible on one
 device but is a different draw than ``make_batch`` of the same ids.  Every
 kernel has all D optimisations (B = D), as in the 6-optimisation lattices of
-Section 3.3.  Input generation only: no part of the suggestion method.
+Section 3.3 (or the first B of them).  Input generation only: no part of the
+suggestion method.
 """
 from __future__ import annotations
 
@@ -22,25 +23,30 @@ def _chunk_seed(seed: int, chunk: int) -> int:
 
 
 class TorchWorld:
-    def __init__(self, seed: int, E: int, D: int, device="cuda"):
+    def __init__(self, seed: int, E: int, D: int, device="cuda", B: int | None = None):
         wd = world_for(seed, E, D)
-        self.seed, self.E, self.D, self.B = seed, E, D, D
+        B = D if B is None else int(B)
+        if not 0 <= B <= D:
+            raise ValueError("B must be in [0, D]")
+        self.seed, self.E, self.D, self.B = seed, E, D, B
         f = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device)  # noqa: E731
-        self.mu, self.bias, self.w, self.gamma, self.delta = f(wd.mu), f(wd.bias), f(wd.w), f(wd.gamma), f(wd.delta)
-        n = 1 << D
+        # kernels carry the first B of the D global optimisations
+        self.mu, self.bias, self.w = f(wd.mu), f(wd.bias[:B]), f(wd.w[:B])
+        self.gamma, self.delta = f(wd.gamma[:B, :B]), f(wd.delta[:B])
+        n = 1 << B
         S = torch.arange(n, device=device)
-        self.bits = ((S[:, None] >> torch.arange(D, device=device)) & 1).to(torch.float64)   # [n, D]
+        self.bits = ((S[:, None] >> torch.arange(B, device=device)) & 1).to(torch.float64)   # [n, B]
         self.pair = 0.5 * ((self.bits @ self.gamma) * self.bits).sum(1)                    # [n]
         self.shift = self.bits @ self.delta                                                # [n, E]
         self.device = device
 
     def chunk(self, chunk: int, K: int, dtype=torch.float32):
-        """Kernels of chunk ``chunk``: counters [K*2^D, E], cycles [K*2^D] and
-        the true log-speedups [K, 2^D] (rows kernel after kernel, version S at
+        """Kernels of chunk ``chunk``: counters [K*2^B, E], cycles [K*2^B] and
+        the true log-speedups [K, 2^B] (rows kernel after kernel, version S at
         kernel offset S)."""
         g = torch.Generator(device=self.device)
-        g.manual_seed(_chunk_seed(self.seed, chunk))
-        E, n = self.E, 1 << self.D
+        g.manual_seed(_chunk_seed(self.seed * 64 + self.B, chunk))
+        E, n = self.E, 1 << self.B
         a = torch.randn((K, E + 1), generator=g, device=self.device, dtype=torch.float64)
         lc0 = self.mu + COUNTER_SIGMA * a
         u = (a[:, :E] - a[:, E:]) / math.sqrt(2.0)
