@@ -45,6 +45,26 @@ def path_bytes(N, E, K, n, table=True, tsize=4):
     return N * (E + 1) * tsize + (N * tsize if table else 0) + K * n * (4 + tsize) + K * 4
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1910_07776_amd", "csrc", "path_impl.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "path_kernel_512x64x128_traffic.txt")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the scoring kernel from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE (scaled by a 1 GiB copy's readings), recorded in profiles/ with
+    the kernel source's hash; None if the kernel changed since."""
+    import hashlib
+    try:
+        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != cur:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(model_o, batch, budget_s=12.0):
     from threadpoolctl import threadpool_info
     from oracle import plain as P
@@ -171,7 +191,7 @@ def main():
                    "autotuned": {"waves": tune["waves"], "unroll": tune["unroll"]}},
         "suggestions_per_s": sugg_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "path_kernel", "bytes_per_launch": by},
         "fit_ms": fit_ms,
     }

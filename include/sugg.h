@@ -182,10 +182,26 @@ SUGG_API int32_t sugg_suggest_subset(sugg_ctx* ctx, const sugg_plan* plan, const
  * With ref [K x C] (e.g. a learned surrogate's values of the same subsets)
  * and flag_out [K] (both device, or both null): flag_out[k] = 1 when some
  * candidate S >= 1 of kernel k has |ref - out| > tol (or a non-finite
- * difference), else 0. */
+ * difference), else 0; with accumulate != 0 a flag already set stays set
+ * (flag_out is not cleared first), so several calls can judge one kernel. */
 SUGG_API int32_t sugg_judge(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
                             const int32_t* cand, int32_t C, void* out, const void* ref, double tol,
-                            int32_t* flag_out, hipStream_t stream);
+                            int32_t* flag_out, int32_t accumulate, hipStream_t stream);
+
+/* Threshold band of short suggestion lists, for judging a learned
+ * surrogate's decisions at the Tier 3 threshold (Section 2: candidates are
+ * kept only above a preset threshold).  Per segment i (scores[seg_off[i] ..
+ * seg_off[i+1]), entries below skip_head excluded) whose list from
+ * sugg_rank_suggest (top_idx [nseg x n], top_count [nseg]) holds fewer than n
+ * entries: the other entries p with scores[p] >= tau - band (compared in
+ * FP64), ascending, into cand_out [nseg x C] (int32, -1 padding) with their
+ * scores in ref_out [nseg x C] (dtype, NaN padding); flag_out[i] = 1 when
+ * more than C qualified, else 0.  A full list (n entries) has an empty band.
+ * All pointers device; 1 <= n <= SUGG_MAX_SUGGEST, 1 <= C <= 64, band >= 0. */
+SUGG_API int32_t sugg_band_select(sugg_ctx* ctx, int32_t dtype, const void* scores, const int64_t* seg_off,
+                                  int32_t nseg, int32_t skip_head, const int32_t* top_idx,
+                                  const int32_t* top_count, int32_t n, double tau, double band, int32_t C,
+                                  int32_t* cand_out, void* ref_out, int32_t* flag_out, hipStream_t stream);
 
 /* Waits for the stream, then returns and clears the device status word:
  * SUGG_E_BAD_COUNTER or SUGG_E_SINGULAR if a kernel flagged one since the

@@ -63,7 +63,9 @@ SIGNATURES = {
     "sugg_suggest": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "sugg_sync": (_I32, [_P, _P]),
     "sugg_suggest_subset": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
-    "sugg_judge": (_I32, [_P, _P, _P, _P, _P, _I32, _P, _P, C.c_double, _P, _P]),
+    "sugg_judge": (_I32, [_P, _P, _P, _P, _P, _I32, _P, _P, C.c_double, _P, _I32, _P]),
+    "sugg_band_select": (_I32, [_P, _I32, _P, _P, _I32, _I32, _P, _P, _I32, C.c_double, C.c_double, _I32, _P,
+                                _P, _P, _P]),
     "sugg_capture_begin": (_I32, [_P, _P]),
     "sugg_capture_end": (_I32, [_P, _P, C.POINTER(_P)]),
     "sugg_graph_launch": (_I32, [_P, _P, _P]),

@@ -343,7 +343,7 @@ namespace {
 
 template <typename T>
 int run_judge(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, const int32_t* cand, int32_t C,
-                     T* out, const T* ref, double tol, int32_t* flag, hipStream_t s) {
+                     T* out, const T* ref, double tol, int32_t* flag, int32_t accumulate, hipStream_t s) {
   JudgeArgs<T> j;
   j.counters = c;
   j.cycles = cyc;
@@ -363,6 +363,7 @@ int run_judge(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, const
   j.ref = ref;
   j.tol = tol;
   j.flag = flag;
+  j.accumulate = accumulate;
   j.status = ctx->d_status;
   PathArgs<T> a{};
   a.judge = &j;
@@ -649,7 +650,7 @@ int32_t sugg_suggest_subset(sugg_ctx* ctx, const sugg_plan* plan, const void* co
 
 int32_t sugg_judge(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
                    const int32_t* cand, int32_t C, void* out, const void* ref, double tol, int32_t* flag_out,
-                   hipStream_t stream) {
+                   int32_t accumulate, hipStream_t stream) {
   if (!ctx) return SUGG_E_ARG;
   if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
   if (C < 1 || C > 64) return ctx->fail(SUGG_E_ARG, "candidates per kernel must be in [1, 64]");
@@ -664,9 +665,9 @@ int32_t sugg_judge(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, c
   if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
   if (plan->dtype == SUGG_F32)
     return run_judge<float>(ctx, plan, (const float*)counters, (const float*)cycles, cand, C, (float*)out,
-                            (const float*)ref, tol, flag_out, stream);
+                            (const float*)ref, tol, flag_out, accumulate, stream);
   return run_judge<double>(ctx, plan, (const double*)counters, (const double*)cycles, cand, C, (double*)out,
-                           (const double*)ref, tol, flag_out, stream);
+                           (const double*)ref, tol, flag_out, accumulate, stream);
 }
 
 int32_t sugg_rank_suggest(sugg_ctx* ctx, int32_t dtype, const void* scores, const int64_t* seg_off, int32_t nseg,
@@ -685,6 +686,29 @@ int32_t sugg_rank_suggest(sugg_ctx* ctx, int32_t dtype, const void* scores, cons
                                        (float*)score_out, count_out, stream), "rank");
   return ctx->hip(launch_rank<double>((const double*)scores, seg_off, nseg, skip_head, n, tau, idx_out,
                                       (double*)score_out, count_out, stream), "rank");
+}
+
+int32_t sugg_band_select(sugg_ctx* ctx, int32_t dtype, const void* scores, const int64_t* seg_off, int32_t nseg,
+                         int32_t skip_head, const int32_t* top_idx, const int32_t* top_count, int32_t n,
+                         double tau, double band, int32_t C, int32_t* cand_out, void* ref_out, int32_t* flag_out,
+                         hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (dtype != SUGG_F32 && dtype != SUGG_F64) return ctx->fail(SUGG_E_ARG, "bad dtype %d", dtype);
+  if (nseg < 0 || skip_head < 0) return ctx->fail(SUGG_E_ARG, "negative nseg or skip_head");
+  if (n < 1 || n > SUGG_MAX_SUGGEST) return ctx->fail(SUGG_E_ARG, "n must be in [1, %d]", SUGG_MAX_SUGGEST);
+  if (C < 1 || C > 64) return ctx->fail(SUGG_E_ARG, "band capacity must be in [1, 64]");
+  if (!std::isfinite(tau) || !(band >= 0.0) || !std::isfinite(band))
+    return ctx->fail(SUGG_E_ARG, "tau must be finite and band finite and >= 0");
+  if (nseg == 0) return SUGG_OK;
+  if (!scores || !seg_off || !top_idx || !top_count || !cand_out || !ref_out || !flag_out)
+    return ctx->fail(SUGG_E_ARG, "null argument");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  const double lo = tau - band;
+  if (dtype == SUGG_F32)
+    return ctx->hip(launch_band<float>((const float*)scores, seg_off, nseg, skip_head, top_idx, top_count, n, lo, C,
+                                       cand_out, (float*)ref_out, flag_out, stream), "band");
+  return ctx->hip(launch_band<double>((const double*)scores, seg_off, nseg, skip_head, top_idx, top_count, n, lo, C,
+                                      cand_out, (double*)ref_out, flag_out, stream), "band");
 }
 
 int32_t sugg_sync(sugg_ctx* ctx, hipStream_t stream) {

@@ -10,6 +10,7 @@
 namespace sugg {
 
 constexpr int kWave = 64;
+constexpr int kMaxSuggest = 8;   // longest suggestion list
 constexpr int kRowLanes = 16;   // lanes that share one counter row (one DPP row)
 
 enum StatusBits : int { kStatusBadCounter = 1, kStatusSingular = 2 };

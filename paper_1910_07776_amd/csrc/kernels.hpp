@@ -38,6 +38,7 @@ struct JudgeArgs {
   const T* ref;            // [K, C] reference values (with flag)
   double tol;
   int32_t* flag;           // [K] or null: 1 where some candidate differs from ref by > tol
+  int32_t accumulate;      // nonzero: keep flags already set (no clearing)
   int32_t* status;
 };
 
@@ -91,6 +92,13 @@ template <typename T>
 hipError_t launch_rank(const T* scores, const int64_t* seg_off, int32_t nseg, int32_t skip_head,
                        int32_t n, T tau, int32_t* idx_out, T* score_out, int32_t* count_out,
                        hipStream_t s);
+
+// Threshold band of short suggestion lists (entries outside the list with
+// score >= lo, ascending, at most C per segment; flag 1 on overflow).
+template <typename T>
+hipError_t launch_band(const T* scores, const int64_t* seg_off, int32_t nseg, int32_t skip_head,
+                       const int32_t* top_idx, const int32_t* top_count, int32_t n, double lo, int32_t C,
+                       int32_t* cand_out, T* ref_out, int32_t* flag_out, hipStream_t s);
 
 // FP64 column statistics of x = ln(c / cyc) over all N rows.
 template <typename T>

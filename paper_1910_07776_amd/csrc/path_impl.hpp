@@ -149,25 +149,31 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
   const bool dynamic = (int)gridDim.x < a.n_items;
 
   const int EP = ly.ep;
-  for (int i = tid; i < D * EP; i += nthr) {
-    const int o = i / EP, j = i - o * EP;
-    Wl[i] = (FULL || j < E) ? a.W[(int64_t)o * (E + 1) + j] : T(0);
-  }
-  for (int o = tid; o < D; o += nthr) Wb[o] = a.W[(int64_t)o * (E + 1) + E];
-
   // this lane's columns: chunk ch covers columns (l16 + 16 ch) * VW + [0, VW);
   // z = fma(log(c) - log(cyc), s, m) with s = unit / sigma, m = -mu / sigma
   T s_r[NCH][VW], m_r[NCH][VW];
-#pragma unroll
-  for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-    for (int v = 0; v < VW; ++v) {
-      const int col = (l16 + kRowLanes * ch) * VW + v;
-      const bool ok = FULL || col < E;
-      const T isg = ok ? a.isg[col] : T(0);
-      s_r[ch][v] = isg * feat_log_unit<T>();
-      m_r[ch][v] = ok ? -a.mu[col] * isg : T(0);
+  // weights, intercepts and column constants are staged after the first
+  // item's row loads are in flight (so the two memory latencies overlap)
+  auto stage_model = [&]() {
+    for (int i = tid; i < D * EP; i += nthr) {
+      const int o = i / EP, j = i - o * EP;
+      Wl[i] = (FULL || j < E) ? a.W[(int64_t)o * (E + 1) + j] : T(0);
     }
+    for (int o = tid; o < D; o += nthr) Wb[o] = a.W[(int64_t)o * (E + 1) + E];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        const int col = (l16 + kRowLanes * ch) * VW + v;
+        const bool ok = FULL || col < E;
+        const T isg = ok ? a.isg[col] : T(0);
+        s_r[ch][v] = isg * feat_log_unit<T>();
+        m_r[ch][v] = ok ? -a.mu[col] * isg : T(0);
+      }
+  };
+  bool staged = false;
+  T ca[U][NCH][VW], cb[U][NCH][VW];
+  T cya[U], cyb[U];
   bool bad = false;
 
   int it = blockIdx.x;
@@ -188,20 +194,6 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
     const int B = item.B, nk = item.nk, R = item.R;
     const uint32_t mask = (1u << B) - 1u;
     const bool contig = item.row0 >= 0;
-    if (tid == 0) s_any = a.kmask ? 0 : 1;
-    __syncthreads();
-    for (int i = tid; i < nk; i += nthr) {
-      const KRec& rec = a.recs[item.first + i];
-      kid[i] = rec.kid;
-      kro[i] = rec.row_off;
-      if (a.kmask && a.kmask[rec.kid]) s_any = 1;
-    }
-    for (int i = tid; i < nk * B; i += nthr) {
-      const int kk = i / B, b = i - kk * B;
-      kop[i] = a.recs[item.first + kk].opt[b];
-    }
-
-    // ---- rows: Tier 1 features and Tier 2 predictions ----------------------
     // Rows past the item are clamped to its last row (read, never written).
     auto row_addr = [&](int r) -> int64_t {
       r = r < R ? r : R - 1;
@@ -232,6 +224,29 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
         cy[u] = contig ? icyc[rr] : a.cycles[grow];
       }
     };
+    const int step = nwaves * 4 * U;
+    const int b0 = wave * 4 * U;
+    // adjacent kernels need no metadata for their first rows: issue them now
+    const bool early = contig && b0 < R && !a.kmask;
+    if (early) load(b0, ca, cya);
+    if (!staged) {
+      stage_model();
+      staged = true;
+    }
+    if (tid == 0) s_any = a.kmask ? 0 : 1;
+    __syncthreads();
+    for (int i = tid; i < nk; i += nthr) {
+      const KRec& rec = a.recs[item.first + i];
+      kid[i] = rec.kid;
+      kro[i] = rec.row_off;
+      if (a.kmask && a.kmask[rec.kid]) s_any = 1;
+    }
+    for (int i = tid; i < nk * B; i += nthr) {
+      const int kk = i / B, b = i - kk * B;
+      kop[i] = a.recs[item.first + kk].opt[b];
+    }
+
+    // ---- rows: Tier 1 features and Tier 2 predictions ----------------------
     auto compute = [&](int base, const T (&c)[U][NCH][VW], const T (&cy)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -265,19 +280,13 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
     };
 
     // two register buffers: the next rows load while the current ones compute
-    const int step = nwaves * 4 * U;
-    const int b0 = wave * 4 * U;
-    T ca[U][NCH][VW], cb[U][NCH][VW];
-    T cya[U], cyb[U];
-    if (contig && b0 < R && !a.kmask) load(b0, ca, cya);   // needs no metadata: before the barrier
     __syncthreads();
     if (!s_any) {   // masked run: no selected kernel in this item
       it = dynamic ? s_next : a.n_items;
       __syncthreads();
       continue;
     }
-    if (contig && b0 < R && a.kmask) load(b0, ca, cya);
-    if (!contig && b0 < R) load(b0, ca, cya);
+    if (!early && b0 < R) load(b0, ca, cya);
     for (int base = b0; base < R; base += 2 * step) {
       if (base + step < R) load(base + step, cb, cyb);
       compute(base, ca, cya);
@@ -499,7 +508,7 @@ hipError_t launch_judge_vpl(const JudgeArgs<T>& a, hipStream_t s) {
   if (jobs <= 0) return hipSuccess;
   const size_t smem = sizeof(T) * ((size_t)a.D * kRowLanes * VPL + a.D);
   const dim3 grid((unsigned)((jobs + 3) / 4));
-  if (a.flag) {
+  if (a.flag && !a.accumulate) {
     const hipError_t e = launch_fill_i32(a.flag, 0, a.K, s);
     if (e != hipSuccess) return e;
   }

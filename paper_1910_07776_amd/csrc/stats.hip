@@ -273,6 +273,66 @@ hipError_t launch_rank(const T* scores, const int64_t* seg_off, int32_t nseg, in
   return hipGetLastError();
 }
 
+// Threshold band of a short suggestion list: for each segment whose top list
+// (top_idx / top_count, as written by rank_kernel) holds fewer than n
+// entries, the other entries p >= skip with score >= lo (compared in FP64),
+// in ascending p, at most C of them; flag_out = 1 when there were more.  A
+// full list has an empty band.  One wave per segment; the wave's ballot and
+// prefix count place each taken entry, so the order is ascending.
+template <typename T>
+__global__ void __launch_bounds__(256) band_kernel(const T* __restrict__ scores,
+                                                   const int64_t* __restrict__ seg_off, int nseg, int skip,
+                                                   const int32_t* __restrict__ top_idx,
+                                                   const int32_t* __restrict__ top_count, int n, double lo, int C,
+                                                   int32_t* cand_out, T* ref_out, int32_t* flag_out) {
+  const int lane = threadIdx.x & 63;
+  const int seg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (seg >= nseg) return;
+  int32_t listed[kMaxSuggest];
+  const int cnt = top_count[seg];
+#pragma unroll
+  for (int i = 0; i < kMaxSuggest; ++i) listed[i] = i < cnt && i < n ? top_idx[(int64_t)seg * n + i] : -1;
+  int64_t total = 0;
+  if (cnt < n) {
+    const int64_t b0 = seg_off[seg], len = seg_off[seg + 1] - b0;
+    for (int64_t base = skip; base < len; base += kWave) {   // uniform per wave
+      const int64_t p = base + lane;
+      bool take = false;
+      T v = T(0);
+      if (p < len) {
+        v = scores[b0 + p];
+        take = (double)v >= lo;
+#pragma unroll
+        for (int i = 0; i < kMaxSuggest; ++i) take = take && listed[i] != (int32_t)p;
+      }
+      const uint64_t m = __ballot(take);
+      const int64_t pos = total + __popcll(m & ((1ull << lane) - 1ull));
+      if (take && pos < C) {
+        cand_out[(int64_t)seg * C + pos] = (int32_t)p;
+        ref_out[(int64_t)seg * C + pos] = v;
+      }
+      total += __popcll(m);
+    }
+  }
+  for (int64_t j = (total < C ? total : C) + lane; j < C; j += kWave) {
+    cand_out[(int64_t)seg * C + j] = -1;
+    ref_out[(int64_t)seg * C + j] = qnan<T>();
+  }
+  if (lane == 0) flag_out[seg] = total > C ? 1 : 0;
+}
+
+template <typename T>
+hipError_t launch_band(const T* scores, const int64_t* seg_off, int32_t nseg, int32_t skip_head,
+                       const int32_t* top_idx, const int32_t* top_count, int32_t n, double lo, int32_t C,
+                       int32_t* cand_out, T* ref_out, int32_t* flag_out, hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  const int blocks = (nseg + 3) / 4;
+  (void)hipGetLastError();  // report only this launch's status
+  hipLaunchKernelGGL((band_kernel<T>), dim3(blocks), dim3(256), 0, s, scores, seg_off, nseg, skip_head, top_idx,
+                     top_count, n, lo, C, cand_out, ref_out, flag_out);
+  return hipGetLastError();
+}
+
 #define SUGG_INST(T)                                                                                     \
   template hipError_t launch_colstats<T>(const T*, const T*, int64_t, int32_t, double*, int32_t, double*, \
                                          double*, T*, T*, int32_t*, hipStream_t);                         \
@@ -283,7 +343,10 @@ hipError_t launch_rank(const T* scores, const int64_t* seg_off, int32_t nseg, in
   template hipError_t launch_zfeat64<T>(const T*, const T*, int64_t, int32_t, const double*,              \
                                         const double*, double*, double*, hipStream_t);                    \
   template hipError_t launch_rank<T>(const T*, const int64_t*, int32_t, int32_t, int32_t, T, int32_t*, T*, \
-                                     int32_t*, hipStream_t);
+                                     int32_t*, hipStream_t);                                              \
+  template hipError_t launch_band<T>(const T*, const int64_t*, int32_t, int32_t, const int32_t*,         \
+                                     const int32_t*, int32_t, double, int32_t, int32_t*, T*, int32_t*,    \
+                                     hipStream_t);
 SUGG_INST(float)
 SUGG_INST(double)
 #undef SUGG_INST

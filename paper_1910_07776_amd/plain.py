@@ -191,11 +191,13 @@ def suggest_subset(ctx: Context, plan: Plan, counters, cycles, kmask, out):
     return out
 
 
-def judge(ctx: Context, plan: Plan, counters, cycles, cand, out=None, ref=None, tol: float = 0.1, flag=None):
+def judge(ctx: Context, plan: Plan, counters, cycles, cand, out=None, ref=None, tol: float = 0.1, flag=None,
+          accumulate: bool = False):
     """Plain composed log-speedups of candidate subsets cand [K, C] (int32,
     < 0 = none), reading only each subset's chain of versions.  With ref
     (values to check, [K, C]) and flag (int32 [K]): flag[k] = 1 where some
-    candidate differs from ref by more than tol."""
+    candidate differs from ref by more than tol (``accumulate``: flags
+    already set stay set)."""
     plan.check_inputs(counters, cycles)
     if cand.dtype != torch.int32 or cand.dim() != 2 or cand.shape[0] != plan.K or not cand.is_contiguous():
         raise ValueError("cand must be a contiguous int32 [K, C] tensor")
@@ -204,24 +206,57 @@ def judge(ctx: Context, plan: Plan, counters, cycles, cand, out=None, ref=None, 
     if (ref is None) != (flag is None):
         raise ValueError("ref and flag go together")
     A.check(ctx.h, A.lib().sugg_judge(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(cand), cand.shape[1],
-                                      _ptr(out), _ptr(ref), float(tol), _ptr(flag), _stream()))
+                                      _ptr(out), _ptr(ref), float(tol), _ptr(flag), int(bool(accumulate)),
+                                      _stream()))
     return out
 
 
-def rank_suggest(ctx: Context, scores, seg_off, n: int = 3, tau: float = TAU, skip_head: int = 0):
-    """Tier 3 over segments scores[seg_off[i]:seg_off[i+1]]; returns (idx, score, count)."""
+def rank_suggest(ctx: Context, scores, seg_off, n: int = 3, tau: float = TAU, skip_head: int = 0, out=None):
+    """Tier 3 over segments scores[seg_off[i]:seg_off[i+1]]; returns (idx, score, count),
+    written into ``out`` = (idx [nseg, n], score [nseg, n], count [nseg]) when given."""
     if scores.dtype not in _DT or not scores.is_contiguous() or scores.device != ctx.device:
         raise ValueError("scores must be a contiguous float32/float64 tensor on the context device")
     if seg_off.dtype != torch.int64 or not seg_off.is_contiguous() or seg_off.device != ctx.device:
         raise ValueError("seg_off must be a contiguous int64 tensor on the context device")
     nseg = seg_off.numel() - 1
-    idx = torch.empty((max(nseg, 0), n), dtype=torch.int32, device=ctx.device)
-    sc = torch.empty((max(nseg, 0), n), dtype=scores.dtype, device=ctx.device)
-    cnt = torch.empty(max(nseg, 0), dtype=torch.int32, device=ctx.device)
+    if out is None:
+        out = (torch.empty((max(nseg, 0), n), dtype=torch.int32, device=ctx.device),
+               torch.empty((max(nseg, 0), n), dtype=scores.dtype, device=ctx.device),
+               torch.empty(max(nseg, 0), dtype=torch.int32, device=ctx.device))
+    idx, sc, cnt = out
+    if (idx.shape != (max(nseg, 0), n) or sc.shape != idx.shape or cnt.numel() != max(nseg, 0)
+            or idx.dtype != torch.int32 or cnt.dtype != torch.int32 or sc.dtype != scores.dtype
+            or not (idx.is_contiguous() and sc.is_contiguous() and cnt.is_contiguous())):
+        raise ValueError("out must be contiguous (idx int32 [nseg, n], score [nseg, n], count int32 [nseg])")
     A.check(ctx.h, A.lib().sugg_rank_suggest(ctx.h, _DT[scores.dtype], _ptr(scores), _ptr(seg_off),
                                              max(nseg, 0), skip_head, n, float(tau), _ptr(idx), _ptr(sc),
                                              _ptr(cnt), _stream()))
     return idx, sc, cnt
+
+
+def band_select(ctx: Context, scores, seg_off, top_idx, top_count, tau: float = TAU, band: float = 0.1,
+                cap: int = 16, skip_head: int = 0, out=None):
+    """Threshold band of short lists (see ``rank_suggest``): per segment whose
+    list holds fewer than n entries, the other entries with score >= tau -
+    band, ascending, at most ``cap``.  Returns (cand [nseg, cap] int32,
+    ref [nseg, cap] scores, flag [nseg] int32: 1 = more than cap)."""
+    if scores.dtype not in _DT or not scores.is_contiguous() or scores.device != ctx.device:
+        raise ValueError("scores must be a contiguous float32/float64 tensor on the context device")
+    if seg_off.dtype != torch.int64 or not seg_off.is_contiguous() or seg_off.device != ctx.device:
+        raise ValueError("seg_off must be a contiguous int64 tensor on the context device")
+    nseg = max(seg_off.numel() - 1, 0)
+    if (top_idx.dtype != torch.int32 or top_idx.dim() != 2 or top_idx.shape[0] != nseg
+            or not top_idx.is_contiguous() or top_count.dtype != torch.int32 or top_count.numel() != nseg):
+        raise ValueError("top_idx [nseg, n] and top_count [nseg] must be contiguous int32 tensors")
+    if out is None:
+        out = (torch.empty((nseg, cap), dtype=torch.int32, device=ctx.device),
+               torch.empty((nseg, cap), dtype=scores.dtype, device=ctx.device),
+               torch.empty(nseg, dtype=torch.int32, device=ctx.device))
+    cand, ref, flag = out
+    A.check(ctx.h, A.lib().sugg_band_select(ctx.h, _DT[scores.dtype], _ptr(scores), _ptr(seg_off), nseg, skip_head,
+                                            _ptr(top_idx), _ptr(top_count), top_idx.shape[1], float(tau),
+                                            float(band), cap, _ptr(cand), _ptr(ref), _ptr(flag), _stream()))
+    return cand, ref, flag
 
 
 TUNE_WAVES = (2, 4, 8)

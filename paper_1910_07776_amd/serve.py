@@ -6,10 +6,12 @@ Per query of K kernels with B optimisations each (all work on one stream,
 every step a libsugg kernel):
   1. z0 = standardised baseline counters of each kernel (Tier 1, baseline rows)
   2. the surrogate's table for all 2^B subsets, then its top-n above tau
-  3. judge: the plain composed value of those n subsets, reading only the
-     versions on their chains; a kernel whose surrogate value differs from the
-     plain one by more than ``tol`` (log-speedup) is flagged
-  4. flagged kernels are re-scored by the plain path (masked fused kernel);
+  3. the threshold band: for a kernel whose list is shorter than n, the other
+     subsets within ``band`` below tau (at most ``cap``; more: fall back)
+  4. judge: the plain composed value of the listed and band subsets, reading
+     only the versions on their chains; a kernel where some surrogate value
+     differs from the plain one by more than ``tol`` (log-speedup) is flagged
+  5. flagged kernels are re-scored by the plain path (masked fused kernel);
      the others keep the surrogate's list, scored with the plain values.
 Queries whose B has no trained surrogate take the plain path entirely.
 """
@@ -25,8 +27,10 @@ from . import plain as G
 
 
 class Server:
-    def __init__(self, ctx: G.Context, nets: dict, n: int = 3, tol: float = 0.1, budget_bytes: int = 8 << 30):
+    def __init__(self, ctx: G.Context, nets: dict, n: int = 3, tol: float = 0.1, budget_bytes: int = 8 << 30,
+                 band: float = 0.1, cap: int = 16):
         self.ctx, self.nets, self.n, self.tol, self.budget = ctx, nets, n, tol, budget_bytes
+        self.band, self.cap = band, cap
         self.plans = {}
         self.fallbacks = torch.zeros((), dtype=torch.int64, device=ctx.device)
         self.kernels_total = 0
@@ -42,7 +46,7 @@ class Server:
         """Bytes a query holds on the device: its counters and cycles, the
         surrogate's table and activations, the outputs."""
         rows = K << B
-        return rows * (E + 1) * 4 + K * (1 << B) * 4 + K * (E + 2 * 512) * 4 + K * 64
+        return rows * (E + 1) * 4 + K * (1 << B) * 4 + K * (E + 2 * 512) * 4 + K * 64 * 4
 
     def answer(self, plan, counters, cycles, out):
         """Suggestions of one query into out = {"idx", "score", "count"};
@@ -55,15 +59,18 @@ class Server:
             G.suggest(self.ctx, plan, counters, cycles, out=out)
             self.fallbacks += plan.K
             return None
-        K, n = plan.K, self.n
+        K, n, dev = plan.K, self.n, self.ctx.device
+        tau = self.ctx.params["tau"]
         z0 = G.load_features(self.ctx, plan, counters, cycles, baseline=True)
         ys = mlp(z0)
-        seg = torch.arange(0, K + 1, dtype=torch.int64, device=self.ctx.device) * (1 << B)
-        cand, sc, cnt = G.rank_suggest(self.ctx, ys.view(-1), seg, n=n, tau=self.ctx.params["tau"], skip_head=1)
-        flag = torch.empty(K, dtype=torch.int32, device=self.ctx.device)
-        out["idx"].copy_(cand)
-        out["count"].copy_(cnt)
-        G.judge(self.ctx, plan, counters, cycles, cand, out=out["score"], ref=sc, tol=self.tol, flag=flag)
+        seg = torch.arange(0, K + 1, dtype=torch.int64, device=dev) * (1 << B)
+        sc = torch.empty((K, n), dtype=ys.dtype, device=dev)
+        G.rank_suggest(self.ctx, ys.view(-1), seg, n=n, tau=tau, skip_head=1, out=(out["idx"], sc, out["count"]))
+        bc, br, flag = G.band_select(self.ctx, ys.view(-1), seg, out["idx"], out["count"], tau=tau,
+                                     band=self.band, cap=self.cap, skip_head=1)
+        G.judge(self.ctx, plan, counters, cycles, out["idx"], out=out["score"], ref=sc, tol=self.tol, flag=flag,
+                accumulate=True)
+        G.judge(self.ctx, plan, counters, cycles, bc, ref=br, tol=self.tol, flag=flag, accumulate=True)
         G.suggest_subset(self.ctx, plan, counters, cycles, flag, out)
         self.fallbacks += flag.sum()
         return flag

@@ -1,10 +1,14 @@
 """GPU serving pieces: the judge (plain composed values of given subsets, and
-the surrogate-disagreement flags), masked re-scoring, and the server's
-fallback to the plain models."""
+the surrogate-disagreement flags), the threshold band, masked re-scoring, and
+the server against the oracle's serving rule (surrogate values are the rule's
+input; the plain values are the FP64 oracle's)."""
 import numpy as np
 import pytest
 import torch
 
+from oracle import plain as P
+from oracle import serve as V
+from oracle.checks import check_list
 from synthgen import make_batch
 
 pytestmark = pytest.mark.gpu
@@ -67,6 +71,48 @@ def test_judge_flags_disagreements(env):
     G.judge(ctx, p, c, cy, torch.from_numpy(cand).cuda(), ref=torch.from_numpy(ref).cuda(), tol=0.1, flag=flag)
     G.sync(ctx)
     assert np.array_equal(flag.cpu().numpy(), want)
+    # accumulate: flags already set stay set, the others follow this call
+    pre = (np.arange(te.K) % 5 == 0).astype(np.int32)
+    flag.copy_(torch.from_numpy(pre))
+    G.judge(ctx, p, c, cy, torch.from_numpy(cand).cuda(), ref=torch.from_numpy(ref).cuda(), tol=0.1, flag=flag,
+            accumulate=True)
+    G.sync(ctx)
+    assert np.array_equal(flag.cpu().numpy(), want | pre)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_band_select_matches_oracle(env, dtype):
+    G, ctx = env[0], env[1]
+    rng = np.random.default_rng(11)
+    lens = np.concatenate([[1, 2, 65, 130, 0], rng.integers(1, 1025, 60)])
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    # per-segment levels: full lists, short lists, and bands over the cap
+    kind = rng.integers(0, 4, size=len(lens))
+    mean = np.array([-0.1, -0.3, -0.5, -0.03])[kind]
+    sd = np.array([0.12, 0.12, 0.12, 0.02])[kind]
+    sc = rng.normal(np.repeat(mean, lens), np.repeat(sd, lens))
+    sc[rng.random(off[-1]) < 0.01] = np.nan
+    sd = torch.from_numpy(sc).to(dtype).cuda()
+    so = torch.from_numpy(off).cuda()
+    n, cap, tau = 3, 16, P.TAU
+    idx, _, cnt = G.rank_suggest(ctx, sd, so, n=n, tau=tau, skip_head=1)
+    cand, ref, flag = G.band_select(ctx, sd, so, idx, cnt, tau=tau, band=0.1, cap=cap, skip_head=1)
+    G.sync(ctx)
+    v = sd.cpu().numpy().astype(np.float64)
+    idx, cnt, cand, ref, flag = (x.cpu().numpy() for x in (idx, cnt, cand, ref, flag))
+    short = full = 0
+    for i in range(len(lens)):
+        seg = v[off[i]:off[i + 1]]
+        listed = [int(x) for x in idx[i, :cnt[i]]]
+        want = V.band(seg, listed, tau, n, 0.1)
+        short += cnt[i] < n
+        full += bool(want) and len(want) > cap
+        got = [int(x) for x in cand[i] if x >= 0]
+        assert got == want[:cap], i
+        assert np.array_equal(ref[i, :len(got)], seg[got].astype(ref.dtype))
+        assert (cand[i, len(got):] == -1).all() and np.isnan(ref[i, len(got):]).all()
+        assert flag[i] == int(len(want) > cap)
+    assert short > 10 and full > 3
 
 
 def test_masked_rescoring(env):
@@ -118,3 +164,51 @@ def test_server_falls_back_to_plain_exactly(env):
     st = serve.run_loop(srv, queries, serve.poisson_arrivals(20, 2000.0, 1))
     assert st["queries"] == 20 and st["p50_ms"] <= st["p99_ms"]
     bad.close()
+
+
+def test_server_matches_the_oracle_serving_rule(env):
+    G, ctx = env[0], env[1]
+    from paper_1910_07776_amd import serve, surrogate as Sg
+    tr = make_batch(77, range(5000, 5256), 128, 12, brange=(0, 12))
+    model = P.fit(tr, 12)
+    q = make_batch(77, range(900, 1140), 128, 12, brange=(6, 6))
+    _, table_o, _ = P.run(model, q)
+    plan = G.Plan(ctx, q.nopts, q.opt_ids, 128, 12)
+    c, cy = torch.from_numpy(q.counters).cuda(), torch.from_numpy(q.cycles).cuda()
+    net = Sg.MLP(ctx, 128, 512, 64, max_batch=256, seed=13)
+    p0 = net.params.clone()
+    K = q.K
+    kept = fell = banded = 0
+    # untrained networks at several output scales and tolerances: some
+    # kernels keep the surrogate's answer, some fall back
+    for scale, tol in ((0.5, 0.1), (1.0, 0.1), (1.0, 0.3), (2.0, 0.3), (3.0, 1.0)):
+        net.params.copy_(p0 * scale)
+        srv = serve.Server(ctx, {6: net}, n=3, tol=tol, band=0.1, cap=16)
+        out = {"idx": torch.empty((K, 3), dtype=torch.int32, device="cuda"),
+               "score": torch.empty((K, 3), device="cuda"),
+               "count": torch.empty(K, dtype=torch.int32, device="cuda"), "table": None}
+        flag = srv.answer(plan, c, cy, out)
+        ys = net(G.load_features(ctx, plan, c, cy, baseline=True))
+        G.sync(ctx)
+        ys, flag = ys.cpu().numpy().astype(np.float64), flag.cpu().numpy()
+        idx, score, count = out["idx"].cpu().numpy(), out["score"].cpu().numpy(), out["count"].cpu().numpy()
+        for k in range(K):
+            plain_k = table_o[q.row_off[k]:q.row_off[k + 1]]
+            fb, ans, judged = V.serve_kernel(ys[k], plain_k, tol=tol, band_width=0.1, cap=16)
+            if any(abs(abs(ys[k, S] - plain_k[S]) - tol) <= 1e-4 for S in judged):
+                continue   # within FP32 rounding of the tolerance: either decision is right
+            assert flag[k] == int(fb), (scale, tol, k)
+            got = [int(x) for x in idx[k, :count[k]]]
+            banded += len(judged) > len(P.rank(ys[k], P.TAU, 3, first=1))
+            if fb:
+                fell += 1
+                errs = check_list(got, score[k, :count[k]], plain_k, P.TAU, 3, 1e-5, first=1)
+                assert not errs, (scale, tol, k, errs)
+            else:
+                kept += 1
+                assert got == [S for S, _ in ans], (scale, tol, k)
+                for (S, v), g in zip(ans, score[k]):
+                    assert abs(np.exp(g) - np.exp(v)) <= 1e-5 * np.exp(v), (scale, tol, k, S)
+    print(f"kept {kept} fell back {fell} with band {banded}")
+    assert kept > 0 and fell > 0, (kept, fell)
+    net.close()
