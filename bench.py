@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=320)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--ibk", action="store_true", help="also run the IBK section with --no-extra")
     ap.add_argument("--ragged-only", action="store_true",
                     help="only the 16,384-kernel ragged measurement (for profiling it alone)")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -196,6 +197,8 @@ def main():
         "fit_ms": fit_ms,
     }
 
+    if not args.no_extra or args.ibk:
+        out["ibk"] = ibk_extra(G, dev, train, test)
     if not args.no_extra:
         out["ragged_16384"] = ragged_extra(G, ctx, dev)
         out["surrogate"] = surrogate_extra(G, dev)
@@ -208,6 +211,57 @@ def main():
         one = P.SubBatch(test, range(K_BATCH))
         out["cpu_baseline"] = cpu_baseline(om, one)
     print(json.dumps(out), flush=True)
+
+
+def speedup_mape(table, truth, row_off):
+    """Mean |e^L - e^T| / e^T over every (kernel, S != 0)."""
+    keep = np.ones(len(table), dtype=bool)
+    keep[np.asarray(row_off[:-1], dtype=np.int64)] = False
+    a, t = np.exp(table[keep]), np.exp(np.asarray(truth, dtype=np.float64)[keep])
+    return float(np.mean(np.abs(a - t) / t))
+
+
+def ibk_extra(G, dev, train, test, reps: int = 10):
+    """The paper's instance-based Tier 2 model (IBK, k = 10) on the headline
+    shape: 512 training kernels (16,384 stored samples per optimisation),
+    scoring 512 kernels x 64 versions: 32,256 chain-edge searches, each over
+    its optimisation's 16,384 samples in 128 dimensions."""
+    import torch
+    from synthgen import make_batch
+    ctx = G.Context(0)
+    ptr = G.Plan(ctx, train.nopts, train.opt_ids, E, D)
+    tc, tcy = torch.from_numpy(train.counters).to(dev), torch.from_numpy(train.cycles).to(dev)
+    t0 = time.perf_counter()
+    G.ibk_fit(ctx, ptr, tc, tcy, k=10)
+    fit_s = time.perf_counter() - t0
+    one = make_batch(1910, range(K_BATCH), E, D)
+    plan = G.Plan(ctx, one.nopts, one.opt_ids, E, D)
+    c, cy = torch.from_numpy(one.counters).to(dev), torch.from_numpy(one.cycles).to(dev)
+    res = G.ibk_suggest(ctx, plan, c, cy)
+    G.sync(ctx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        res = G.ibk_suggest(ctx, plan, c, cy)
+    e1.record()
+    torch.cuda.synchronize()
+    G.sync(ctx)
+    ms = e0.elapsed_time(e1) / reps
+    queries = int(plan.N - plan.K)
+    samples = int(G.ibk_counts(ctx, D)[0])
+    flop = 2.0 * queries * samples * 128
+    tab = res[3].cpu().numpy().astype(np.float64)
+    mape_ibk = speedup_mape(tab, one.truth, one.row_off)
+    G.fit(ctx, ptr, tc, tcy)
+    lin = G.predict(ctx, plan, c, cy)[0].cpu().numpy().astype(np.float64)
+    mape_lin = speedup_mape(lin, one.truth, one.row_off)
+    tf = flop / (ms / 1e3) / 1e12
+    log(f"ibk: {ms:.3f} ms/pass ({tf:.1f} TFLOP/s FP32), MAPE {mape_ibk:.4f} vs linear {mape_lin:.4f}")
+    ctx.close()
+    return {"k": 10, "samples_per_opt": samples, "queries": queries, "ms_per_pass": ms,
+            "predictions_per_s": queries / (ms / 1e3), "suggestions_per_s": plan.K / (ms / 1e3),
+            "distance_tflops": tf, "mfma_fp32_frac": tf / 157.3, "fit_s_host_incl": fit_s,
+            "mape_ibk": mape_ibk, "mape_linear": mape_lin}
 
 
 def ragged_extra(G, ctx, dev):

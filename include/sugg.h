@@ -222,6 +222,39 @@ SUGG_API int32_t sugg_capture_end(sugg_ctx* ctx, hipStream_t stream, sugg_graph*
 SUGG_API int32_t sugg_graph_launch(sugg_ctx* ctx, sugg_graph* graph, hipStream_t stream);
 SUGG_API void sugg_graph_destroy(sugg_graph* graph);
 
+/* ---- Instance-based Tier 2 model (IBK) ---------------------------------------
+ * Section 3.4's instance-based learner, the one the paper adopts (Section 6;
+ * its results use k = 10): every before/after pair of an optimisation in the
+ * training kernels is stored (the before version's standardised feature
+ * vector and the measured log-speedup of adding it), and a prediction is
+ * the mean label of the k stored vectors nearest in Euclidean distance (the
+ * paper's "mode" of real-valued labels read as their mean; equal distances:
+ * the earlier stored sample, samples stored kernel by kernel, then by
+ * version).  The IBK model lives beside the linear one in the context.
+ * E <= 128.  Distances are evaluated in FP32, labels averaged in FP64.
+ *
+ * sugg_ibk_fit: column statistics of the training rows (as sugg_load_features
+ *   FIT_STATS, kept with the IBK model), their standardised vectors, and the
+ *   sample database of every global id; 1 <= k <= 16.  Synchronous (the
+ *   database is built on the host from the plan and uploaded); replaces a
+ *   previous IBK model.
+ * sugg_ibk_counts: samples stored per global id into counts[0..D) (host).
+ * sugg_ibk_predict / sugg_ibk_suggest: as sugg_predict / sugg_suggest with
+ *   the IBK model for Tier 2 (table_out, grid_out, idx_out, score_out,
+ *   count_out with the same layouts); every id of the plan needs samples
+ *   (else SUGG_E_UNTRAINED_OPT).  A plan's first IBK call per output form
+ *   (with or without the grid) builds and uploads its query lists and
+ *   allocates its workspace (not inside a graph capture); later calls only
+ *   enqueue kernels. */
+SUGG_API int32_t sugg_ibk_fit(sugg_ctx* ctx, const sugg_plan* train, const void* counters, const void* cycles,
+                              int32_t k, hipStream_t stream);
+SUGG_API int32_t sugg_ibk_counts(sugg_ctx* ctx, int64_t* counts, int32_t D);
+SUGG_API int32_t sugg_ibk_predict(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                                  void* grid_out, void* table_out, hipStream_t stream);
+SUGG_API int32_t sugg_ibk_suggest(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                                  void* table_out, int32_t* idx_out, void* score_out, int32_t* count_out,
+                                  hipStream_t stream);
+
 /* ---- Learned surrogate ------------------------------------------------------
  * An extension of the paper's Tier 2 (which predicts one optimisation at a
  * time): an MLP in -> hidden -> hidden -> out with exact-erf GELU after both

@@ -18,59 +18,7 @@ using namespace sugg;
 
 #include "ctx.hpp"
 
-struct sugg_graph {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int device = 0;
-  ~sugg_graph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-  }
-};
-
-struct sugg_plan {
-  sugg_ctx* ctx = nullptr;   // identity only: never dereferenced after creation
-  int device = 0;
-  int K = 0, E = 0, D = 0, dtype = SUGG_F32, Bmax = 0;
-  int64_t N = 0;
-  std::vector<int32_t> nopts, opt_ids;
-  std::vector<int64_t> row_off, opt_off;
-  std::vector<int64_t> opt_pairs;   // per global id: number of before/after pairs
-  // device structure
-  Item* d_items = nullptr;
-  KRec* d_recs = nullptr;
-  int64_t* d_row_off = nullptr;
-  int64_t* d_opt_off = nullptr;
-  int32_t* d_opt_ids = nullptr;
-  int32_t* d_nopts = nullptr;
-  int32_t* d_queue = nullptr;
-  int n_items = 0, max_item_rows = 1, max_item_kernels = 1;
-  int uni_B = -1, uni_nk = 0;
-  PathLaunch cfg{4, 2, 0};   // launch shape of the scoring kernel (autotuned)
-  // statistics workspace
-  double* d_stat_partial = nullptr;
-  int stat_chunks = 1;
-  // fit workspace (allocated on the first fit)
-  bool fit_ready = false;
-  double* d_z64 = nullptr;
-  double* d_lcyc64 = nullptr;
-  double* d_gram_partial = nullptr;
-  double* d_solveA = nullptr;
-  double* d_reduced = nullptr;
-  GramWork* d_gwork = nullptr;
-  int64_t* d_pair_base = nullptr;
-  int64_t* d_pair_row0 = nullptr;
-  int32_t* d_pair_bit = nullptr;
-  int32_t* d_opt_work_begin = nullptr;
-  int n_gwork = 0;
-
-  ~sugg_plan() {
-    dfree(d_items); dfree(d_recs); dfree(d_row_off); dfree(d_opt_off); dfree(d_opt_ids); dfree(d_nopts);
-    dfree(d_queue); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
-    dfree(d_solveA); dfree(d_reduced); dfree(d_gwork); dfree(d_pair_base); dfree(d_pair_row0); dfree(d_pair_bit);
-    dfree(d_opt_work_begin);
-  }
-};
+#include "plan.hpp"
 
 namespace {
 
@@ -319,6 +267,9 @@ int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* gri
   a.K = p->K;
   a.uni_B = p->uni_B;
   a.uni_nk = p->uni_nk;
+  a.uni_ops = p->uni_ops;
+  a.uni_opt_lo = p->uni_opt_lo;
+  a.uni_opt_hi = p->uni_opt_hi;
   a.n_items = p->n_items;
   a.queue = p->d_queue;
   a.mu = model_mu<T>(ctx);
@@ -406,6 +357,7 @@ void sugg_destroy(sugg_ctx* ctx) {
   if (!ctx) return;
   (void)device_ok(ctx);
   ctx->free_model();
+  ibk_model_free(ctx->ibk);
   dfree(ctx->d_status);
   delete ctx;
 }
@@ -487,6 +439,18 @@ int32_t sugg_plan_create(sugg_ctx* ctx, int32_t K, int32_t E, int32_t D, int32_t
   if (K > 0 && std::all_of(p->nopts.begin(), p->nopts.end(), [&](int32_t b) { return b == p->nopts[0]; })) {
     p->uni_B = p->nopts[0];
     p->uni_nk = items[0].nk;
+    // and when every kernel also carries the same optimisation ids
+    bool same = true;
+    for (int k = 1; k < K && same; ++k)
+      for (int b = 0; b < p->uni_B; ++b) same &= p->opt_ids[p->opt_off[k] + b] == p->opt_ids[b];
+    if (same) {
+      p->uni_ops = 1;
+      for (int b = 0; b < p->uni_B; ++b) {
+        const uint64_t o = (uint64_t)(uint8_t)p->opt_ids[b];
+        if (b < 8) p->uni_opt_lo |= o << (8 * b);
+        else p->uni_opt_hi |= o << (8 * (b - 8));
+      }
+    }
   }
   p->n_items = (int)items.size();
   p->stat_chunks = colstats_chunks(std::max<int64_t>(p->N, 1));

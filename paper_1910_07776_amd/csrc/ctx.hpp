@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "ibk.hpp"
 #include "kernels.hpp"
 #include "sugg.h"
 
@@ -34,6 +35,8 @@ struct sugg_ctx {
   double *mu64 = nullptr, *sig64 = nullptr, *isg64 = nullptr, *W64 = nullptr;
   float *mu32 = nullptr, *isg32 = nullptr, *W32 = nullptr;
   std::vector<int64_t> counts;
+  // instance-based model (separate from the linear one)
+  IbkModel* ibk = nullptr;
   int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;

@@ -1,0 +1,95 @@
+// Internal: the instance-based Tier 2 model (IBK, k nearest neighbours by
+// Euclidean distance between standardised feature vectors, Section 3.4), its
+// device database and the per-plan query workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace sugg {
+
+constexpr int kIbkList = 16;       // neighbours kept per query (k <= 16)
+constexpr int kIbkQueries = 128;   // queries per workgroup (4 waves x 32)
+constexpr int kIbkTile = 32;       // database samples per staged tile
+
+// Database of one fitted IBK model.  Samples of global optimisation o are
+// [off[o], off[o+1]), stored kernel by kernel, then by before-version S; each
+// is a training row (its standardised vector in Z) and a label.
+struct IbkModel {
+  int E = 0, Epad = 0, D = 0, k = 10;
+  int64_t Ntr = 0, Ns = 0;
+  float* Z = nullptr;          // [Ntr, Epad] FP32, columns >= E zero
+  float* norm = nullptr;       // [Ntr] squared norms of the rows of Z
+  int32_t* srow = nullptr;     // [Ns] before-row of each sample
+  double* y = nullptr;         // [Ns] ln cyc(before) - ln cyc(after)
+  int64_t* d_off = nullptr;    // [D+1]
+  double* mu64 = nullptr;      // [E] training column means of ln(c / cyc)
+  double* sig64 = nullptr;     // [E] and population standard deviations
+  void* mu_t = nullptr;        // [E] the statistics in the training dtype (written by
+  void* isg_t = nullptr;       //     the shared column-statistics kernel, unused here)
+  std::vector<int64_t> off;    // host copy of d_off
+};
+
+// Query lists of one plan for one output mode.  Mode 0 (edges): one query per
+// version S >= 1 of every kernel, the prediction of adding its highest bit to
+// S without it (the last step of its ascending chain), written to row(k, S).
+// Mode 1 (grid): one query per (version S, local bit b not in S), written to
+// grid[row(k, S) * Bmax + b].  Queries are grouped by global id; a tile is
+// (id, first query, count <= kIbkQueries).
+struct IbkQueries {
+  bool built = false;
+  int64_t n = 0;
+  int n_tiles = 0;
+  int32_t* src = nullptr;      // [n] row whose feature vector is the query
+  int64_t* dst = nullptr;      // [n] output index
+  int32_t* tiles = nullptr;    // [n_tiles * 4]
+  std::vector<int64_t> per_opt;
+};
+
+struct IbkPlan {
+  int Epad = 0;
+  float* zq = nullptr;         // [N, Epad] standardised rows of the batch
+  void* edges = nullptr;       // [N] plan dtype: chain-edge predictions
+  IbkQueries q[2];
+};
+
+struct IbkKnnArgs {
+  const float* zq;
+  const float* Z;
+  const float* norm;
+  const int32_t* srow;
+  const double* y;
+  const int64_t* off;
+  const int32_t* q_src;
+  const int64_t* q_dst;
+  const int32_t* tiles;
+  int32_t Epad;
+  int32_t k;
+  void* out;                   // plan dtype
+};
+
+template <typename T>
+hipError_t launch_ibk_z(const T* counters, const T* cycles, int64_t N, int32_t E, int32_t Epad,
+                        const double* mu, const double* sig, float* z, int32_t* status, hipStream_t s);
+template <typename T>
+hipError_t launch_ibk_nan(T* p, int64_t n, hipStream_t s);
+hipError_t launch_ibk_norm(const float* z, int64_t N, int32_t Epad, float* norm, hipStream_t s);
+template <typename T>
+hipError_t launch_ibk_labels(const T* cycles, const int32_t* before, const int32_t* after, int64_t Ns,
+                             double* y, hipStream_t s);
+template <typename T>
+hipError_t launch_ibk_knn(const IbkKnnArgs& a, int n_tiles, hipStream_t s);
+template <typename T>
+hipError_t launch_ibk_compose(const T* edges, const T* grid, int32_t grid_ld, const int64_t* row_off,
+                              const int32_t* nopts, int32_t K, int32_t Bmax, T* table, int32_t* idx_out,
+                              T* score_out, int32_t* count_out, int32_t n, T tau, hipStream_t s);
+
+}  // namespace sugg
+
+using sugg::IbkModel;
+using sugg::IbkPlan;
+
+void ibk_model_free(IbkModel*& m);
+void ibk_plan_free(IbkPlan*& p);

@@ -57,6 +57,9 @@ struct PathArgs {
   int32_t K;
   int32_t uni_B;           // >= 0: all kernels have uni_B optimisations and item i
   int32_t uni_nk;          //       holds kernels [i*uni_nk, (i+1)*uni_nk) (items unused)
+  int32_t uni_ops;         // nonzero (with uni_B >= 0): every kernel has the same global
+  uint64_t uni_opt_lo;     //   optimisation ids, byte b of (lo, hi) = id of local bit b;
+  uint64_t uni_opt_hi;     //   the kernel records are then not read
   int32_t* queue;          // [2] next item, finished workgroups; zero at launch, re-armed by the kernel
   const T* mu;             // [E]
   const T* isg;            // [E] 1 / sigma

@@ -109,6 +109,36 @@ __host__ __device__ inline PathSmem path_smem(int D, int max_rows, int max_nk, i
   return s;
 }
 
+template <typename T> __device__ __forceinline__ T lane_read(T v, int l);
+template <> __device__ __forceinline__ float lane_read<float>(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <> __device__ __forceinline__ double lane_read<double>(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Maximum over aligned groups of G lanes (G a power of two <= 64), received
+// by every lane of the group.  Groups of 16 or more reduce each 16-lane row
+// with DPP rotations and combine rows through lane reads; smaller groups
+// exchange through lane shuffles.
+template <typename T>
+__device__ __forceinline__ T group_max(T v, int G, int lane) {
+  if (G < kRowLanes) {
+    for (int off = 1; off < G; off <<= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+  }
+  v = fmax(v, row_ror<8>(v));
+  v = fmax(v, row_ror<4>(v));
+  v = fmax(v, row_ror<2>(v));
+  v = fmax(v, row_ror<1>(v));
+  if (G == kRowLanes) return v;
+  const T r0 = lane_read(v, 0), r1 = lane_read(v, 16), r2 = lane_read(v, 32), r3 = lane_read(v, 48);
+  if (G == 32) return lane < 32 ? fmax(r0, r1) : fmax(r2, r3);
+  return fmax(fmax(r0, r1), fmax(r2, r3));
+}
+
 template <typename T, int KT>
 __device__ __forceinline__ void write_list(const Entry<T> (&L)[KT], int k, int n, int32_t* idx_out,
                                            T* score_out, int32_t* count_out) {
@@ -228,22 +258,37 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
     const int b0 = wave * 4 * U;
     // adjacent kernels need no metadata for their first rows: issue them now
     const bool early = contig && b0 < R && !a.kmask;
+    const bool early2 = early && b0 + step < R;
     if (early) load(b0, ca, cya);
+    if (early2) load(b0 + step, cb, cyb);
     if (!staged) {
       stage_model();
       staged = true;
     }
     if (tid == 0) s_any = a.kmask ? 0 : 1;
     __syncthreads();
-    for (int i = tid; i < nk; i += nthr) {
-      const KRec& rec = a.recs[item.first + i];
-      kid[i] = rec.kid;
-      kro[i] = rec.row_off;
-      if (a.kmask && a.kmask[rec.kid]) s_any = 1;
-    }
-    for (int i = tid; i < nk * B; i += nthr) {
-      const int kk = i / B, b = i - kk * B;
-      kop[i] = a.recs[item.first + kk].opt[b];
+    if (a.uni_B >= 0 && a.uni_ops) {
+      // same ids everywhere: the records hold nothing the item does not know
+      for (int i = tid; i < nk; i += nthr) {
+        kid[i] = item.first + i;
+        kro[i] = (int64_t)(item.first + i) << B;
+        if (a.kmask && a.kmask[item.first + i]) s_any = 1;
+      }
+      for (int i = tid; i < nk * B; i += nthr) {
+        const int b = i % B;
+        kop[i] = (int)(((b < 8 ? a.uni_opt_lo >> (8 * b) : a.uni_opt_hi >> (8 * (b - 8)))) & 0xffu);
+      }
+    } else {
+      for (int i = tid; i < nk; i += nthr) {
+        const KRec& rec = a.recs[item.first + i];
+        kid[i] = rec.kid;
+        kro[i] = rec.row_off;
+        if (a.kmask && a.kmask[rec.kid]) s_any = 1;
+      }
+      for (int i = tid; i < nk * B; i += nthr) {
+        const int kk = i / B, b = i - kk * B;
+        kop[i] = a.recs[item.first + kk].opt[b];
+      }
     }
 
     // ---- rows: Tier 1 features and Tier 2 predictions ----------------------
@@ -264,12 +309,23 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
         const int kk = live ? (r >> B) : 0;
         const uint32_t S = (uint32_t)r & mask;
         const int ms = msb(S);
-        for (int h = hlo; h < B; ++h) {
-          const int o = kop[kk * B + h];
-          const T p = row_dot<T, NCH, VW>(z, Wl + o * EP, l16) + Wb[o];
-          if (l16 == 0 && live) {
-            if (GRID) a.grid[row_addr(r) * a.grid_ld + h] = ((S >> h) & 1u) ? qnan<T>() : p;
-            if (h > ms) eb[r | (1 << h)] = p;
+        // four independent dot products at a time (their weight reads and
+        // row reductions overlap); each is the same arithmetic as row_dot alone
+        for (int h0 = hlo; h0 < B; h0 += 4) {
+          T p[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int h = h0 + q < B ? h0 + q : B - 1;
+            const int o = kop[kk * B + h];
+            p[q] = row_dot<T, NCH, VW>(z, Wl + o * EP, l16) + Wb[o];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int h = h0 + q;
+            if (h < B && l16 == 0 && live) {
+              if (GRID) a.grid[row_addr(r) * a.grid_ld + h] = ((S >> h) & 1u) ? qnan<T>() : p[q];
+              if (h > ms) eb[r | (1 << h)] = p[q];
+            }
           }
         }
         if (GRID && l16 == 0 && live) {
@@ -288,7 +344,7 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
     }
     if (!early && b0 < R) load(b0, ca, cya);
     for (int base = b0; base < R; base += 2 * step) {
-      if (base + step < R) load(base + step, cb, cyb);
+      if (base + step < R && !(early2 && base == b0)) load(base + step, cb, cyb);
       compute(base, ca, cya);
       if (base + step >= R) break;
       if (base + 2 * step < R) load(base + 2 * step, ca, cya);
@@ -311,20 +367,46 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
     // ---- Tier 3 ranking -----------------------------------------------------
     if (a.idx_out) {
       if (B <= 6) {
+        // a kernel's 2^B subsets sit in one aligned group of G lanes: the
+        // top n by n rounds of a group maximum (ties: the lowest lane, i.e.
+        // the smallest S), each winner dropping out of the next round
         const int G = 1 << B;
+        const int gbase = lane & ~(G - 1);
+        const uint64_t gmask = G == kWave ? ~0ull : ((1ull << G) - 1ull);
         for (int c0 = wave * kWave; c0 < R; c0 += nwaves * kWave) {
-          Entry<T> lst[KT];
-#pragma unroll
-          for (int i = 0; i < KT; ++i) lst[i] = empty_entry<T>();
           const int r = c0 + lane;
-          if (r < R) {
-            const int S = r & (int)mask;
+          const int S = r & (int)mask;
+          T x = -__builtin_inf();
+          if (r < R && S != 0) {
             const T v = Lb[r];
-            if (S != 0 && v > a.tau) { lst[0].v = v; lst[0].s = S; }
+            if (v > a.tau) x = v;
           }
-          group_merge<T, KT>(lst, G);
-          if (r < R && (r & (int)mask) == 0 && (!a.kmask || a.kmask[kid[r >> B]]))
-            write_list<T, KT>(lst, kid[r >> B], a.n, a.idx_out, a.score_out, a.count_out);
+          T v = x;
+          int place = -1;
+          for (int j = 0; j < a.n; ++j) {
+            const T m = group_max(v, G, lane);
+            const bool hit = v == m && m > -__builtin_inf();
+            const uint64_t won = (__ballot(hit) >> gbase) & gmask;
+            if (won && lane == gbase + __ffsll((long long)won) - 1) {
+              place = j;
+              v = -__builtin_inf();
+            }
+          }
+          const int cnt = __popcll((__ballot(place >= 0) >> gbase) & gmask);
+          const bool sel = r < R && (!a.kmask || a.kmask[kid[r >> B]]);
+          if (sel && place >= 0) {
+            const int k = kid[r >> B];
+            a.idx_out[(int64_t)k * a.n + place] = S;
+            a.score_out[(int64_t)k * a.n + place] = x;
+          }
+          if (sel && S == 0) {
+            const int k = kid[r >> B];
+            for (int j = cnt; j < a.n; ++j) {
+              a.idx_out[(int64_t)k * a.n + j] = -1;
+              a.score_out[(int64_t)k * a.n + j] = qnan<T>();
+            }
+            a.count_out[k] = cnt;
+          }
         }
       } else {
         for (int kk = 0; kk < nk; ++kk) {

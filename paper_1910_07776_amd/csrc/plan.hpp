@@ -1,0 +1,68 @@
+// Internal: graphs and plans (the host-built structure of a batch), shared by
+// the C entry points of the linear and the instance-based scoring paths.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "ctx.hpp"
+#include "ibk.hpp"
+
+struct sugg_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+  ~sugg_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+struct sugg_plan {
+  sugg_ctx* ctx = nullptr;   // identity only: never dereferenced after creation
+  int device = 0;
+  int K = 0, E = 0, D = 0, dtype = SUGG_F32, Bmax = 0;
+  int64_t N = 0;
+  std::vector<int32_t> nopts, opt_ids;
+  std::vector<int64_t> row_off, opt_off;
+  std::vector<int64_t> opt_pairs;   // per global id: number of before/after pairs
+  // device structure
+  sugg::Item* d_items = nullptr;
+  sugg::KRec* d_recs = nullptr;
+  int64_t* d_row_off = nullptr;
+  int64_t* d_opt_off = nullptr;
+  int32_t* d_opt_ids = nullptr;
+  int32_t* d_nopts = nullptr;
+  int32_t* d_queue = nullptr;
+  int n_items = 0, max_item_rows = 1, max_item_kernels = 1;
+  int uni_B = -1, uni_nk = 0;
+  int uni_ops = 0;
+  uint64_t uni_opt_lo = 0, uni_opt_hi = 0;
+  sugg::PathLaunch cfg{4, 2, 0};   // launch shape of the scoring kernel (autotuned)
+  // statistics workspace
+  double* d_stat_partial = nullptr;
+  int stat_chunks = 1;
+  // fit workspace (allocated on the first fit)
+  bool fit_ready = false;
+  double* d_z64 = nullptr;
+  double* d_lcyc64 = nullptr;
+  double* d_gram_partial = nullptr;
+  double* d_solveA = nullptr;
+  double* d_reduced = nullptr;
+  sugg::GramWork* d_gwork = nullptr;
+  int64_t* d_pair_base = nullptr;
+  int64_t* d_pair_row0 = nullptr;
+  int32_t* d_pair_bit = nullptr;
+  int32_t* d_opt_work_begin = nullptr;
+  int n_gwork = 0;
+  // instance-based (IBK) scoring workspace, built on its first use
+  IbkPlan* ibk = nullptr;
+
+  ~sugg_plan() {
+    ibk_plan_free(ibk);
+    dfree(d_items); dfree(d_recs); dfree(d_row_off); dfree(d_opt_off); dfree(d_opt_ids); dfree(d_nopts);
+    dfree(d_queue); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
+    dfree(d_solveA); dfree(d_reduced); dfree(d_gwork); dfree(d_pair_base); dfree(d_pair_row0); dfree(d_pair_bit);
+    dfree(d_opt_work_begin);
+  }
+};

@@ -211,6 +211,44 @@ def judge(ctx: Context, plan: Plan, counters, cycles, cand, out=None, ref=None, 
     return out
 
 
+# ---- instance-based Tier 2 model (IBK) ---------------------------------------
+def ibk_fit(ctx: Context, plan: Plan, counters, cycles, k: int = 10):
+    """Store every before/after pair of the plan's kernels as IBK samples (k
+    nearest neighbours, mean label); replaces the context's IBK model."""
+    plan.check_inputs(counters, cycles)
+    A.check(ctx.h, A.lib().sugg_ibk_fit(ctx.h, plan.h, _ptr(counters), _ptr(cycles), int(k), _stream()))
+
+
+def ibk_counts(ctx: Context, D: int) -> np.ndarray:
+    out = np.zeros(D, dtype=np.int64)
+    A.check(ctx.h, A.lib().sugg_ibk_counts(ctx.h, out.ctypes.data_as(C.c_void_p), D))
+    return out
+
+
+def ibk_predict(ctx: Context, plan: Plan, counters, cycles, grid: bool = False):
+    """Returns (table [N], grid [N, Bmax] or None) with IBK as Tier 2."""
+    plan.check_inputs(counters, cycles)
+    table = torch.empty(plan.N, dtype=plan.dtype, device=ctx.device)
+    g = torch.empty((plan.N, plan.Bmax), dtype=plan.dtype, device=ctx.device) if grid else None
+    A.check(ctx.h, A.lib().sugg_ibk_predict(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(g), _ptr(table),
+                                            _stream()))
+    return table, g
+
+
+def ibk_suggest(ctx: Context, plan: Plan, counters, cycles, table: bool = True, out=None):
+    """``suggest`` with IBK as Tier 2; returns (idx, score, count, table or None)."""
+    plan.check_inputs(counters, cycles)
+    n = ctx.params["n_suggest"]
+    if out is None:
+        out = {"idx": torch.empty((plan.K, n), dtype=torch.int32, device=ctx.device),
+               "score": torch.empty((plan.K, n), dtype=plan.dtype, device=ctx.device),
+               "count": torch.empty(plan.K, dtype=torch.int32, device=ctx.device),
+               "table": torch.empty(plan.N, dtype=plan.dtype, device=ctx.device) if table else None}
+    A.check(ctx.h, A.lib().sugg_ibk_suggest(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(out["table"]),
+                                            _ptr(out["idx"]), _ptr(out["score"]), _ptr(out["count"]), _stream()))
+    return out["idx"], out["score"], out["count"], out["table"]
+
+
 def rank_suggest(ctx: Context, scores, seg_off, n: int = 3, tau: float = TAU, skip_head: int = 0, out=None):
     """Tier 3 over segments scores[seg_off[i]:seg_off[i+1]]; returns (idx, score, count),
     written into ``out`` = (idx [nseg, n], score [nseg, n], count [nseg]) when given."""
