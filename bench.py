@@ -90,11 +90,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--ibk", action="store_true", help="also run the IBK section with --no-extra")
+    ap.add_argument("--retune", action="store_true",
+                    help="re-run the autotuner for every plan and rewrite the tuning database")
     ap.add_argument("--ragged-only", action="store_true",
                     help="only the 16,384-kernel ragged measurement (for profiling it alone)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run N device-to-device copies of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
+    global RETUNE
+    RETUNE = args.retune
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -147,8 +151,8 @@ def main():
              "table": torch.empty(nb_rows, dtype=torch.float32, device=dev)} for _ in range(N_BATCHES)]
     views = [(cnt_all[i * nb_rows:(i + 1) * nb_rows], cyc_all[i * nb_rows:(i + 1) * nb_rows])
              for i in range(N_BATCHES)]
-    tune = G.autotune(ctx, plan, *views[0], reps=10)
-    log(f"autotuned launch: {tune['waves']} waves x unroll {tune['unroll']}")
+    tuned = tune(G, ctx, plan, *views[0], reps=10)
+    log(f"launch: {tuned['waves']} waves x unroll {tuned['unroll']} ({tuned['source']})")
     # eager pass first (validates arguments), then capture all batches once
     for i in range(N_BATCHES):
         G.suggest(ctx, plan, *views[i], out=outs[i])
@@ -189,7 +193,7 @@ def main():
         "config": {"workload": "plain method, 512 kernels x 64 versions x 128 FP32 events, top-3 per kernel",
                    "kernels_per_step": K_BATCH, "versions_per_kernel": 1 << B, "events": E,
                    "distinct_resident_batches": N_BATCHES, "launch": "hipGraph of 32 passes",
-                   "autotuned": {"waves": tune["waves"], "unroll": tune["unroll"]}},
+                   "autotuned": {k: tuned[k] for k in ("waves", "unroll", "source", "times_ms") if k in tuned}},
         "suggestions_per_s": sugg_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
@@ -211,6 +215,24 @@ def main():
         one = P.SubBatch(test, range(K_BATCH))
         out["cpu_baseline"] = cpu_baseline(om, one)
     print(json.dumps(out), flush=True)
+
+
+TUNE_DB = os.path.join(ROOT, "paper_1910_07776_amd", "tuning_db.json")
+RETUNE = False
+
+
+def tune(G, ctx, plan, c, cy, reps):
+    """Launch shape of a plan: from the tuning database (autotuner results on
+    this GPU architecture), else (or with --retune) tuned live and recorded."""
+    from paper_1910_07776_amd import tuning
+    db = tuning.TuneCache(TUNE_DB)
+    key = tuning.plan_key(plan, ctx.params["n_suggest"])
+    if RETUNE and key in db:
+        dict.__delitem__(db, key)
+    live = key not in db
+    cfg = dict(G.autotune(ctx, plan, c, cy, reps=reps, cache=db))
+    cfg["source"] = "live autotune" if live else "tuning database"
+    return cfg
 
 
 def speedup_mape(table, truth, row_off):
@@ -290,8 +312,8 @@ def ragged_extra(G, ctx, dev):
            "score": torch.empty((te.K, n), dtype=torch.float32, device=dev),
            "count": torch.empty(te.K, dtype=torch.int32, device=dev),
            "table": torch.empty(te.N, dtype=torch.float32, device=dev)}
-    tune = G.autotune(ctx, plan, c, cy, reps=3)
-    log(f"ragged autotuned launch: {tune['waves']} waves x unroll {tune['unroll']}")
+    tuned = tune(G, ctx, plan, c, cy, reps=3)
+    log(f"ragged launch: {tuned['waves']} waves x unroll {tuned['unroll']} ({tuned['source']})")
     G.suggest(ctx, plan, c, cy, out=out)
     G.sync(ctx)
     g = G.Graph(ctx)
@@ -315,7 +337,7 @@ def ragged_extra(G, ctx, dev):
     return {"kernels": te.K, "versions": int(te.N), "ms_per_pass": ms,
             "predictions_per_s": entries / (ms / 1e3), "suggestions_per_s": te.K / (ms / 1e3),
             "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_pass": by, "fit_ms": fit_ms,
-            "autotuned": {"waves": tune["waves"], "unroll": tune["unroll"]}, "tune_ms": tune["times_ms"]}
+            "autotuned": {k: tuned[k] for k in ("waves", "unroll", "source", "times_ms") if k in tuned}}
 
 
 def surrogate_extra(G, dev):
@@ -360,7 +382,7 @@ def surrogate_extra(G, dev):
     n = ctx.params["n_suggest"]
     outp = {"idx": torch.empty((K, n), dtype=torch.int32, device=dev), "score": torch.empty((K, n), device=dev),
             "count": torch.empty(K, dtype=torch.int32, device=dev), "table": torch.empty(K << B, device=dev)}
-    G.autotune(ctx, plan, counters, cycles, reps=3)
+    tune(G, ctx, plan, counters, cycles, reps=3)
     inf = Sg.MLP(ctx, E, 512, 1 << B, max_batch=K, params=mlp.params.cpu().numpy())
     z0 = torch.empty((K, E), device=dev)
     ys = torch.empty((K, 1 << B), device=dev)
@@ -420,11 +442,14 @@ def surrogate_extra(G, dev):
     return res
 
 
-def serving_extra(G, dev, n_queries: int = 3000):
+def serving_extra(G, dev, n_queries: int = 10000):
     """Profiling queries of 1-4096 kernels (log-uniform), B ~ U{6..10}, Poisson
-    arrivals at 50 % and 80 % of the measured surrogate capacity, HBM budget
-    8 GB: surrogate + judge + plain fallback, and the plain path alone on the
-    80 % trace.  Inputs are resident (one pool of 4096 kernels per B)."""
+    arrivals at 50 % and 80 % of the measured serving capacity, HBM budget
+    8 GB: surrogate + judge + plain fallback for queries of at least 2^21
+    versions (smaller ones take the one-launch plain path: below that size it
+    answers faster, see service_ms), and the plain path alone on the same
+    80 % trace.  Inputs are resident (one pool of 4096
+    kernels per B)."""
     import torch
     from synthgen import make_batch
     from synthgen.torch_world import TorchWorld
@@ -438,13 +463,13 @@ def serving_extra(G, dev, n_queries: int = 3000):
     nets, pools, train_info = {}, {}, {}
     for Bq in range(6, 11):
         tw = TorchWorld(1910, E, Dg, B=Bq)
-        ntr = {6: 1 << 18, 7: 1 << 18, 8: 1 << 17, 9: 1 << 16, 10: 1 << 15}[Bq]
+        ntr = {6: 1 << 18, 7: 1 << 18, 8: 1 << 18, 9: 1 << 17, 10: 1 << 16}[Bq]
         chunk = max(1024, (1 << 22) >> Bq)
         data = Sg.build_dataset(ctx, tw, ntr, chunk=chunk, chunk_base=0)
         val = Sg.build_dataset(ctx, tw, 8192, chunk=min(chunk, 8192), chunk_base=5000, with_truth=True)
         mlp = Sg.MLP(ctx, E, 512, 1 << Bq, max_batch=4096, seed=Bq)
-        hist = Sg.train(mlp, data["X"], data["Y"], epochs=4, lr=1e-3, val=(val["X"], val["T"]), check_every=4)
-        train_info[Bq] = {"train_kernels": ntr, "val_mape_surrogate": hist[-1]["val_mape"],
+        hist = Sg.train(mlp, data["X"], data["Y"], epochs=8, lr=1e-3, val=(val["X"], val["T"]), check_every=8)
+        train_info[Bq] = {"train_kernels": ntr, "epochs": 8, "val_mape_surrogate": hist[-1]["val_mape"],
                           "val_mape_plain": Sg.mape(val["Y"], val["T"])}
         log(f"serving: B={Bq} surrogate MAPE {hist[-1]['val_mape']:.4f} "
             f"(plain {train_info[Bq]['val_mape_plain']:.4f})")
@@ -452,7 +477,8 @@ def serving_extra(G, dev, n_queries: int = 3000):
         del data, val
         c, cy, _ = tw.chunk(7000, 4096)
         pools[Bq] = (c, cy)
-    srv = serve.Server(ctx, nets, n=3, tol=0.1, budget_bytes=8 << 30)
+    min_rows = 1 << 21
+    srv = serve.Server(ctx, nets, n=3, tol=0.1, budget_bytes=8 << 30, min_rows=min_rows)
     rng = np.random.default_rng(11)
     qs = []
     for _ in range(n_queries):
@@ -465,25 +491,54 @@ def serving_extra(G, dev, n_queries: int = 3000):
         out = {"idx": torch.empty((K, 3), dtype=torch.int32, device=dev), "score": torch.empty((K, 3), device=dev),
                "count": torch.empty(K, dtype=torch.int32, device=dev), "table": None}
         qs.append((plan, c[rows], cy[rows], out, serve.Server.footprint(K, Bq, E)))
-    # closed loop: service capacity
+    # service time of one query (answer on the host) by size, surrogate path
+    # (forced) against the plain path
+    svc = {}
+    for Bq in (6, 8, 10):
+        for K in (64, 512, 4096):
+            c, cy = pools[Bq]
+            plan = srv.plan(Bq, K, E, Dg)
+            out = {"idx": torch.empty((K, 3), dtype=torch.int32, device=dev),
+                   "score": torch.empty((K, 3), device=dev),
+                   "count": torch.empty(K, dtype=torch.int32, device=dev), "table": None}
+            args_q = (plan, c[:K << Bq], cy[:K << Bq], out)
+            row = {}
+            for mode in ("surrogate", "plain"):
+                srv.min_rows = 0 if mode == "surrogate" else 1 << 62
+                ts = []
+                for _ in range(12):
+                    t0 = time.perf_counter()
+                    srv.answer(*args_q)
+                    torch.cuda.current_stream().synchronize()
+                    ts.append(time.perf_counter() - t0)
+                row[mode] = float(np.median(ts[2:]) * 1e3)
+            svc[f"B{Bq}_K{K}"] = row
+    srv.min_rows = min_rows
+    log("service ms (surrogate / plain): " + ", ".join(f"{k} {v['surrogate']:.3f}/{v['plain']:.3f}"
+                                                       for k, v in svc.items()))
+    # closed loop, one query at a time with its answer on the host (as in the
+    # real-time loop): service capacity
     for q in qs[:50]:
         srv.answer(*q[:4])
     torch.cuda.synchronize()
     srv.fallbacks.zero_()
-    srv.kernels_total = 0
+    srv.kernels_total = srv.kernels_plain = 0
     t0 = time.perf_counter()
     for q in qs:
         srv.answer(*q[:4])
-    torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()
     busy = time.perf_counter() - t0
     cap = len(qs) / busy
-    fallback_rate = float(srv.fallbacks.item()) / max(1, srv.kernels_total)
-    res = {"queries": len(qs), "capacity_qps": cap, "fallback_rate": fallback_rate,
-           "kernels_per_s_closed_loop": srv.kernels_total / busy, "nets": train_info}
+    sur_kernels = srv.kernels_total - srv.kernels_plain
+    res = {"queries": len(qs), "capacity_qps": cap, "min_rows_for_surrogate": min_rows,
+           "kernels_total": srv.kernels_total, "kernels_plain_by_policy": srv.kernels_plain,
+           "surrogate_fallback_rate": float(srv.fallbacks.item()) / max(1, sur_kernels),
+           "kernels_per_s_closed_loop": srv.kernels_total / busy, "service_ms": svc, "nets": train_info}
+    log(f"serving capacity {cap:.0f} queries/s, surrogate fallback rate {res['surrogate_fallback_rate']:.3f}")
     for frac in (0.5, 0.8):
         arr = serve.poisson_arrivals(len(qs), frac * cap, seed=int(frac * 100))
         st = serve.run_loop(srv, qs, arr)
-        res[f"surrogate_at_{int(frac * 100)}pct"] = st
+        res[f"served_at_{int(frac * 100)}pct"] = st
         log(f"serving {int(frac * 100)}%: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms")
         if frac == 0.8:
             stp = serve.run_loop(srv, qs, arr, plain_only=True)

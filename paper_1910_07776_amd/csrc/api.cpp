@@ -275,6 +275,7 @@ int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* gri
   a.mu = model_mu<T>(ctx);
   a.isg = model_isg<T>(ctx);
   a.W = model_W<T>(ctx);
+  a.ldw = sizeof(T) == 4 ? w32_ld(p->E) : p->E + 1;
   a.grid = grid;
   a.grid_ld = p->Bmax;
   a.table = table;
@@ -301,6 +302,7 @@ int run_judge(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, const
   j.E = p->E;
   j.D = ctx->D;
   j.W = model_W<T>(ctx);
+  j.ldw = sizeof(T) == 4 ? w32_ld(p->E) : p->E + 1;
   j.mu = model_mu<T>(ctx);
   j.isg = model_isg<T>(ctx);
   j.row_off = p->d_row_off;
@@ -839,7 +841,8 @@ int32_t sugg_model_set(sugg_ctx* ctx, int32_t E, int32_t D, const double* mu, co
   int rc = ctx->ensure_model(E, D);
   if (rc) return rc;
   std::vector<double> isg(E), w64(W ? W : mu, W ? W + (size_t)D * (E + 1) : mu);
-  std::vector<float> mu32(E), isg32(E), w32((size_t)D * (E + 1));
+  const int ldw = w32_ld(E);
+  std::vector<float> mu32(E), isg32(E), w32((size_t)D * ldw, 0.0f);
   for (int j = 0; j < E; ++j) {
     isg[j] = 1.0 / sigma[j];
     mu32[j] = (float)mu[j];
@@ -848,7 +851,7 @@ int32_t sugg_model_set(sugg_ctx* ctx, int32_t E, int32_t D, const double* mu, co
   for (int o = 0; o < D; ++o)
     for (int j = 0; j <= E; ++j) {
       const double v = W[(size_t)o * (E + 1) + j];
-      w32[(size_t)o * (E + 1) + j] = counts[o] > 0 ? (float)v : 0.0f;
+      w32[(size_t)o * ldw + j] = counts[o] > 0 ? (float)v : 0.0f;
     }
   hipError_t e = hipMemcpy(ctx->mu64, mu, sizeof(double) * E, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ctx->sig64, sigma, sizeof(double) * E, hipMemcpyHostToDevice);
@@ -856,7 +859,7 @@ int32_t sugg_model_set(sugg_ctx* ctx, int32_t E, int32_t D, const double* mu, co
   if (e == hipSuccess) e = hipMemcpy(ctx->mu32, mu32.data(), sizeof(float) * E, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ctx->isg32, isg32.data(), sizeof(float) * E, hipMemcpyHostToDevice);
   if (e == hipSuccess && D > 0) e = hipMemcpy(ctx->W64, W, sizeof(double) * D * (E + 1), hipMemcpyHostToDevice);
-  if (e == hipSuccess && D > 0) e = hipMemcpy(ctx->W32, w32.data(), sizeof(float) * D * (E + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess && D > 0) e = hipMemcpy(ctx->W32, w32.data(), sizeof(float) * D * ldw, hipMemcpyHostToDevice);
   if (e != hipSuccess) return ctx->hip(e, "model upload");
   for (int o = 0; o < D; ++o) ctx->counts[o] = counts[o];
   ctx->has_stats = true;

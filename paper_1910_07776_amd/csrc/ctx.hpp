@@ -68,7 +68,7 @@ struct sugg_ctx {
     if (r == hipSuccess) r = hipMalloc((void**)&mu32, sizeof(float) * e);
     if (r == hipSuccess) r = hipMalloc((void**)&isg32, sizeof(float) * e);
     if (r == hipSuccess && d > 0) r = hipMalloc((void**)&W64, sizeof(double) * (size_t)d * (e + 1));
-    if (r == hipSuccess && d > 0) r = hipMalloc((void**)&W32, sizeof(float) * (size_t)d * (e + 1));
+    if (r == hipSuccess && d > 0) r = hipMalloc((void**)&W32, sizeof(float) * (size_t)d * sugg::w32_ld(e));
     if (r != hipSuccess) {
       free_model();
       return hip(r, "model allocation");

@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kSolveThreads) solve_kernel(const SolveArgs a,
   if (wb == we) {
     for (int j = tid; j < n1; j += kSolveThreads) {
       a.W64[(int64_t)o * n1 + j] = __builtin_nan("");
-      a.W32[(int64_t)o * n1 + j] = 0.0f;
+      a.W32[(int64_t)o * w32_ld(E) + j] = 0.0f;
     }
     return;
   }
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(kSolveThreads) solve_kernel(const SolveArgs a,
   }
   for (int j = tid; j < n1; j += kSolveThreads) {
     a.W64[(int64_t)o * n1 + j] = y[j];
-    a.W32[(int64_t)o * n1 + j] = (float)y[j];
+    a.W32[(int64_t)o * w32_ld(E) + j] = (float)y[j];
   }
   if (tid == 0 && bad) atomicOr(a.status, (int)kStatusSingular);
 }

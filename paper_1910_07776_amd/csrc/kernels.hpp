@@ -17,6 +17,10 @@ struct alignas(16) KRec {
   uint8_t opt[16];
 };
 
+// Row stride of the FP32 weight copy: E weights and the intercept, padded to
+// a multiple of 4 so every row starts 16-byte aligned.
+__host__ __device__ inline int w32_ld(int E) { return (E + 4) & ~3; }
+
 // Arguments of the judge: plain composed log-speedups of given subsets.
 template <typename T>
 struct JudgeArgs {
@@ -24,7 +28,8 @@ struct JudgeArgs {
   const T* cycles;
   int32_t E;
   int32_t D;
-  const T* W;              // [D, E+1]
+  const T* W;              // [D, ldw]: E weights then the intercept
+  int32_t ldw;             // row stride of W
   const T* mu;
   const T* isg;
   const int64_t* row_off;  // [K+1]
@@ -63,7 +68,8 @@ struct PathArgs {
   int32_t* queue;          // [2] next item, finished workgroups; zero at launch, re-armed by the kernel
   const T* mu;             // [E]
   const T* isg;            // [E] 1 / sigma
-  const T* W;              // [D, E+1]
+  const T* W;              // [D, ldw]: E weights then the intercept
+  int32_t ldw;             // row stride of W
   T* grid;                 // [N, grid_ld] or null
   int32_t grid_ld;
   T* table;                // [N] or null
@@ -160,7 +166,7 @@ struct SolveArgs {
   double* reduced;    // [D, E*E + 2E + 2] workspace: summed partials
   double* A;          // [D, (E+1)^2] workspace when the system does not fit in LDS
   double* W64;        // [D, E+1]
-  float* W32;         // [D, E+1]
+  float* W32;         // [D, w32_ld(E)]
   int32_t* status;
 };
 

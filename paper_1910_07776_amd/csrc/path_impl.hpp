@@ -81,6 +81,60 @@ __device__ __forceinline__ T row_dot(const T (&z)[NCH][VW], const T* wrow, int l
   return row_sum16(part);
 }
 
+// Weights into LDS: D rows of EP columns (zero past E) plus the intercepts.
+// FULL (E == EP): FP32 rows are 16-byte aligned (stride w32_ld(E)), copied as
+// float4.
+template <typename T, bool FULL>
+__device__ __forceinline__ void stage_weights(const T* W, int ldw, int D, int E, int EP, T* Wl, T* Wb, int tid,
+                                              int nthr) {
+  if (FULL && sizeof(T) == 4) {
+    const int q = EP / 4;
+    for (int i = tid; i < D * q; i += nthr) {
+      const int o = i / q, j = (i - o * q) * 4;
+      *reinterpret_cast<float4*>(Wl + o * EP + j) = *reinterpret_cast<const float4*>(W + (int64_t)o * ldw + j);
+    }
+  } else {
+    for (int i = tid; i < D * EP; i += nthr) {
+      const int o = i / EP, j = i - o * EP;
+      Wl[i] = (FULL || j < E) ? W[(int64_t)o * ldw + j] : T(0);
+    }
+  }
+  for (int o = tid; o < D; o += nthr) Wb[o] = W[(int64_t)o * ldw + E];
+}
+
+// This lane's column constants: z = fma(log(c) - log(cyc), s, m) with
+// s = unit / sigma and m = -mu / sigma (zero past E).
+template <typename T, int NCH, int VW, bool FULL>
+__device__ __forceinline__ void column_constants(const T* mu, const T* isg, int E, int l16, T (&s)[NCH][VW],
+                                                 T (&m)[NCH][VW]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int c0 = (l16 + kRowLanes * ch) * VW;
+    T iv[VW], mv[VW];
+    if (FULL || c0 + VW <= E) {
+      const VecN<T, VW> qi = *reinterpret_cast<const VecN<T, VW>*>(isg + c0);
+      const VecN<T, VW> qm = *reinterpret_cast<const VecN<T, VW>*>(mu + c0);
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        iv[v] = qi.v[v];
+        mv[v] = qm.v[v];
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        const bool ok = c0 + v < E;
+        iv[v] = ok ? isg[c0 + v] : T(0);
+        mv[v] = ok ? mu[c0 + v] : T(0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      s[ch][v] = iv[v] * feat_log_unit<T>();
+      m[ch][v] = -mv[v] * iv[v];
+    }
+  }
+}
+
 // Dynamic LDS layout of the fused kernel (host and device agree on it).
 struct PathSmem {
   int ep;        // padded weight row length
@@ -185,21 +239,8 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
   // weights, intercepts and column constants are staged after the first
   // item's row loads are in flight (so the two memory latencies overlap)
   auto stage_model = [&]() {
-    for (int i = tid; i < D * EP; i += nthr) {
-      const int o = i / EP, j = i - o * EP;
-      Wl[i] = (FULL || j < E) ? a.W[(int64_t)o * (E + 1) + j] : T(0);
-    }
-    for (int o = tid; o < D; o += nthr) Wb[o] = a.W[(int64_t)o * (E + 1) + E];
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-      for (int v = 0; v < VW; ++v) {
-        const int col = (l16 + kRowLanes * ch) * VW + v;
-        const bool ok = FULL || col < E;
-        const T isg = ok ? a.isg[col] : T(0);
-        s_r[ch][v] = isg * feat_log_unit<T>();
-        m_r[ch][v] = ok ? -a.mu[col] * isg : T(0);
-      }
+    stage_weights<T, FULL>(a.W, a.ldw, D, E, EP, Wl, Wb, tid, nthr);
+    column_constants<T, NCH, VW, FULL>(a.mu, a.isg, E, l16, s_r, m_r);
   };
   bool staged = false;
   T ca[U][NCH][VW], cb[U][NCH][VW];
@@ -353,23 +394,29 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
     __syncthreads();
 
     // ---- compose the subset table -----------------------------------------
-    for (int r = tid; r < R; r += nthr) {
+    // L(S) = sum over the bits b of S, ascending, of the edge into
+    // S & (2^(b+1) - 1); thread r composes row r of the item
+    auto compose_row = [&](int r) -> T {
       const uint32_t S = (uint32_t)r & mask;
       const int kb = r & ~(int)mask;
       T L = T(0);
       for (int b = 0; b < B; ++b)
         if ((S >> b) & 1u) L += eb[kb | (int)(S & ((2u << b) - 1u))];
-      Lb[r] = L;
       if (a.table && (!a.kmask || a.kmask[kid[r >> B]])) a.table[(contig ? item.row0 + r : kro[r >> B] + S)] = L;
+      return L;
+    };
+    if (B > 6 || !a.idx_out) {
+      for (int r = tid; r < R; r += nthr) Lb[r] = compose_row(r);
+      __syncthreads();
     }
-    __syncthreads();
 
     // ---- Tier 3 ranking -----------------------------------------------------
     if (a.idx_out) {
       if (B <= 6) {
-        // a kernel's 2^B subsets sit in one aligned group of G lanes: the
-        // top n by n rounds of a group maximum (ties: the lowest lane, i.e.
-        // the smallest S), each winner dropping out of the next round
+        // a kernel's 2^B subsets sit in one aligned group of G lanes of the
+        // wave that composes them: the top n by n rounds of a group maximum
+        // (ties: the lowest lane, i.e. the smallest S), each winner dropping
+        // out of the next round
         const int G = 1 << B;
         const int gbase = lane & ~(G - 1);
         const uint64_t gmask = G == kWave ? ~0ull : ((1ull << G) - 1ull);
@@ -377,9 +424,9 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
           const int r = c0 + lane;
           const int S = r & (int)mask;
           T x = -__builtin_inf();
-          if (r < R && S != 0) {
-            const T v = Lb[r];
-            if (v > a.tau) x = v;
+          if (r < R) {
+            const T v = compose_row(r);
+            if (S != 0 && v > a.tau) x = v;
           }
           T v = x;
           int place = -1;
@@ -512,22 +559,9 @@ __global__ void __launch_bounds__(256) judge_kernel(const JudgeArgs<T> a) {
   const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, grp = lane >> 4;
   T* Wl = reinterpret_cast<T*>(smem);
   T* Wb = Wl + D * EP;
-  for (int i = tid; i < D * EP; i += blockDim.x) {
-    const int o = i / EP, j = i - o * EP;
-    Wl[i] = j < E ? a.W[(int64_t)o * (E + 1) + j] : T(0);
-  }
-  for (int o = tid; o < D; o += blockDim.x) Wb[o] = a.W[(int64_t)o * (E + 1) + E];
+  stage_weights<T, false>(a.W, a.ldw, D, E, EP, Wl, Wb, tid, (int)blockDim.x);
   T s_r[NCH][VW], m_r[NCH][VW];
-#pragma unroll
-  for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-    for (int v = 0; v < VW; ++v) {
-      const int col = (l16 + kRowLanes * ch) * VW + v;
-      const bool ok = col < E;
-      const T isg = ok ? a.isg[col] : T(0);
-      s_r[ch][v] = isg * feat_log_unit<T>();
-      m_r[ch][v] = ok ? -a.mu[col] * isg : T(0);
-    }
+  column_constants<T, NCH, VW, false>(a.mu, a.isg, E, l16, s_r, m_r);
   __syncthreads();   // the only barrier: waves below work independently
   const int64_t job = (int64_t)blockIdx.x * 4 + (tid >> 6);
   if (job >= (int64_t)a.K * a.C) return;

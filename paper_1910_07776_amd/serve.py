@@ -13,7 +13,10 @@ every step a libsugg kernel):
      differs from the plain one by more than ``tol`` (log-speedup) is flagged
   5. flagged kernels are re-scored by the plain path (masked fused kernel);
      the others keep the surrogate's list, scored with the plain values.
-Queries whose B has no trained surrogate take the plain path entirely.
+Queries whose B has no trained surrogate, and queries too small to amortise
+the surrogate's extra launches (fewer than ``min_rows`` profiled versions in
+all; the plain path answers them in one launch), take the plain path
+entirely.
 """
 from __future__ import annotations
 
@@ -28,12 +31,13 @@ from . import plain as G
 
 class Server:
     def __init__(self, ctx: G.Context, nets: dict, n: int = 3, tol: float = 0.1, budget_bytes: int = 8 << 30,
-                 band: float = 0.1, cap: int = 16):
+                 band: float = 0.1, cap: int = 16, min_rows: int = 0):
         self.ctx, self.nets, self.n, self.tol, self.budget = ctx, nets, n, tol, budget_bytes
-        self.band, self.cap = band, cap
+        self.band, self.cap, self.min_rows = band, cap, min_rows
         self.plans = {}
         self.fallbacks = torch.zeros((), dtype=torch.int64, device=ctx.device)
         self.kernels_total = 0
+        self.kernels_plain = 0       # answered by the plain path by policy (no surrogate tried)
 
     def plan(self, B: int, K: int, E: int, D: int):
         key = (B, K, E, D)
@@ -55,9 +59,9 @@ class Server:
         B = int(plan.nopts[0]) if plan.K else 0
         mlp = self.nets.get(B)
         self.kernels_total += plan.K
-        if mlp is None or plan.K > mlp.max_batch:
+        if mlp is None or plan.K > mlp.max_batch or plan.N < self.min_rows:
             G.suggest(self.ctx, plan, counters, cycles, out=out)
-            self.fallbacks += plan.K
+            self.kernels_plain += plan.K
             return None
         K, n, dev = plan.K, self.n, self.ctx.device
         tau = self.ctx.params["tau"]
