@@ -99,60 +99,70 @@ hipError_t launch_ibk_labels(const T* cycles, const int32_t* before, const int32
   return hipGetLastError();
 }
 
+// ---- sample rows in database order ---------------------------------------------
+__global__ void __launch_bounds__(256) ibk_gather_kernel(const float* __restrict__ Z, const int32_t* __restrict__ srow,
+                                                         int64_t Ns, int Epad, float* __restrict__ Zs) {
+  const int q = Epad / 4;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Ns * q; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i / q;
+    const int c = (int)(i - s * q) * 4;
+    *reinterpret_cast<float4*>(Zs + s * Epad + c) =
+        *reinterpret_cast<const float4*>(Z + (int64_t)srow[s] * Epad + c);
+  }
+}
+
+hipError_t launch_ibk_gather(const float* Z, const int32_t* srow, int64_t Ns, int32_t Epad, float* Zs,
+                             hipStream_t s) {
+  if (Ns <= 0) return hipSuccess;
+  int64_t blocks = (Ns * (Epad / 4) + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(ibk_gather_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Z, srow, Ns, (int)Epad, Zs);
+  return hipGetLastError();
+}
+
 // ---- the k-nearest-neighbour search ------------------------------------------
-// Each lane keeps the 16 nearest samples seen so far, ascending by (distance,
-// sample index), in LDS (entry j of thread t at [j * 256 + t]); the current
-// 16th is cached in registers so most candidates cost one comparison.
-struct KnnList {
-  float* d;
-  int* i;
-  float wd;
-  int wi;
-  __device__ __forceinline__ void init(float* ld, int* li, int tid) {
-    d = ld + tid;
-    i = li + tid;
-    for (int j = 0; j < kIbkList; ++j) {
-      d[j * 256] = INFINITY;
-      i[j * 256] = INT_MAX;
-    }
-    wd = INFINITY;
-    wi = INT_MAX;
+// A lane's KT nearest samples so far, ascending by (distance, sample index),
+// in registers.  Insertion is a fixed compare-exchange pass (no indexing by
+// lane data); callers guard it with a wave-uniform test so that the common
+// case (no lane of the wave improves its list) costs one comparison.
+template <int KT>
+__device__ __forceinline__ bool knn_better(float d, int s, float wd, int wi) {
+  return d < wd || (d == wd && s < wi);
+}
+
+template <int KT>
+__device__ __forceinline__ void knn_insert(float (&ld)[KT], int (&li)[KT], float d, int s) {
+  // the new entry replaces the last, then sinks to its place
+  ld[KT - 1] = d;
+  li[KT - 1] = s;
+#pragma unroll
+  for (int j = KT - 1; j > 0; --j) {
+    const bool sw = ld[j] < ld[j - 1] || (ld[j] == ld[j - 1] && li[j] < li[j - 1]);
+    const float td = ld[j - 1];
+    const int ti = li[j - 1];
+    ld[j - 1] = sw ? ld[j] : td;
+    li[j - 1] = sw ? li[j] : ti;
+    ld[j] = sw ? td : ld[j];
+    li[j] = sw ? ti : li[j];
   }
-  __device__ __forceinline__ void insert(float dv, int s) {
-    if (dv < wd || (dv == wd && s < wi)) {
-      int j = kIbkList - 1;
-      for (; j > 0; --j) {
-        const float pd = d[(j - 1) * 256];
-        const int pi = i[(j - 1) * 256];
-        if (pd < dv || (pd == dv && pi < s)) break;
-        d[j * 256] = pd;
-        i[j * 256] = pi;
-      }
-      d[j * 256] = dv;
-      i[j * 256] = s;
-      wd = d[(kIbkList - 1) * 256];
-      wi = i[(kIbkList - 1) * 256];
-    }
-  }
-};
+}
 
 // One workgroup: one tile of up to 128 queries of one optimisation (wave w
 // owns queries 32w .. 32w+31, one per lane column), sweeping the
-// optimisation's samples in tiles of 32 staged in LDS; the next tile's loads
-// are in flight while the current one is multiplied.  Lane l holds query
-// (l mod 32)'s feature half h = l / 32: the matrix core's k-slot h of step j
-// carries feature h*EH + j, for samples (A) and queries (B) alike, so the
-// block product is the full dot product.
-template <int EH, typename T>
+// optimisation's samples (contiguous rows) in tiles of 32 staged in LDS; the
+// next tile's loads are in flight while the current one is multiplied.  Lane
+// l holds query (l mod 32)'s feature half h = l / 32: the matrix core's
+// k-slot h of step j carries feature h*EH + j, for samples (A) and queries
+// (B) alike, so the block product is the full dot product.
+template <int EH, int KT, typename T>
 __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
   constexpr int EP = 2 * EH;
   constexpr int LS = EP + 4;                           // padded LDS row (floats)
   constexpr int F4 = (kIbkTile * EP / 4) / 256;        // float4 per thread per tile
   static_assert(F4 >= 1 && (kIbkTile * EP / 4) % 256 == 0, "tile staging shape");
   __shared__ __align__(16) float tz[kIbkTile * LS];
-  __shared__ float tn[kIbkTile];
-  __shared__ float lst_d[kIbkList * 256];
-  __shared__ int lst_i[kIbkList * 256];
+  __shared__ __align__(16) float tn[kIbkTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 31, h = lane >> 5;
   const int o = a.tiles[blockIdx.x * 4 + 0];
@@ -163,6 +173,8 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
   const int qloc = wave * 32 + col;
   const bool qvalid = qloc < nq;
   const bool wave_live = wave * 32 < nq;
+  const float* Zo = a.Z + s0 * EP;
+  const float* No = a.norm + s0;
 
   float qv[EH];
   {
@@ -181,8 +193,13 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
 #pragma unroll
   for (int j = 0; j < EH; ++j) qn = fmaf(qv[j], qv[j], qn);
   qn += __shfl_xor(qn, 32, kWave);
-  KnnList L;
-  L.init(lst_d, lst_i, tid);
+  float ld[KT];
+  int li[KT];
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    ld[j] = INFINITY;
+    li[j] = INT_MAX;
+  }
 
   float4 stg[F4];
   float stn = INFINITY;
@@ -191,18 +208,10 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
     for (int f = 0; f < F4; ++f) {
       const int idx = tid + f * 256;
       const int row = idx / (EP / 4), c4 = idx - row * (EP / 4);
-      const int s = t0 + row;
-      if (s < ns) {
-        const int32_t r = a.srow[s0 + s];
-        stg[f] = *reinterpret_cast<const float4*>(a.Z + (int64_t)r * EP + c4 * 4);
-      } else {
-        stg[f] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      }
+      stg[f] = t0 + row < ns ? *reinterpret_cast<const float4*>(Zo + (int64_t)(t0 + row) * EP + c4 * 4)
+                             : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-    if (tid < kIbkTile) {
-      const int s = t0 + tid;
-      stn = s < ns ? a.norm[a.srow[s0 + s]] : INFINITY;
-    }
+    if (tid < kIbkTile) stn = t0 + tid < ns ? No[t0 + tid] : INFINITY;
   };
   auto store = [&]() {
 #pragma unroll
@@ -220,43 +229,84 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
     __syncthreads();
     if (t0 + kIbkTile < ns) fetch(t0 + kIbkTile);   // in flight during the products
     if (wave_live) {
-      floatx16 acc;
+      // two accumulation chains (alternate groups of four features) keep
+      // the matrix core busy across the dependent-accumulate latency
+      floatx16 acc0, acc1;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+      for (int r = 0; r < 16; ++r) {
+        acc0[r] = 0.0f;
+        acc1[r] = 0.0f;
+      }
       const float* ar = &tz[col * LS + h * EH];
 #pragma unroll
-      for (int j = 0; j < EH; j += 4) {
+      for (int j = 0; j < EH; j += 8) {
         const float4 av = *reinterpret_cast<const float4*>(ar + j);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, qv[j], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, qv[j + 1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, qv[j + 2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, qv[j + 3], acc, 0, 0, 0);
+        const float4 bv = *reinterpret_cast<const float4*>(ar + j + 4);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, qv[j], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(bv.x, qv[j + 4], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, qv[j + 1], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(bv.y, qv[j + 5], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, qv[j + 2], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(bv.z, qv[j + 6], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, qv[j + 3], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(bv.w, qv[j + 7], acc1, 0, 0, 0);
       }
-      // block entry r of this lane: sample (r/4)*8 + h*4 + r%4, query col
-      float dd[16];
+      // block entry r of this lane: sample (r/4)*8 + h*4 + r%4, query col;
+      // padded samples have an infinite norm and never enter a list
+      float4 tq[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) tq[g] = *reinterpret_cast<const float4*>(&tn[g * 8 + h * 4]);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = (r >> 2) * 8 + h * 4 + (r & 3);
-        dd[r] = t0 + i < ns ? qn + tn[i] - 2.0f * acc[r] : INFINITY;
+        const float4 t4 = tq[r >> 2];
+        const float tnv = (r & 3) == 0 ? t4.x : (r & 3) == 1 ? t4.y : (r & 3) == 2 ? t4.z : t4.w;
+        const float d = qn + tnv - 2.0f * (acc0[r] + acc1[r]);
+        const bool in = knn_better<KT>(d, t0 + i, ld[KT - 1], li[KT - 1]);
+        if (__ballot(in) != 0ull) {
+          if (in) knn_insert<KT>(ld, li, d, t0 + i);
+        }
       }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) L.insert(dd[r], t0 + (r >> 2) * 8 + h * 4 + (r & 3));
     }
     __syncthreads();   // the tile is consumed before the next store
   }
   // the two lanes of a query column saw disjoint samples: merge the partner's
-  // list into the lane of half 0, then average the k nearest labels
-  if (h == 0) {
-    const float* pd = lst_d + (tid ^ 32);
-    const int* pi = lst_i + (tid ^ 32);
-    for (int j = 0; j < kIbkList; ++j) L.insert(pd[j * 256], pi[j * 256]);
-    if (qvalid) {
-      const int kk = a.k < ns ? a.k : ns;
-      double sum = 0.0;
-      for (int j = 0; j < kk; ++j) sum += a.y[s0 + L.i[j * 256]];
-      reinterpret_cast<T*>(a.out)[a.q_dst[q0 + qloc]] = (T)(sum / (double)kk);
-    }
+  // list, then average the k nearest labels
+  float od[KT];
+  int oi[KT];
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {   // the partner's list as it stands, before either lane merges
+    od[j] = __shfl_xor(ld[j], 32, kWave);
+    oi[j] = __shfl_xor(li[j], 32, kWave);
   }
+#pragma unroll
+  for (int j = 0; j < KT; ++j)
+    if (knn_better<KT>(od[j], oi[j], ld[KT - 1], li[KT - 1])) knn_insert<KT>(ld, li, od[j], oi[j]);
+  if (h == 0 && qvalid) {
+    // a non-finite query or sample (bad counters, reported through the status
+    // word) leaves slots unfilled: the prediction is then NaN, and no label
+    // is read outside the optimisation's samples
+    const int kk = a.k < ns ? a.k : ns;
+    double sum = 0.0;
+    bool full = true;
+#pragma unroll
+    for (int j = 0; j < KT; ++j)
+      if (j < kk) {
+        const bool ok = li[j] >= 0 && li[j] < ns;
+        full = full && ok;
+        sum += ok ? a.y[s0 + li[j]] : 0.0;
+      }
+    reinterpret_cast<T*>(a.out)[a.q_dst[q0 + qloc]] = full ? (T)(sum / (double)kk) : qnan<T>();
+  }
+}
+
+template <int EH, typename T>
+hipError_t launch_knn_eh(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
+  if (a.k <= 4) hipLaunchKernelGGL((ibk_knn_kernel<EH, 4, T>), dim3(n_tiles), dim3(256), 0, s, a);
+  else if (a.k <= 8) hipLaunchKernelGGL((ibk_knn_kernel<EH, 8, T>), dim3(n_tiles), dim3(256), 0, s, a);
+  else if (a.k <= 12) hipLaunchKernelGGL((ibk_knn_kernel<EH, 12, T>), dim3(n_tiles), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((ibk_knn_kernel<EH, 16, T>), dim3(n_tiles), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -264,19 +314,11 @@ hipError_t launch_ibk_knn(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   (void)hipGetLastError();
   switch (a.Epad) {
-    case 32:
-      hipLaunchKernelGGL((ibk_knn_kernel<16, T>), dim3(n_tiles), dim3(256), 0, s, a);
-      break;
-    case 64:
-      hipLaunchKernelGGL((ibk_knn_kernel<32, T>), dim3(n_tiles), dim3(256), 0, s, a);
-      break;
-    case 128:
-      hipLaunchKernelGGL((ibk_knn_kernel<64, T>), dim3(n_tiles), dim3(256), 0, s, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 32: return launch_knn_eh<16, T>(a, n_tiles, s);
+    case 64: return launch_knn_eh<32, T>(a, n_tiles, s);
+    case 128: return launch_knn_eh<64, T>(a, n_tiles, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 // ---- composition along the ascending chain, then the top-n ------------------

@@ -16,13 +16,12 @@ constexpr int kIbkTile = 32;       // database samples per staged tile
 
 // Database of one fitted IBK model.  Samples of global optimisation o are
 // [off[o], off[o+1]), stored kernel by kernel, then by before-version S; each
-// is a training row (its standardised vector in Z) and a label.
+// is the standardised vector of its before version (a row of Z) and a label.
 struct IbkModel {
   int E = 0, Epad = 0, D = 0, k = 10;
   int64_t Ntr = 0, Ns = 0;
-  float* Z = nullptr;          // [Ntr, Epad] FP32, columns >= E zero
-  float* norm = nullptr;       // [Ntr] squared norms of the rows of Z
-  int32_t* srow = nullptr;     // [Ns] before-row of each sample
+  float* Z = nullptr;          // [Ns, Epad] FP32 sample vectors, columns >= E zero
+  float* norm = nullptr;       // [Ns] their squared norms
   double* y = nullptr;         // [Ns] ln cyc(before) - ln cyc(after)
   int64_t* d_off = nullptr;    // [D+1]
   double* mu64 = nullptr;      // [E] training column means of ln(c / cyc)
@@ -59,7 +58,6 @@ struct IbkKnnArgs {
   const float* zq;
   const float* Z;
   const float* norm;
-  const int32_t* srow;
   const double* y;
   const int64_t* off;
   const int32_t* q_src;
@@ -76,6 +74,8 @@ hipError_t launch_ibk_z(const T* counters, const T* cycles, int64_t N, int32_t E
 template <typename T>
 hipError_t launch_ibk_nan(T* p, int64_t n, hipStream_t s);
 hipError_t launch_ibk_norm(const float* z, int64_t N, int32_t Epad, float* norm, hipStream_t s);
+hipError_t launch_ibk_gather(const float* Z, const int32_t* srow, int64_t Ns, int32_t Epad, float* Zs,
+                             hipStream_t s);
 template <typename T>
 hipError_t launch_ibk_labels(const T* cycles, const int32_t* before, const int32_t* after, int64_t Ns,
                              double* y, hipStream_t s);

@@ -16,7 +16,7 @@ using namespace sugg;
 
 void ibk_model_free(IbkModel*& m) {
   if (!m) return;
-  dfree(m->Z); dfree(m->norm); dfree(m->srow); dfree(m->y); dfree(m->d_off);
+  dfree(m->Z); dfree(m->norm); dfree(m->y); dfree(m->d_off);
   dfree(m->mu64); dfree(m->sig64); dfree(m->mu_t); dfree(m->isg_t);
   delete m;
   m = nullptr;
@@ -82,30 +82,38 @@ int fit_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, int k, hipStrea
     hb.insert(hb.end(), bef[o].begin(), bef[o].end());
     ha.insert(ha.end(), aft[o].begin(), aft[o].end());
   }
+  int32_t* d_before = nullptr;
   int32_t* d_after = nullptr;
   double* partial = nullptr;
+  float* zrows = nullptr;
   const int chunks = colstats_chunks(std::max<int64_t>(p->N, 1));
+  const int64_t ns1 = std::max<int64_t>(m->Ns, 1);
   hipError_t e = hipMalloc((void**)&m->mu64, sizeof(double) * E);
   if (e == hipSuccess) e = hipMalloc((void**)&m->sig64, sizeof(double) * E);
   if (e == hipSuccess) e = hipMalloc((void**)&m->mu_t, sizeof(T) * E);
   if (e == hipSuccess) e = hipMalloc((void**)&m->isg_t, sizeof(T) * E);
   if (e == hipSuccess) e = hipMalloc((void**)&partial, sizeof(double) * 2 * E * chunks);
-  if (e == hipSuccess) e = hipMalloc((void**)&m->Z, sizeof(float) * (size_t)p->N * m->Epad);
-  if (e == hipSuccess) e = hipMalloc((void**)&m->norm, sizeof(float) * (size_t)p->N);
-  if (e == hipSuccess) e = upload_vec(m->srow, hb);
+  if (e == hipSuccess) e = hipMalloc((void**)&zrows, sizeof(float) * (size_t)p->N * m->Epad);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->Z, sizeof(float) * (size_t)ns1 * m->Epad);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->norm, sizeof(float) * (size_t)ns1);
+  if (e == hipSuccess) e = upload_vec(d_before, hb);
   if (e == hipSuccess) e = upload_vec(d_after, ha);
-  if (e == hipSuccess) e = hipMalloc((void**)&m->y, sizeof(double) * std::max<int64_t>(m->Ns, 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->y, sizeof(double) * ns1);
   if (e == hipSuccess) e = upload_vec(m->d_off, m->off);
-  // Tier 1 statistics, standardised rows, norms, labels
+  // Tier 1 statistics, standardised rows, sample vectors in database order,
+  // their norms, labels
   if (e == hipSuccess)
     e = launch_colstats<T>(c, cyc, p->N, E, partial, chunks, m->mu64, m->sig64, (T*)m->mu_t, (T*)m->isg_t,
                            ctx->d_status, s);
-  if (e == hipSuccess) e = launch_ibk_z<T>(c, cyc, p->N, E, m->Epad, m->mu64, m->sig64, m->Z, ctx->d_status, s);
-  if (e == hipSuccess) e = launch_ibk_norm(m->Z, p->N, m->Epad, m->norm, s);
-  if (e == hipSuccess) e = launch_ibk_labels<T>(cyc, m->srow, d_after, m->Ns, m->y, s);
+  if (e == hipSuccess) e = launch_ibk_z<T>(c, cyc, p->N, E, m->Epad, m->mu64, m->sig64, zrows, ctx->d_status, s);
+  if (e == hipSuccess) e = launch_ibk_gather(zrows, d_before, m->Ns, m->Epad, m->Z, s);
+  if (e == hipSuccess) e = launch_ibk_norm(m->Z, m->Ns, m->Epad, m->norm, s);
+  if (e == hipSuccess) e = launch_ibk_labels<T>(cyc, d_before, d_after, m->Ns, m->y, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dfree(d_before);
   dfree(d_after);
   dfree(partial);
+  dfree(zrows);
   if (e != hipSuccess) {
     ibk_model_free(m);
     return ctx->hip(e, "IBK fit");
@@ -216,7 +224,6 @@ int score_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, T* grid, T* t
   a.zq = w->zq;
   a.Z = m->Z;
   a.norm = m->norm;
-  a.srow = m->srow;
   a.y = m->y;
   a.off = m->d_off;
   a.q_src = q.src;

@@ -350,25 +350,32 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
         const int kk = live ? (r >> B) : 0;
         const uint32_t S = (uint32_t)r & mask;
         const int ms = msb(S);
-        // four independent dot products at a time (their weight reads and
-        // row reductions overlap); each is the same arithmetic as row_dot alone
-        for (int h0 = hlo; h0 < B; h0 += 4) {
-          T p[4];
+        // Q independent dot products at a time (their weight reads and row
+        // reductions overlap); each is the same arithmetic as row_dot alone
+        auto dots = [&](auto qc, int h0) {
+          constexpr int Q = decltype(qc)::value;
+          T p[Q];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int h = h0 + q < B ? h0 + q : B - 1;
-            const int o = kop[kk * B + h];
+          for (int q = 0; q < Q; ++q) {
+            const int o = kop[kk * B + h0 + q];
             p[q] = row_dot<T, NCH, VW>(z, Wl + o * EP, l16) + Wb[o];
           }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < Q; ++q) {
             const int h = h0 + q;
-            if (h < B && l16 == 0 && live) {
+            if (l16 == 0 && live) {
               if (GRID) a.grid[row_addr(r) * a.grid_ld + h] = ((S >> h) & 1u) ? qnan<T>() : p[q];
               if (h > ms) eb[r | (1 << h)] = p[q];
             }
           }
+        };
+        int h0 = hlo;
+        for (; h0 + 4 <= B; h0 += 4) dots(std::integral_constant<int, 4>{}, h0);
+        if (h0 + 2 <= B) {
+          dots(std::integral_constant<int, 2>{}, h0);
+          h0 += 2;
         }
+        if (h0 < B) dots(std::integral_constant<int, 1>{}, h0);
         if (GRID && l16 == 0 && live) {
           const int64_t grow = row_addr(r);
           for (int b = B; b < a.grid_ld; ++b) a.grid[grow * a.grid_ld + b] = qnan<T>();

@@ -179,3 +179,31 @@ def test_ibk_errors(G, ctx):
                       dev(one.counters), dev(one.cycles))
     assert e.value.name == "SUGG_E_STATE"
     ctx2.close()
+
+
+def test_ibk_bad_counters_give_nan_and_the_status(G, ctx):
+    """A non-positive counter makes its row's feature vector NaN: the device
+    status reports it, that row's searches find no neighbour and predict NaN,
+    and every other prediction stays finite."""
+    from paper_1910_07776_amd._abi import SuggError
+    tr = make_batch(34, range(16), 128, 6, brange=(4, 4))
+    ids4 = np.tile(np.arange(4, dtype=np.int32), 16)
+    G.ibk_fit(ctx, G.Plan(ctx, tr.nopts, ids4, 128, 6), dev(tr.counters), dev(tr.cycles), k=10)
+    G.sync(ctx)
+    te = make_batch(34, range(100, 104), 128, 6, brange=(2, 2))
+    p = G.Plan(ctx, np.full(4, 2, np.int32), np.tile(np.arange(2, dtype=np.int32), 4), 128, 6)
+    c = te.counters.copy()
+    c[5, 3] = -1.0                                        # kernel 1, version 1
+    table, grid = G.ibk_predict(ctx, p, dev(c), dev(te.cycles), grid=True)
+    with pytest.raises(SuggError) as e:
+        G.sync(ctx)
+    assert e.value.name == "SUGG_E_BAD_COUNTER"
+    g = grid.cpu().numpy()
+    assert np.isnan(g[5]).all()                           # bit 1 of version 1: no neighbour
+    others = np.ones(16, dtype=bool)
+    others[5] = False
+    want = np.zeros((16, 2), dtype=bool)
+    for r in range(16):
+        S = r % 4
+        want[r] = [(S >> b) & 1 == 0 for b in range(2)]
+    assert np.isfinite(g[others][want[others]]).all()
