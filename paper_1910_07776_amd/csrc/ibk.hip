@@ -165,11 +165,16 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
   __shared__ __align__(16) float tn[kIbkTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 31, h = lane >> 5;
-  const int o = a.tiles[blockIdx.x * 4 + 0];
-  const int q0 = a.tiles[blockIdx.x * 4 + 1];
-  const int nq = a.tiles[blockIdx.x * 4 + 2];
+  const int tile = blockIdx.x / a.split, part = blockIdx.x - tile * a.split;
+  const int o = a.tiles[tile * 4 + 0];
+  const int q0 = a.tiles[tile * 4 + 1];
+  const int nq = a.tiles[tile * 4 + 2];
   const int64_t s0 = a.off[o];
   const int ns = (int)(a.off[o + 1] - s0);
+  // this workgroup's share of the samples: whole 32-sample tiles
+  const int ntl = (ns + kIbkTile - 1) / kIbkTile, per = (ntl + a.split - 1) / a.split;
+  const int tb = part * per * kIbkTile;
+  const int te = min(ns, (part + 1) * per * kIbkTile);
   const int qloc = wave * 32 + col;
   const bool qvalid = qloc < nq;
   const bool wave_live = wave * 32 < nq;
@@ -208,10 +213,10 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
     for (int f = 0; f < F4; ++f) {
       const int idx = tid + f * 256;
       const int row = idx / (EP / 4), c4 = idx - row * (EP / 4);
-      stg[f] = t0 + row < ns ? *reinterpret_cast<const float4*>(Zo + (int64_t)(t0 + row) * EP + c4 * 4)
+      stg[f] = t0 + row < te ? *reinterpret_cast<const float4*>(Zo + (int64_t)(t0 + row) * EP + c4 * 4)
                              : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-    if (tid < kIbkTile) stn = t0 + tid < ns ? No[t0 + tid] : INFINITY;
+    if (tid < kIbkTile) stn = t0 + tid < te ? No[t0 + tid] : INFINITY;
   };
   auto store = [&]() {
 #pragma unroll
@@ -223,11 +228,11 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
     if (tid < kIbkTile) tn[tid] = stn;
   };
 
-  fetch(0);
-  for (int t0 = 0; t0 < ns; t0 += kIbkTile) {   // uniform over the workgroup
+  if (tb < te) fetch(tb);
+  for (int t0 = tb; t0 < te; t0 += kIbkTile) {   // uniform over the workgroup
     store();
     __syncthreads();
-    if (t0 + kIbkTile < ns) fetch(t0 + kIbkTile);   // in flight during the products
+    if (t0 + kIbkTile < te) fetch(t0 + kIbkTile);   // in flight during the products
     if (wave_live) {
       // two accumulation chains (alternate groups of four features) keep
       // the matrix core busy across the dependent-accumulate latency
@@ -282,6 +287,17 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
 #pragma unroll
   for (int j = 0; j < KT; ++j)
     if (knn_better<KT>(od[j], oi[j], ld[KT - 1], li[KT - 1])) knn_insert<KT>(ld, li, od[j], oi[j]);
+  if (a.split > 1) {   // partial list of this share; merged by ibk_merge_kernel
+    if (h == 0 && qvalid) {
+      const int64_t base = ((int64_t)(q0 + qloc) * a.split + part) * kIbkList;
+#pragma unroll
+      for (int j = 0; j < kIbkList; ++j) {
+        a.part_d[base + j] = j < KT ? ld[j] : INFINITY;
+        a.part_i[base + j] = j < KT ? li[j] : INT_MAX;
+      }
+    }
+    return;
+  }
   if (h == 0 && qvalid) {
     // a non-finite query or sample (bad counters, reported through the status
     // word) leaves slots unfilled: the prediction is then NaN, and no label
@@ -300,13 +316,68 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
   }
 }
 
+// Merge of the partial lists of one query (one thread per query): the KT
+// nearest over all shares, then the mean of their labels.
+template <int KT, typename T>
+__global__ void __launch_bounds__(256) ibk_merge_kernel(const IbkKnnArgs a) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= a.n_queries) return;
+  float ld[KT];
+  int li[KT];
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    ld[j] = INFINITY;
+    li[j] = INT_MAX;
+  }
+  for (int p = 0; p < a.split; ++p) {
+    const int64_t base = (q * a.split + p) * kIbkList;
+    for (int j = 0; j < KT; ++j) {
+      const float d = a.part_d[base + j];
+      const int s = a.part_i[base + j];
+      if (!knn_better<KT>(d, s, ld[KT - 1], li[KT - 1])) break;   // lists are ascending
+      knn_insert<KT>(ld, li, d, s);
+    }
+  }
+  // the query's optimisation: the tile that holds it (tiles ascend in q)
+  int lo = 0, hi = a.n_tiles - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.tiles[mid * 4 + 1] <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  const int o = a.tiles[lo * 4 + 0];
+  const int64_t s0 = a.off[o];
+  const int ns = (int)(a.off[o + 1] - s0);
+  const int kk = a.k < ns ? a.k : ns;
+  double sum = 0.0;
+  bool full = true;
+#pragma unroll
+  for (int j = 0; j < KT; ++j)
+    if (j < kk) {
+      const bool ok = li[j] >= 0 && li[j] < ns;
+      full = full && ok;
+      sum += ok ? a.y[s0 + li[j]] : 0.0;
+    }
+  reinterpret_cast<T*>(a.out)[a.q_dst[q]] = full ? (T)(sum / (double)kk) : qnan<T>();
+}
+
+template <int EH, int KT, typename T>
+hipError_t launch_knn_kt(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
+  hipLaunchKernelGGL((ibk_knn_kernel<EH, KT, T>), dim3(n_tiles * a.split), dim3(256), 0, s, a);
+  if (a.split > 1) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ibk_merge_kernel<KT, T>), dim3((unsigned)((a.n_queries + 255) / 256)), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 template <int EH, typename T>
 hipError_t launch_knn_eh(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
-  if (a.k <= 4) hipLaunchKernelGGL((ibk_knn_kernel<EH, 4, T>), dim3(n_tiles), dim3(256), 0, s, a);
-  else if (a.k <= 8) hipLaunchKernelGGL((ibk_knn_kernel<EH, 8, T>), dim3(n_tiles), dim3(256), 0, s, a);
-  else if (a.k <= 12) hipLaunchKernelGGL((ibk_knn_kernel<EH, 12, T>), dim3(n_tiles), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((ibk_knn_kernel<EH, 16, T>), dim3(n_tiles), dim3(256), 0, s, a);
-  return hipGetLastError();
+  if (a.k <= 4) return launch_knn_kt<EH, 4, T>(a, n_tiles, s);
+  if (a.k <= 8) return launch_knn_kt<EH, 8, T>(a, n_tiles, s);
+  if (a.k <= 12) return launch_knn_kt<EH, 12, T>(a, n_tiles, s);
+  return launch_knn_kt<EH, 16, T>(a, n_tiles, s);
 }
 
 template <typename T>

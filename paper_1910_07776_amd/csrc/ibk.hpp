@@ -51,6 +51,9 @@ struct IbkPlan {
   int Epad = 0;
   float* zq = nullptr;         // [N, Epad] standardised rows of the batch
   void* edges = nullptr;       // [N] plan dtype: chain-edge predictions
+  float* part_d = nullptr;     // partial neighbour lists when samples are split
+  int32_t* part_i = nullptr;
+  int64_t part_cap = 0;        // entries allocated
   IbkQueries q[2];
 };
 
@@ -65,6 +68,11 @@ struct IbkKnnArgs {
   const int32_t* tiles;
   int32_t Epad;
   int32_t k;
+  int32_t split;               // sample partitions per query tile (workgroups per tile)
+  float* part_d;               // [queries, split, kIbkList] partial lists (split > 1)
+  int32_t* part_i;
+  int64_t n_queries;
+  int32_t n_tiles;
   void* out;                   // plan dtype
 };
 

@@ -26,6 +26,8 @@ void ibk_plan_free(IbkPlan*& p) {
   if (!p) return;
   dfree(p->zq);
   dfree(p->edges);
+  dfree(p->part_d);
+  dfree(p->part_i);
   for (auto& q : p->q) {
     dfree(q.src); dfree(q.dst); dfree(q.tiles);
   }
@@ -232,6 +234,29 @@ int score_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, T* grid, T* t
   a.Epad = w->Epad;
   a.k = m->k;
   a.out = grid ? (void*)grid : w->edges;
+  a.n_queries = q.n;
+  a.n_tiles = q.n_tiles;
+  // enough workgroups for about four per compute unit: each query tile's
+  // samples are split into shares whose neighbour lists are merged after
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+    cus = 256;
+  a.split = q.n_tiles > 0 ? std::min(8, std::max(1, (4 * cus + q.n_tiles - 1) / q.n_tiles)) : 1;
+  a.part_d = nullptr;
+  a.part_i = nullptr;
+  if (a.split > 1) {
+    const int64_t need = q.n * a.split * kIbkList;
+    if (w->part_cap < need) {
+      dfree(w->part_d);
+      dfree(w->part_i);
+      w->part_cap = 0;
+      if (e == hipSuccess) e = hipMalloc((void**)&w->part_d, sizeof(float) * need);
+      if (e == hipSuccess) e = hipMalloc((void**)&w->part_i, sizeof(int32_t) * need);
+      if (e == hipSuccess) w->part_cap = need;
+    }
+    a.part_d = w->part_d;
+    a.part_i = w->part_i;
+  }
   if (e == hipSuccess) e = launch_ibk_knn<T>(a, q.n_tiles, s);
   if (e == hipSuccess)
     e = launch_ibk_compose<T>(grid ? nullptr : (const T*)w->edges, grid, p->Bmax, p->d_row_off, p->d_nopts, p->K,
