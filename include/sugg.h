@@ -203,6 +203,28 @@ SUGG_API int32_t sugg_band_select(sugg_ctx* ctx, int32_t dtype, const void* scor
                                   const int32_t* top_count, int32_t n, double tau, double band, int32_t C,
                                   int32_t* cand_out, void* ref_out, int32_t* flag_out, hipStream_t stream);
 
+/* All-paths composition (an estimator of a subset's speedup that does not
+ * depend on the order of adding its optimisations; the paper predicts one
+ * optimisation at a time, Section 2, and leaves subsets open):
+ *   L(0) = 0,  L(S) = (sum over b in S, ascending, of [L(S-b) + P(S-b, b)]) / |S|,
+ * the mean over every order of S of the linear model's predictions added
+ * along it.  table_out [N] (required) and, with idx_out, the top
+ * n_suggest subsets above tau per kernel as in sugg_suggest.  B_k <= 10
+ * (SUGG_E_SHAPE otherwise). */
+SUGG_API int32_t sugg_predict_allpaths(sugg_ctx* ctx, const sugg_plan* plan, const void* counters,
+                                       const void* cycles, void* table_out, int32_t* idx_out, void* score_out,
+                                       int32_t* count_out, hipStream_t stream);
+
+/* Greedy re-profiling (the tool used iteratively, Section 2: apply the best
+ * suggestion, profile the new version, ask again), on kernels whose every
+ * version is profiled: from S = 0, while some b not in S has a predicted
+ * benefit P(S, b) > tau, take the largest (ties: the smaller b) and continue
+ * from row(k, S + b).  path_out [K x (Bmax+1)] int32: the visited versions
+ * starting with 0, -1 after the last; steps_out [K]: optimisations applied;
+ * gain_out [K] (plan dtype): sum of the predicted benefits of the steps. */
+SUGG_API int32_t sugg_greedy(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                             int32_t* path_out, int32_t* steps_out, void* gain_out, hipStream_t stream);
+
 /* Waits for the stream, then returns and clears the device status word:
  * SUGG_E_BAD_COUNTER or SUGG_E_SINGULAR if a kernel flagged one since the
  * last sync, else SUGG_OK. */

@@ -324,6 +324,46 @@ int run_judge(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, const
   return ctx->hip(launch_path<T>(a, 1, 1, 1, p->cfg, s), "judge");
 }
 
+
+template <typename T>
+int run_paths(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, bool greedy, T* table, int32_t* idx,
+              T* score, int32_t* count, int32_t* path, int32_t* steps, T* gain, hipStream_t s) {
+  PathsArgs<T> a{};
+  a.counters = c;
+  a.cycles = cyc;
+  a.E = p->E;
+  a.D = ctx->D;
+  a.ldw = sizeof(T) == 4 ? w32_ld(p->E) : p->E + 1;
+  a.W = model_W<T>(ctx);
+  a.mu = model_mu<T>(ctx);
+  a.isg = model_isg<T>(ctx);
+  a.row_off = p->d_row_off;
+  a.nopts = p->d_nopts;
+  a.opt_off = p->d_opt_off;
+  a.opt_ids = p->d_opt_ids;
+  a.K = p->K;
+  a.Bmax = p->Bmax;
+  a.n = ctx->params.n_suggest;
+  a.tau = (T)ctx->params.tau;
+  a.table = table;
+  a.idx_out = idx;
+  a.score_out = score;
+  a.count_out = count;
+  a.path_out = path;
+  a.steps_out = steps;
+  a.gain_out = gain;
+  a.status = ctx->d_status;
+  return ctx->hip(launch_paths<T>(a, greedy, s), greedy ? "greedy" : "all-paths");
+}
+
+int paths_checks(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles) {
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (plan->N > 0 && (!counters || !cycles)) return ctx->fail(SUGG_E_ARG, "null counters or cycles");
+  int rc = check_model_for(ctx, plan);
+  if (rc) return rc;
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  return SUGG_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -675,6 +715,41 @@ int32_t sugg_band_select(sugg_ctx* ctx, int32_t dtype, const void* scores, const
                                        cand_out, (float*)ref_out, flag_out, stream), "band");
   return ctx->hip(launch_band<double>((const double*)scores, seg_off, nseg, skip_head, top_idx, top_count, n, lo, C,
                                       cand_out, (double*)ref_out, flag_out, stream), "band");
+}
+
+int32_t sugg_predict_allpaths(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                              void* table_out, int32_t* idx_out, void* score_out, int32_t* count_out,
+                              hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (plan && plan->K > 0 && !table_out) return ctx->fail(SUGG_E_ARG, "table_out is required");
+  if (idx_out && (!score_out || !count_out)) return ctx->fail(SUGG_E_ARG, "idx_out needs score_out and count_out");
+  if (plan && plan->Bmax > 10) return ctx->fail(SUGG_E_SHAPE, "all-paths composition supports B <= 10");
+  int rc = paths_checks(ctx, plan, counters, cycles);
+  if (rc || plan->K == 0) return rc;
+  const size_t lds = plan->dtype == SUGG_F32 ? paths_lds_bytes<float>(ctx->D, plan->E, plan->Bmax)
+                                             : paths_lds_bytes<double>(ctx->D, plan->E, plan->Bmax);
+  if (lds > kLdsPerWorkgroup) return ctx->fail(SUGG_E_BUDGET, "model and tables do not fit in LDS");
+  if (plan->dtype == SUGG_F32)
+    return run_paths<float>(ctx, plan, (const float*)counters, (const float*)cycles, false, (float*)table_out,
+                            idx_out, (float*)score_out, count_out, nullptr, nullptr, nullptr, stream);
+  return run_paths<double>(ctx, plan, (const double*)counters, (const double*)cycles, false, (double*)table_out,
+                           idx_out, (double*)score_out, count_out, nullptr, nullptr, nullptr, stream);
+}
+
+int32_t sugg_greedy(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                    int32_t* path_out, int32_t* steps_out, void* gain_out, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (plan && plan->K > 0 && (!path_out || !steps_out || !gain_out))
+    return ctx->fail(SUGG_E_ARG, "path_out, steps_out and gain_out are required");
+  int rc = paths_checks(ctx, plan, counters, cycles);
+  if (rc || plan->K == 0) return rc;
+  if (path_lds_bound(plan->dtype == SUGG_F32 ? 4 : 8, ctx->D, plan->E, 1, 1, 1) > kLdsPerWorkgroup)
+    return ctx->fail(SUGG_E_BUDGET, "model does not fit in LDS");
+  if (plan->dtype == SUGG_F32)
+    return run_paths<float>(ctx, plan, (const float*)counters, (const float*)cycles, true, nullptr, nullptr, nullptr,
+                            nullptr, path_out, steps_out, (float*)gain_out, stream);
+  return run_paths<double>(ctx, plan, (const double*)counters, (const double*)cycles, true, nullptr, nullptr,
+                           nullptr, nullptr, path_out, steps_out, (double*)gain_out, stream);
 }
 
 int32_t sugg_sync(sugg_ctx* ctx, hipStream_t stream) {

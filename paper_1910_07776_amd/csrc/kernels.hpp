@@ -174,6 +174,36 @@ hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 
+// Arguments of the all-paths composition and greedy re-profiling kernels.
+template <typename T>
+struct PathsArgs {
+  const T* counters;
+  const T* cycles;
+  int32_t E, D, ldw;
+  const T* W;
+  const T* mu;
+  const T* isg;
+  const int64_t* row_off;
+  const int32_t* nopts;
+  const int64_t* opt_off;
+  const int32_t* opt_ids;
+  int32_t K, Bmax, n;
+  T tau;
+  T* table;          // allpaths: [N]
+  int32_t* idx_out;  // allpaths (nullable): [K, n]
+  T* score_out;
+  int32_t* count_out;
+  int32_t* path_out;  // greedy: [K, Bmax + 1]
+  int32_t* steps_out; // greedy: [K]
+  T* gain_out;        // greedy: [K]
+  int32_t* status;
+};
+
+template <typename T>
+hipError_t launch_paths(const PathsArgs<T>& a, bool greedy, hipStream_t s);
+template <typename T>
+size_t paths_lds_bytes(int D, int E, int Bmax);
+
 // ---- surrogate MLP --------------------------------------------------------
 enum GemmEpilogue : int {
   kEpiWgrad = 0,       // FP32 split-K partial of a weight gradient

@@ -211,6 +211,34 @@ def judge(ctx: Context, plan: Plan, counters, cycles, cand, out=None, ref=None, 
     return out
 
 
+def predict_allpaths(ctx: Context, plan: Plan, counters, cycles, rank: bool = True):
+    """All-paths composed table [N] (the mean over every order of adding a
+    subset's optimisations) and, with rank, its top-n per kernel:
+    returns (table, idx, score, count) (the last three None without rank)."""
+    plan.check_inputs(counters, cycles)
+    n = ctx.params["n_suggest"]
+    table = torch.empty(plan.N, dtype=plan.dtype, device=ctx.device)
+    idx = torch.empty((plan.K, n), dtype=torch.int32, device=ctx.device) if rank else None
+    sc = torch.empty((plan.K, n), dtype=plan.dtype, device=ctx.device) if rank else None
+    cnt = torch.empty(plan.K, dtype=torch.int32, device=ctx.device) if rank else None
+    A.check(ctx.h, A.lib().sugg_predict_allpaths(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(table),
+                                                 _ptr(idx), _ptr(sc), _ptr(cnt), _stream()))
+    return table, idx, sc, cnt
+
+
+def greedy(ctx: Context, plan: Plan, counters, cycles):
+    """Greedy re-profiling per kernel: returns (path [K, Bmax+1] int32 of the
+    visited versions from 0, -1 after the last; steps [K]; gain [K], the sum
+    of the predicted benefits of the steps)."""
+    plan.check_inputs(counters, cycles)
+    path = torch.empty((plan.K, plan.Bmax + 1), dtype=torch.int32, device=ctx.device)
+    steps = torch.empty(plan.K, dtype=torch.int32, device=ctx.device)
+    gain = torch.empty(plan.K, dtype=plan.dtype, device=ctx.device)
+    A.check(ctx.h, A.lib().sugg_greedy(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(path), _ptr(steps),
+                                       _ptr(gain), _stream()))
+    return path, steps, gain
+
+
 # ---- instance-based Tier 2 model (IBK) ---------------------------------------
 def ibk_fit(ctx: Context, plan: Plan, counters, cycles, k: int = 10):
     """Store every before/after pair of the plan's kernels as IBK samples (k

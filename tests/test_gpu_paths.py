@@ -1,0 +1,90 @@
+"""GPU all-paths composition and greedy re-profiling against the FP64 oracle.
+The greedy walk must equal the oracle's walk over the GPU's own grid exactly
+(the same FP32 predictions decide every step) and the FP64 model's walk up to
+decisions within 1e-5 of a tie or of the threshold; all-paths tables match to
+1e-5 on the speedup scale."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import paths as A
+from oracle import plain as P
+from oracle.checks import check_list
+from synthgen import make_batch
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def env():
+    from paper_1910_07776_amd import plain as G
+    ctx = G.Context(0)
+    tr = make_batch(41, range(3000, 3128), 128, 10, brange=(2, 10))
+    G.fit(ctx, G.Plan(ctx, tr.nopts, tr.opt_ids, 128, 10), torch.from_numpy(tr.counters).cuda(),
+          torch.from_numpy(tr.cycles).cuda())
+    model = P.fit(tr, 10)
+    te = make_batch(41, range(60), 128, 10, brange=(0, 10))
+    p = G.Plan(ctx, te.nopts, te.opt_ids, 128, 10)
+    c, cy = torch.from_numpy(te.counters).cuda(), torch.from_numpy(te.cycles).cuda()
+    yield G, ctx, model, te, p, c, cy
+    ctx.close()
+
+
+def test_allpaths_table_and_suggestions(env):
+    G, ctx, model, te, p, c, cy = env
+    table, idx, sc, cnt = G.predict_allpaths(ctx, p, c, cy)
+    t2, _, _, _ = G.predict_allpaths(ctx, p, c, cy, rank=False)
+    G.sync(ctx)
+    assert torch.equal(table, t2)
+    grid_o = P.predict_grid(model, te, Bmax=p.Bmax)
+    to, lists = A.suggest_allpaths(grid_o, te)
+    t = table.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_less(np.abs(np.exp(t) - np.exp(to)), RTOL * np.exp(to) + 1e-300)
+    idx, sc, cnt = idx.cpu().numpy(), sc.cpu().numpy(), cnt.cpu().numpy()
+    for k in range(te.K):
+        r0, r1 = te.row_off[k], te.row_off[k + 1]
+        errs = check_list(idx[k, :cnt[k]], sc[k, :cnt[k]], to[r0:r1], P.TAU, 3, 1e-5, first=1)
+        assert not errs, (k, errs)
+
+
+def test_greedy_walks(env):
+    G, ctx, model, te, p, c, cy = env
+    path, steps, gain = G.greedy(ctx, p, c, cy)
+    _, grid = G.predict(ctx, p, c, cy, grid=True)
+    G.sync(ctx)
+    path, steps, gain = path.cpu().numpy(), steps.cpu().numpy(), gain.cpu().numpy()
+    g32 = grid.cpu().numpy().astype(np.float64)
+    go = P.predict_grid(model, te, Bmax=p.Bmax)
+    walked = 0
+    for k in range(te.K):
+        B, r0 = int(te.nopts[k]), int(te.row_off[k])
+        # exact: the oracle's walk over the GPU's own predictions
+        pw, sw = A.greedy_kernel(g32[r0:r0 + (1 << B), :B], B, P.TAU)
+        assert steps[k] == len(sw) and list(path[k, :steps[k] + 1]) == pw, k
+        assert (path[k, steps[k] + 1:] == -1).all()
+        assert abs(gain[k] - sum(sw)) <= 1e-6 * max(1.0, abs(sum(sw)))
+        # FP64 model: equal up to a decision within tolerance of a tie or of
+        # the threshold (where one walk stops and the other goes on)
+        po, so = A.greedy_kernel(go[r0:r0 + (1 << B), :B], B, P.TAU)
+        n = min(len(po), len(pw))
+        first = next((i for i in range(n) if po[i] != pw[i]), None)
+        if first is None and len(po) != len(pw):
+            first = n
+        if first is not None:
+            S = po[first - 1]
+            vals = sorted((go[r0 + S, b] for b in range(B) if not (S >> b) & 1), reverse=True)
+            near_tie = len(vals) > 1 and abs(vals[0] - vals[1]) <= 1e-5
+            near_tau = bool(vals) and abs(vals[0] - P.TAU) <= 1e-5
+            assert near_tie or near_tau, (k, first, po, pw)
+        walked += len(pw) > 1
+    assert walked > te.K // 2
+
+
+def test_allpaths_rejects_more_than_ten_bits(env):
+    G, ctx = env[0], env[1]
+    from paper_1910_07776_amd._abi import SuggError
+    big = make_batch(41, range(1), 128, 12, brange=(11, 11))
+    q = G.Plan(ctx, big.nopts, big.opt_ids, 128, 12)
+    with pytest.raises(SuggError):
+        G.predict_allpaths(ctx, q, torch.from_numpy(big.counters).cuda(), torch.from_numpy(big.cycles).cuda())
