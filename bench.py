@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--ibk", action="store_true", help="also run the IBK section with --no-extra")
+    ap.add_argument("--paths", action="store_true", help="also run the all-paths/greedy section with --no-extra")
     ap.add_argument("--retune", action="store_true",
                     help="re-run the autotuner for every plan and rewrite the tuning database")
     ap.add_argument("--ragged-only", action="store_true",
@@ -203,6 +204,8 @@ def main():
 
     if not args.no_extra or args.ibk:
         out["ibk"] = ibk_extra(G, dev, train, test)
+    if not args.no_extra or args.paths:
+        out["paths"] = paths_extra(G, ctx, dev)
     if not args.no_extra:
         out["ragged_16384"] = ragged_extra(G, ctx, dev)
         out["surrogate"] = surrogate_extra(G, dev)
@@ -233,6 +236,49 @@ def tune(G, ctx, plan, c, cy, reps):
     cfg = dict(G.autotune(ctx, plan, c, cy, reps=reps, cache=db))
     cfg["source"] = "live autotune" if live else "tuning database"
     return cfg
+
+
+def paths_extra(G, ctx, dev, reps: int = 50):
+    """All-paths composition and greedy re-profiling on 512 kernels x 64
+    versions x 128 events (the headline batch; the linear model fitted on the
+    512 training kernels)."""
+    import torch
+    from synthgen import make_batch
+    one = make_batch(1910, range(K_BATCH), E, D)
+    plan = G.Plan(ctx, one.nopts, one.opt_ids, E, D)
+    c, cy = torch.from_numpy(one.counters).to(dev), torch.from_numpy(one.cycles).to(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for name, fn in (("allpaths", lambda: G.predict_allpaths(ctx, plan, c, cy)),
+                     ("greedy", lambda: G.greedy(ctx, plan, c, cy))):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_us"] = e0.elapsed_time(e1) / reps * 1e3
+        res[name + "_out"] = out
+    G.sync(ctx)
+    ap = res.pop("allpaths_out")[0].cpu().numpy().astype(np.float64)
+    chain = G.predict(ctx, plan, c, cy)[0].cpu().numpy().astype(np.float64)
+    path, steps, gain = (x.cpu().numpy() for x in res.pop("greedy_out"))
+    truth = np.asarray(one.truth, dtype=np.float64)
+    # greedy: true log-speedup of the version reached against the best subset's
+    reached = np.array([truth[one.row_off[k] + path[k, steps[k]]] for k in range(one.K)])
+    best = np.array([truth[one.row_off[k]:one.row_off[k + 1]].max() for k in range(one.K)])
+    by = path_bytes(plan.N, E, plan.K, ctx.params["n_suggest"])
+    res.update({"mape_allpaths": speedup_mape(ap, truth, one.row_off),
+                "mape_chain": speedup_mape(chain, truth, one.row_off),
+                "allpaths_hbm_gbs": by / (res["allpaths_us"] * 1e-6) / 1e9,
+                "greedy_mean_steps": float(steps.mean()),
+                "greedy_true_gain_mean": float(reached.mean()), "best_subset_true_gain_mean": float(best.mean()),
+                "greedy_reaches_best_frac": float(np.mean(reached >= best - 1e-12))})
+    log(f"paths: all-paths {res['allpaths_us']:.1f} us (MAPE {res['mape_allpaths']:.4f} vs chain "
+        f"{res['mape_chain']:.4f}), greedy {res['greedy_us']:.1f} us, {res['greedy_mean_steps']:.2f} steps, "
+        f"true gain {res['greedy_true_gain_mean']:.3f} of best {res['best_subset_true_gain_mean']:.3f}")
+    return res
 
 
 def speedup_mape(table, truth, row_off):
