@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--ibk", action="store_true", help="also run the IBK section with --no-extra")
     ap.add_argument("--paths", action="store_true", help="also run the all-paths/greedy section with --no-extra")
+    ap.add_argument("--launch", default=None,
+                    help="WAVES,UNROLL: force the scoring kernel's launch shape (no tuning)")
     ap.add_argument("--retune", action="store_true",
                     help="re-run the autotuner for every plan and rewrite the tuning database")
     ap.add_argument("--ragged-only", action="store_true",
@@ -98,8 +100,9 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run N device-to-device copies of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
-    global RETUNE
+    global RETUNE, FORCE
     RETUNE = args.retune
+    FORCE = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -222,12 +225,16 @@ def main():
 
 TUNE_DB = os.path.join(ROOT, "paper_1910_07776_amd", "tuning_db.json")
 RETUNE = False
+FORCE = None
 
 
 def tune(G, ctx, plan, c, cy, reps):
     """Launch shape of a plan: from the tuning database (autotuner results on
     this GPU architecture), else (or with --retune) tuned live and recorded."""
     from paper_1910_07776_amd import tuning
+    if FORCE:
+        plan.set_launch(FORCE[0], FORCE[1], 0)
+        return {"waves": FORCE[0], "unroll": FORCE[1], "source": "forced (--launch)"}
     db = tuning.TuneCache(TUNE_DB)
     key = tuning.plan_key(plan, ctx.params["n_suggest"])
     if RETUNE and key in db:
