@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--ibk", action="store_true", help="also run the IBK section with --no-extra")
     ap.add_argument("--paths", action="store_true", help="also run the all-paths/greedy section with --no-extra")
+    ap.add_argument("--serving", action="store_true", help="also run the serving section with --no-extra")
     ap.add_argument("--launch", default=None,
                     help="WAVES,UNROLL: force the scoring kernel's launch shape (no tuning)")
     ap.add_argument("--retune", action="store_true",
@@ -212,6 +213,7 @@ def main():
     if not args.no_extra:
         out["ragged_16384"] = ragged_extra(G, ctx, dev)
         out["surrogate"] = surrogate_extra(G, dev)
+    if not args.no_extra or args.serving:
         out["serving"] = serving_extra(G, dev)
 
     if not args.no_cpu:

@@ -225,6 +225,25 @@ SUGG_API int32_t sugg_predict_allpaths(sugg_ctx* ctx, const sugg_plan* plan, con
 SUGG_API int32_t sugg_greedy(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
                              int32_t* path_out, int32_t* steps_out, void* gain_out, hipStream_t stream);
 
+/* One serving query, every step enqueued on the stream (no host wait): for
+ * a plan whose K kernels all have B optimisations (FP32), a frozen surrogate
+ * mapping E features to 2^B log-speedups (K <= its max batch):
+ *   1. each kernel's standardised baseline row (Tier 1, as sugg_load_features
+ *      with SUGG_BASELINE), 2. the surrogate's table, 3. its top n_suggest
+ *      above tau, 4. the threshold band of short lists (sugg_band_select, at
+ *      most cap subsets), 5. the judge of the listed and band subsets
+ *      against the plain composed values, 6. the plain fused path for the
+ *      kernels flagged (difference above tol, or band overflow).
+ * idx_out [K x n] / score_out [K x n] / count_out [K]: the answer (subsets of
+ * the surrogate's list with their plain values, or the plain answer where
+ * flagged); flag_out [K]: 1 where the plain path answered.  A learned
+ * surrogate is an extension of the paper's Tier 2, which stays the judge.
+ * The plan keeps a workspace for its queries (allocated on its first call,
+ * not inside a graph capture). */
+SUGG_API int32_t sugg_serve_query(sugg_ctx* ctx, const sugg_plan* plan, sugg_mlp* mlp, const void* counters,
+                                  const void* cycles, double tol, double band, int32_t cap, int32_t* idx_out,
+                                  void* score_out, int32_t* count_out, int32_t* flag_out, hipStream_t stream);
+
 /* Waits for the stream, then returns and clears the device status word:
  * SUGG_E_BAD_COUNTER or SUGG_E_SINGULAR if a kernel flagged one since the
  * last sync, else SUGG_OK. */
@@ -297,6 +316,10 @@ SUGG_API int32_t sugg_mlp_create(sugg_ctx* ctx, int32_t in, int32_t hidden, int3
                                  sugg_mlp** out_mlp);
 SUGG_API void sugg_mlp_destroy(sugg_mlp* mlp);
 SUGG_API int64_t sugg_mlp_param_count(const sugg_mlp* mlp);
+/* Keeps a copy of params for inference (sugg_serve_query): the BF16 working
+ * weights are packed from it once, and again only after another call
+ * packed other parameters. */
+SUGG_API int32_t sugg_mlp_freeze(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, hipStream_t stream);
 /* y = MLP(x); keep != 0 saves what sugg_mlp_backward needs. */
 SUGG_API int32_t sugg_mlp_forward(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, const float* x, int32_t batch,
                                   float* y, int32_t keep, hipStream_t stream);

@@ -752,6 +752,73 @@ int32_t sugg_greedy(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, 
                            nullptr, nullptr, path_out, steps_out, (double*)gain_out, stream);
 }
 
+int32_t sugg_serve_query(sugg_ctx* ctx, const sugg_plan* plan, sugg_mlp* mlp, const void* counters,
+                         const void* cycles, double tol, double band, int32_t cap, int32_t* idx_out, void* score_out,
+                         int32_t* count_out, int32_t* flag_out, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (plan->dtype != SUGG_F32) return ctx->fail(SUGG_E_ARG, "serving runs on FP32 plans");
+  if (plan->K == 0) return SUGG_OK;
+  if (plan->uni_B < 0) return ctx->fail(SUGG_E_SHAPE, "a serving query has one B for all its kernels");
+  if (!counters || !cycles || !idx_out || !score_out || !count_out || !flag_out)
+    return ctx->fail(SUGG_E_ARG, "null argument");
+  if (!(tol >= 0.0) || !(band >= 0.0) || cap < 1 || cap > 64) return ctx->fail(SUGG_E_ARG, "bad tol, band or cap");
+  int in = 0, out = 0, bm = 0;
+  if (!mlp) return ctx->fail(SUGG_E_ARG, "null mlp");
+  mlp_dims(mlp, &in, &out, &bm);
+  const int B = plan->uni_B, K = plan->K, n = ctx->params.n_suggest;
+  if (in != plan->E || out != (1 << B)) return ctx->fail(SUGG_E_SHAPE, "mlp %d -> %d does not map E=%d to 2^%d", in, out, plan->E, B);
+  if (K > bm) return ctx->fail(SUGG_E_SHAPE, "query of %d kernels above the mlp's batch %d", K, bm);
+  int rc = check_model_for(ctx, plan);
+  if (rc) return rc;
+  if (path_lds_bound(4, ctx->D, plan->E, plan->max_item_rows, plan->max_item_kernels, plan->Bmax) > kLdsPerWorkgroup)
+    return ctx->fail(SUGG_E_BUDGET, "model does not fit in LDS");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  sugg_plan* p = const_cast<sugg_plan*>(plan);
+  if (!p->serve || p->serve->cap < cap) {
+    delete p->serve;
+    p->serve = new (std::nothrow) ServeWs();
+    if (!p->serve) return ctx->fail(SUGG_E_BUDGET, "out of host memory");
+    ServeWs& w = *p->serve;
+    w.cap = cap;
+    std::vector<int64_t> seg(K + 1);
+    for (int k = 0; k <= K; ++k) seg[k] = (int64_t)k << B;
+    hipError_t e = hipMalloc((void**)&w.z0, sizeof(float) * (size_t)K * plan->E);
+    if (e == hipSuccess) e = hipMalloc((void**)&w.ys, sizeof(float) * ((size_t)K << B));
+    if (e == hipSuccess) e = hipMalloc((void**)&w.sc, sizeof(float) * (size_t)K * n);
+    if (e == hipSuccess) e = hipMalloc((void**)&w.br, sizeof(float) * (size_t)K * cap);
+    if (e == hipSuccess) e = hipMalloc((void**)&w.bout, sizeof(float) * (size_t)K * cap);
+    if (e == hipSuccess) e = hipMalloc((void**)&w.bc, sizeof(int32_t) * (size_t)K * cap);
+    if (e == hipSuccess) e = upload(w.seg, seg.data(), sizeof(int64_t) * (K + 1));
+    if (e != hipSuccess) {
+      delete p->serve;
+      p->serve = nullptr;
+      return ctx->hip(e, "serving workspace");
+    }
+  }
+  ServeWs& w = *p->serve;
+  const float* c = (const float*)counters;
+  const float* cy = (const float*)cycles;
+  // 1. standardised baseline rows, 2. the surrogate's tables
+  rc = ctx->hip(launch_standardize_rows<float>(c, cy, p->d_row_off, K, p->E, ctx->mu32, ctx->isg32, w.z0,
+                                               ctx->d_status, stream), "serve: baseline features");
+  if (!rc) rc = mlp_infer(ctx, mlp, w.z0, K, w.ys, stream);
+  // 3. its top n, 4. the threshold band of short lists (overflow flags)
+  if (!rc)
+    rc = ctx->hip(launch_rank<float>(w.ys, w.seg, K, 1, n, (float)ctx->params.tau, idx_out, w.sc, count_out, stream),
+                  "serve: rank");
+  if (!rc)
+    rc = ctx->hip(launch_band<float>(w.ys, w.seg, K, 1, idx_out, count_out, n, ctx->params.tau - band, cap, w.bc,
+                                     w.br, flag_out, stream), "serve: band");
+  // 5. the judge on both (plain values of the listed subsets are the answer's scores)
+  if (!rc) rc = run_judge<float>(ctx, p, c, cy, idx_out, n, (float*)score_out, w.sc, tol, flag_out, 1, stream);
+  if (!rc) rc = run_judge<float>(ctx, p, c, cy, w.bc, cap, w.bout, w.br, tol, flag_out, 1, stream);
+  // 6. the plain path for the flagged kernels
+  if (!rc)
+    rc = run_path<float>(ctx, p, c, cy, nullptr, nullptr, idx_out, (float*)score_out, count_out, n, stream, flag_out);
+  return rc;
+}
+
 int32_t sugg_sync(sugg_ctx* ctx, hipStream_t stream) {
   if (!ctx) return SUGG_E_ARG;
   if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");

@@ -23,13 +23,15 @@ struct sugg_mlp {
   __bf16 *dy = nullptr, *dyt = nullptr, *da2 = nullptr, *da2t = nullptr, *da1t = nullptr;
   float *a1 = nullptr, *a2 = nullptr, *part = nullptr, *loss_part = nullptr, *ybuf = nullptr;
   int64_t part_n = 0;
+  float* frozen = nullptr;      // inference copy of the parameters (sugg_mlp_freeze)
+  bool packed_frozen = false;   // the BF16 working weights hold the frozen parameters
   int kept_batch = -1;    // batch of the last forward that kept activations
   bool have_dy = false;   // dY of that batch is in dy/dyt (from sugg_mlp_loss)
   ~sugg_mlp() {
     dfree(w1); dfree(w2); dfree(w2t); dfree(w3); dfree(w3t);
     dfree(xb); dfree(xt); dfree(h1); dfree(h1t); dfree(h2); dfree(h2t);
     dfree(dy); dfree(dyt); dfree(da2); dfree(da2t); dfree(da1t);
-    dfree(a1); dfree(a2); dfree(part); dfree(loss_part); dfree(ybuf);
+    dfree(a1); dfree(a2); dfree(part); dfree(loss_part); dfree(ybuf); dfree(frozen);
   }
 };
 
@@ -77,11 +79,15 @@ int check_mlp(sugg_ctx* ctx, sugg_mlp* m, int batch) {
 
 // forward pass; target (nullable) adds the squared-error loss and dY
 int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int B, float* y, bool keep,
-            const float* target, float* loss, hipStream_t s) {
+            const float* target, float* loss, hipStream_t s, bool pack_weights = true) {
   const int in = m->in, hid = m->hid, out = m->out, bm = m->bm;
-  hipError_t e = launch_pack(params + m->off_w1, hid, in, m->w1, in, nullptr, 0, s);
-  if (e == hipSuccess) e = launch_pack(params + m->off_w2, hid, hid, m->w2, hid, m->w2t, hid, s);
-  if (e == hipSuccess) e = launch_pack(params + m->off_w3, out, hid, m->w3, hid, m->w3t, out, s);
+  hipError_t e = hipSuccess;
+  if (pack_weights) {
+    e = launch_pack(params + m->off_w1, hid, in, m->w1, in, nullptr, 0, s);
+    if (e == hipSuccess) e = launch_pack(params + m->off_w2, hid, hid, m->w2, hid, m->w2t, hid, s);
+    if (e == hipSuccess) e = launch_pack(params + m->off_w3, out, hid, m->w3, hid, m->w3t, out, s);
+    m->packed_frozen = params == m->frozen;
+  }
   if (e == hipSuccess) e = launch_pack(x, B, in, m->xb, in, keep ? m->xt : nullptr, bm, s);
   if (e != hipSuccess) return ctx->hip(e, "mlp pack");
   GemmArgs g = gemm(m->xb, in, m->w1, in, B, hid, in);
@@ -161,6 +167,21 @@ int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grad
 
 }  // namespace
 
+// Inference with the frozen parameters (packed once, repacked only after a
+// call with other parameters overwrote the working weights).
+int mlp_infer(sugg_ctx* ctx, sugg_mlp* m, const float* x, int B, float* y, hipStream_t s) {
+  if (!m || m->ctx != ctx) return ctx->fail(SUGG_E_ARG, "mlp missing or from another context");
+  if (!m->frozen) return ctx->fail(SUGG_E_STATE, "mlp has no frozen parameters (sugg_mlp_freeze)");
+  if (B < 1 || B > m->bm) return ctx->fail(SUGG_E_SHAPE, "batch %d outside [1, %d]", B, m->bm);
+  return forward(ctx, m, m->frozen, x, B, y, false, nullptr, nullptr, s, !m->packed_frozen);
+}
+
+void mlp_dims(const sugg_mlp* m, int* in, int* out, int* max_batch) {
+  *in = m->in;
+  *out = m->out;
+  *max_batch = m->bm;
+}
+
 extern "C" {
 
 int32_t sugg_mlp_create(sugg_ctx* ctx, int32_t in, int32_t hidden, int32_t out, int32_t max_batch, sugg_mlp** res) {
@@ -231,6 +252,20 @@ void sugg_mlp_destroy(sugg_mlp* mlp) {
 }
 
 int64_t sugg_mlp_param_count(const sugg_mlp* mlp) { return mlp ? mlp->nparam : -1; }
+
+int32_t sugg_mlp_freeze(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!mlp || mlp->ctx != ctx || !params) return ctx->fail(SUGG_E_ARG, "mlp or params missing");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  if (!mlp->frozen) {
+    const hipError_t e = hipMalloc((void**)&mlp->frozen, sizeof(float) * mlp->nparam);
+    if (e != hipSuccess) return ctx->hip(e, "frozen parameters");
+  }
+  hipError_t e = hipMemcpyAsync(mlp->frozen, params, sizeof(float) * mlp->nparam, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return ctx->hip(e, "frozen parameters");
+  mlp->packed_frozen = false;
+  return SUGG_OK;
+}
 
 int32_t sugg_mlp_forward(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, const float* x, int32_t batch,
                          float* y, int32_t keep, hipStream_t stream) {

@@ -18,6 +18,20 @@ struct sugg_graph {
   }
 };
 
+// Workspace of a plan's serving queries (sugg_serve_query), built on first use.
+struct ServeWs {
+  int cap = 0;
+  float *z0 = nullptr, *ys = nullptr, *sc = nullptr, *br = nullptr, *bout = nullptr;
+  int32_t* bc = nullptr;
+  int64_t* seg = nullptr;
+  ~ServeWs() {
+    dfree(z0); dfree(ys); dfree(sc); dfree(br); dfree(bout); dfree(bc); dfree(seg);
+  }
+};
+
+int mlp_infer(sugg_ctx* ctx, sugg_mlp* m, const float* x, int B, float* y, hipStream_t s);
+void mlp_dims(const sugg_mlp* m, int* in, int* out, int* max_batch);
+
 struct sugg_plan {
   sugg_ctx* ctx = nullptr;   // identity only: never dereferenced after creation
   int device = 0;
@@ -57,8 +71,10 @@ struct sugg_plan {
   int n_gwork = 0;
   // instance-based (IBK) scoring workspace, built on its first use
   IbkPlan* ibk = nullptr;
+  ServeWs* serve = nullptr;
 
   ~sugg_plan() {
+    delete serve;
     ibk_plan_free(ibk);
     dfree(d_items); dfree(d_recs); dfree(d_row_off); dfree(d_opt_off); dfree(d_opt_ids); dfree(d_nopts);
     dfree(d_queue); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);

@@ -211,6 +211,18 @@ def judge(ctx: Context, plan: Plan, counters, cycles, cand, out=None, ref=None, 
     return out
 
 
+def serve_query(ctx: Context, plan: Plan, mlp, counters, cycles, out, flag, tol: float = 0.1, band: float = 0.1,
+                cap: int = 16):
+    """One serving query in a single call (surrogate, top-n, threshold band,
+    judge, plain fallback; see sugg_serve_query): writes out = {"idx",
+    "score", "count"} and flag [K] (1 where the plain path answered)."""
+    plan.check_inputs(counters, cycles)
+    A.check(ctx.h, A.lib().sugg_serve_query(ctx.h, plan.h, mlp.h, _ptr(counters), _ptr(cycles), float(tol),
+                                            float(band), int(cap), _ptr(out["idx"]), _ptr(out["score"]),
+                                            _ptr(out["count"]), _ptr(flag), _stream()))
+    return flag
+
+
 def predict_allpaths(ctx: Context, plan: Plan, counters, cycles, rank: bool = True):
     """All-paths composed table [N] (the mean over every order of adding a
     subset's optimisations) and, with rank, its top-n per kernel:

@@ -2,8 +2,8 @@
 where it disagrees, answered by the plain per-optimisation models (Section 2's
 Tier 2 stays the reference; the surrogate is an accelerator in front of it).
 
-Per query of K kernels with B optimisations each (all work on one stream,
-every step a libsugg kernel):
+Per query of K kernels with B optimisations each (one library call,
+sugg_serve_query; all work on one stream, every step a libsugg kernel):
   1. z0 = standardised baseline counters of each kernel (Tier 1, baseline rows)
   2. the surrogate's table for all 2^B subsets, then its top-n above tau
   3. the threshold band: for a kernel whose list is shorter than n, the other
@@ -34,6 +34,8 @@ class Server:
                  band: float = 0.1, cap: int = 16, min_rows: int = 0):
         self.ctx, self.nets, self.n, self.tol, self.budget = ctx, nets, n, tol, budget_bytes
         self.band, self.cap, self.min_rows = band, cap, min_rows
+        for m in nets.values():   # the served parameters, packed once
+            m.freeze()
         self.plans = {}
         self.fallbacks = torch.zeros((), dtype=torch.int64, device=ctx.device)
         self.kernels_total = 0
@@ -63,19 +65,8 @@ class Server:
             G.suggest(self.ctx, plan, counters, cycles, out=out)
             self.kernels_plain += plan.K
             return None
-        K, n, dev = plan.K, self.n, self.ctx.device
-        tau = self.ctx.params["tau"]
-        z0 = G.load_features(self.ctx, plan, counters, cycles, baseline=True)
-        ys = mlp(z0)
-        seg = torch.arange(0, K + 1, dtype=torch.int64, device=dev) * (1 << B)
-        sc = torch.empty((K, n), dtype=ys.dtype, device=dev)
-        G.rank_suggest(self.ctx, ys.view(-1), seg, n=n, tau=tau, skip_head=1, out=(out["idx"], sc, out["count"]))
-        bc, br, flag = G.band_select(self.ctx, ys.view(-1), seg, out["idx"], out["count"], tau=tau,
-                                     band=self.band, cap=self.cap, skip_head=1)
-        G.judge(self.ctx, plan, counters, cycles, out["idx"], out=out["score"], ref=sc, tol=self.tol, flag=flag,
-                accumulate=True)
-        G.judge(self.ctx, plan, counters, cycles, bc, ref=br, tol=self.tol, flag=flag, accumulate=True)
-        G.suggest_subset(self.ctx, plan, counters, cycles, flag, out)
+        flag = torch.empty(plan.K, dtype=torch.int32, device=self.ctx.device)
+        G.serve_query(self.ctx, plan, mlp, counters, cycles, out, flag, tol=self.tol, band=self.band, cap=self.cap)
         self.fallbacks += flag.sum()
         return flag
 

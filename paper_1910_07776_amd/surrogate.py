@@ -113,6 +113,13 @@ class MLP:
                                                   x.shape[0], _ptr(y), _ptr(self.loss), _stream()))
         return self.loss
 
+    def freeze(self, params=None):
+        """Keep a copy of the parameters (default: the current ones) for
+        serving queries (``plain.serve_query``)."""
+        p = self.params if params is None else params
+        A.check(self.ctx.h, A.lib().sugg_mlp_freeze(self.ctx.h, self.h, _ptr(p), _stream()))
+        return self
+
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self.step += 1
         A.check(self.ctx.h, A.lib().sugg_mlp_adam(self.ctx.h, self.h, _ptr(self.params), _ptr(self.grads),
