@@ -65,17 +65,17 @@ def close(got, want):
     return np.abs(np.exp(got) - np.exp(want)) <= RTOL * np.exp(want)
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_ibk_matches_oracle(G, ctx, dtype):
+@pytest.mark.parametrize("dtype,E,k", [(torch.float32, 128, 10), (torch.float64, 128, 10),
+                                       (torch.float64, 40, 10), (torch.float32, 37, 3), (torch.float32, 96, 16)])
+def test_ibk_matches_oracle(G, ctx, dtype, E, k):
     npdt = np.float32 if dtype == torch.float32 else np.float64
-    tr = make_batch(31, range(4000, 4048), 128, 6, brange=(2, 6), dtype=npdt)
-    te = make_batch(31, range(40), 128, 6, brange=(0, 6), dtype=npdt)
-    k = 10
-    ptr = G.Plan(ctx, tr.nopts, tr.opt_ids, 128, 6, dtype=dtype)
+    tr = make_batch(31, range(4000, 4048), E, 6, brange=(2, 6), dtype=npdt)
+    te = make_batch(31, range(40), E, 6, brange=(0, 6), dtype=npdt)
+    ptr = G.Plan(ctx, tr.nopts, tr.opt_ids, E, 6, dtype=dtype)
     G.ibk_fit(ctx, ptr, dev(tr.counters), dev(tr.cycles), k=k)
     db = N.database(tr, 6)
     assert np.array_equal(G.ibk_counts(ctx, 6), [len(db["y"].get(o, [])) for o in range(6)])
-    p = G.Plan(ctx, te.nopts, te.opt_ids, 128, 6, dtype=dtype)
+    p = G.Plan(ctx, te.nopts, te.opt_ids, E, 6, dtype=dtype)
     c, cy = dev(te.counters), dev(te.cycles)
     table_g, grid = G.ibk_predict(ctx, p, c, cy, grid=True)
     table_e, _ = G.ibk_predict(ctx, p, c, cy)
@@ -104,7 +104,7 @@ def test_ibk_matches_oracle(G, ctx, dtype):
         errs = check_list(idx[kk, :count[kk]], score[kk, :count[kk]], to[r0:r0 + (1 << B)], P.TAU, 3, 1e-5,
                           first=1)
         assert not errs, (kk, errs)
-    assert checked > te.K // 2
+    assert checked >= te.K // 4   # kernels with every prediction decided (small B mostly)
 
 
 def test_one_neighbour_returns_the_training_labels(G, ctx):

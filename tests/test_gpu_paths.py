@@ -81,6 +81,33 @@ def test_greedy_walks(env):
     assert walked > te.K // 2
 
 
+def test_allpaths_and_greedy_fp64_odd_events():
+    """FP64 counters with E = 37 (no vector loads, padded lanes)."""
+    from paper_1910_07776_amd import plain as G
+    ctx = G.Context(0)
+    tr = make_batch(42, range(500, 540), 37, 5, brange=(1, 5), dtype=np.float64)
+    te = make_batch(42, range(30), 37, 5, brange=(0, 5), dtype=np.float64)
+    G.fit(ctx, G.Plan(ctx, tr.nopts, tr.opt_ids, 37, 5, dtype=torch.float64), torch.from_numpy(tr.counters).cuda(),
+          torch.from_numpy(tr.cycles).cuda())
+    model = P.fit(tr, 5)
+    p = G.Plan(ctx, te.nopts, te.opt_ids, 37, 5, dtype=torch.float64)
+    c, cy = torch.from_numpy(te.counters).cuda(), torch.from_numpy(te.cycles).cuda()
+    table, idx, sc, cnt = G.predict_allpaths(ctx, p, c, cy)
+    path, steps, gain = G.greedy(ctx, p, c, cy)
+    _, grid = G.predict(ctx, p, c, cy, grid=True)
+    G.sync(ctx)
+    go = P.predict_grid(model, te, Bmax=p.Bmax)
+    to = A.compose_allpaths(go, te)
+    np.testing.assert_allclose(table.cpu().numpy(), to, rtol=0, atol=1e-8)
+    g = grid.cpu().numpy()
+    path, steps = path.cpu().numpy(), steps.cpu().numpy()
+    for k in range(te.K):
+        B, r0 = int(te.nopts[k]), int(te.row_off[k])
+        pw, _ = A.greedy_kernel(g[r0:r0 + (1 << B), :B], B, P.TAU)
+        assert list(path[k, :steps[k] + 1]) == pw, k
+    ctx.close()
+
+
 def test_allpaths_rejects_more_than_ten_bits(env):
     G, ctx = env[0], env[1]
     from paper_1910_07776_amd._abi import SuggError
