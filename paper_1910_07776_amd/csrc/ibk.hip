@@ -6,7 +6,9 @@
 // pairs per v_mfma_f32_32x32x2_f32 sweep over the features.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
+#include <type_traits>
 #include <cmath>
 
 #include "common.hpp"
@@ -163,6 +165,10 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
   static_assert(F4 >= 1 && (kIbkTile * EP / 4) % 256 == 0, "tile staging shape");
   __shared__ __align__(16) float tz[kIbkTile * LS];
   __shared__ __align__(16) float tn[kIbkTile];
+  // per-lane queue of candidates that beat the list's last entry as of the
+  // latest merge (entry j of thread t at [j * 256 + t])
+  __shared__ float qd[kIbkQueue * 256];
+  __shared__ int qi[kIbkQueue * 256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 31, h = lane >> 5;
   const int tile = blockIdx.x / a.split, part = blockIdx.x - tile * a.split;
@@ -205,6 +211,16 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
     ld[j] = INFINITY;
     li[j] = INT_MAX;
   }
+
+  int qc = 0;
+  auto flush = [&]() {
+    for (int j = 0; j < qc; ++j) {
+      const float d = qd[j * 256 + tid];
+      const int sidx = qi[j * 256 + tid];
+      if (knn_better<KT>(d, sidx, ld[KT - 1], li[KT - 1])) knn_insert<KT>(ld, li, d, sidx);
+    }
+    qc = 0;
+  };
 
   float4 stg[F4];
   float stn = INFINITY;
@@ -267,14 +283,19 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
         const float4 t4 = tq[r >> 2];
         const float tnv = (r & 3) == 0 ? t4.x : (r & 3) == 1 ? t4.y : (r & 3) == 2 ? t4.z : t4.w;
         const float d = qn + tnv - 2.0f * (acc0[r] + acc1[r]);
-        const bool in = knn_better<KT>(d, t0 + i, ld[KT - 1], li[KT - 1]);
-        if (__ballot(in) != 0ull) {
-          if (in) knn_insert<KT>(ld, li, d, t0 + i);
+        if (knn_better<KT>(d, t0 + i, ld[KT - 1], li[KT - 1])) {
+          qd[qc * 256 + tid] = d;
+          qi[qc * 256 + tid] = t0 + i;
+          ++qc;
         }
       }
+      // merge the queues before one of them could overflow on the next tile:
+      // the wave pays for its fullest lane, once for all of them
+      if (__ballot(qc > kIbkQueue - 16) != 0ull) flush();
     }
     __syncthreads();   // the tile is consumed before the next store
   }
+  flush();
   // the two lanes of a query column saw disjoint samples: merge the partner's
   // list, then average the k nearest labels
   float od[KT];
@@ -370,6 +391,30 @@ hipError_t launch_knn_kt(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
     hipLaunchKernelGGL((ibk_merge_kernel<KT, T>), dim3((unsigned)((a.n_queries + 255) / 256)), dim3(256), 0, s, a);
   }
   return hipGetLastError();
+}
+
+// Sample shares per query tile: enough workgroups for one full round of the
+// resident ones (occupancy of this kernel instance x compute units).
+template <int EH, int KT>
+int split_kt(int n_tiles, int cus) {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(ibk_knn_kernel<EH, KT, float>),
+                                                   256, 0) != hipSuccess || per < 1)
+    per = 2;
+  return n_tiles > 0 ? std::min(8, std::max(1, (per * cus + n_tiles - 1) / n_tiles)) : 1;
+}
+
+int ibk_split(int Epad, int k, int n_tiles, int cus) {
+  auto by_k = [&](auto eh) -> int {
+    constexpr int EH = decltype(eh)::value;
+    if (k <= 4) return split_kt<EH, 4>(n_tiles, cus);
+    if (k <= 8) return split_kt<EH, 8>(n_tiles, cus);
+    if (k <= 12) return split_kt<EH, 12>(n_tiles, cus);
+    return split_kt<EH, 16>(n_tiles, cus);
+  };
+  if (Epad == 32) return by_k(std::integral_constant<int, 16>{});
+  if (Epad == 64) return by_k(std::integral_constant<int, 32>{});
+  return by_k(std::integral_constant<int, 64>{});
 }
 
 template <int EH, typename T>

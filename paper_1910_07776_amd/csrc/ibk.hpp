@@ -13,6 +13,7 @@ namespace sugg {
 constexpr int kIbkList = 16;       // neighbours kept per query (k <= 16)
 constexpr int kIbkQueries = 128;   // queries per workgroup (4 waves x 32)
 constexpr int kIbkTile = 32;       // database samples per staged tile
+constexpr int kIbkQueue = 20;      // queued candidates per lane (at least 16, one tile's)
 
 // Database of one fitted IBK model.  Samples of global optimisation o are
 // [off[o], off[o+1]), stored kernel by kernel, then by before-version S; each
@@ -89,6 +90,7 @@ hipError_t launch_ibk_labels(const T* cycles, const int32_t* before, const int32
                              double* y, hipStream_t s);
 template <typename T>
 hipError_t launch_ibk_knn(const IbkKnnArgs& a, int n_tiles, hipStream_t s);
+int ibk_split(int Epad, int k, int n_tiles, int cus);
 template <typename T>
 hipError_t launch_ibk_compose(const T* edges, const T* grid, int32_t grid_ld, const int64_t* row_off,
                               const int32_t* nopts, int32_t K, int32_t Bmax, T* table, int32_t* idx_out,

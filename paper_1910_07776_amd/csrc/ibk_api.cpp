@@ -236,12 +236,12 @@ int score_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, T* grid, T* t
   a.out = grid ? (void*)grid : w->edges;
   a.n_queries = q.n;
   a.n_tiles = q.n_tiles;
-  // enough workgroups for about four per compute unit: each query tile's
+  // enough workgroups for one round of resident ones: each query tile's
   // samples are split into shares whose neighbour lists are merged after
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
     cus = 256;
-  a.split = q.n_tiles > 0 ? std::min(8, std::max(1, (4 * cus + q.n_tiles - 1) / q.n_tiles)) : 1;
+  a.split = ibk_split(w->Epad, m->k, q.n_tiles, cus);
   a.part_d = nullptr;
   a.part_i = nullptr;
   if (a.split > 1) {
