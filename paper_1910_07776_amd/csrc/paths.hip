@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(kPathsThreads) allpaths_kernel(const PathsArgs
   // composition by levels of |S|
   for (int lev = 1; lev <= B; ++lev) {
     for (int S = tid; S < (1 << B); S += kPathsThreads) {
-      if (__popc((uint32_t)S) != lev) continue;
+      if (__popc((uint32_t)S) != (unsigned)lev) continue;
       T acc = T(0);
       for (int b = 0; b < B; ++b)
         if ((S >> b) & 1) {
