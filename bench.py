@@ -190,6 +190,8 @@ def main():
     by = path_bytes(nb_rows, E, K_BATCH, n)
     achieved = by / (ms_per_step / 1e3) / 1e9
     log(f"{ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s, wall {wall:.2f} s")
+    timing = pass_timing(G, ctx, plan, views, outs, g, stream)
+    accuracy = plain_accuracy(outs[0]["table"].cpu().numpy().astype(np.float64), test, K_BATCH)
 
     out = {
         "metric": METRIC, "value": value, "unit": "predictions/s", "n_gpus": 1, "steps": steps,
@@ -204,6 +206,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "path_kernel", "bytes_per_launch": by},
         "fit_ms": fit_ms,
+        "pass_timing": timing,
+        "accuracy": accuracy,
     }
 
     if not args.no_extra or args.ibk:
@@ -288,6 +292,58 @@ def paths_extra(G, ctx, dev, reps: int = 50):
         f"{res['mape_chain']:.4f}), greedy {res['greedy_us']:.1f} us, {res['greedy_mean_steps']:.2f} steps, "
         f"true gain {res['greedy_true_gain_mean']:.3f} of best {res['best_subset_true_gain_mean']:.3f}")
     return res
+
+
+def pass_timing(G, ctx, plan, views, outs, g, stream, reps: int = 100):
+    """Distribution of the graph replay (32 passes over distinct batches) in
+    us per pass, p10/p50/p90 of `reps` replays; a warm pass (the same 17 MB
+    batch again, resident in the last-level cache) and a cold single pass
+    (after writing 1 GB of other memory), each a median of 20 eager launches."""
+    import torch
+    e = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in e:
+        a.record(stream)
+        g.launch()
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) / N_BATCHES * 1e3 for a, b in e])
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    warm, cold = [], []
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device=views[0][0].device)   # 1 GiB
+    for i in range(22):
+        G.suggest(ctx, plan, *views[0], out=outs[0])            # warm: same batch again
+        a.record()
+        G.suggest(ctx, plan, *views[0], out=outs[0])
+        b.record()
+        torch.cuda.synchronize()
+        warm.append(a.elapsed_time(b) * 1e3)
+        scratch.fill_(float(i))                                 # evict: 1 GiB written
+        a.record()
+        G.suggest(ctx, plan, *views[1], out=outs[1])
+        b.record()
+        torch.cuda.synchronize()
+        cold.append(a.elapsed_time(b) * 1e3)
+    del scratch
+    G.sync(ctx)
+    return {"graph_us_per_pass_p10": float(np.percentile(per, 10)), "graph_us_per_pass_p50": float(np.median(per)),
+            "graph_us_per_pass_p90": float(np.percentile(per, 90)), "warm_single_us": float(np.median(warm[2:])),
+            "cold_single_us": float(np.median(cold[2:]))}
+
+
+def plain_accuracy(table, batch, K):
+    """Accuracy of the composed table against the generator's truth on the
+    first K kernels: speedup MAPE, sign accuracy of the composed predictions
+    (Table 3's measure: speedup or slowdown), and quantiles of actual /
+    expected speedup (Section 5's AC/EX)."""
+    rows = int(batch.row_off[K])
+    truth = np.asarray(batch.truth[:rows], dtype=np.float64)
+    keep = np.ones(rows, dtype=bool)
+    keep[np.asarray(batch.row_off[:K], dtype=np.int64)] = False
+    pred, tru = table[:rows][keep], truth[keep]
+    ratio = np.exp(tru - pred)
+    return {"mape": speedup_mape(table[:rows], truth, batch.row_off[:K + 1]),
+            "sign_accuracy": float(np.mean((pred > 0) == (tru > 0))),
+            "acex_p05_p50_p95": [float(q) for q in np.percentile(ratio, [5, 50, 95])]}
 
 
 def speedup_mape(table, truth, row_off):
