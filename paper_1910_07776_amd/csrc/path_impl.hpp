@@ -306,8 +306,10 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
       stage_model();
       staged = true;
     }
-    if (tid == 0) s_any = a.kmask ? 0 : 1;
-    __syncthreads();
+    if (a.kmask) {   // masked runs: the selection flag starts clear
+      if (tid == 0) s_any = 0;
+      __syncthreads();
+    }
     if (a.uni_B >= 0 && a.uni_ops) {
       // same ids everywhere: the records hold nothing the item does not know
       for (int i = tid; i < nk; i += nthr) {
@@ -384,8 +386,8 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
     };
 
     // two register buffers: the next rows load while the current ones compute
-    __syncthreads();
-    if (!s_any) {   // masked run: no selected kernel in this item
+    __syncthreads();   // weights, item metadata and the selection flag are visible
+    if (a.kmask && !s_any) {   // masked run: no selected kernel in this item
       it = dynamic ? s_next : a.n_items;
       __syncthreads();
       continue;
@@ -494,8 +496,9 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
         }
       }
     }
-    __syncthreads();
-    it = dynamic ? s_next : a.n_items;
+    if (!dynamic) break;   // one item per workgroup
+    __syncthreads();       // this item's LDS is no longer read
+    it = s_next;
     __syncthreads();
   }
   if (__ballot(bad) != 0 && lane == 0) atomicOr(a.status, (int)kStatusBadCounter);
