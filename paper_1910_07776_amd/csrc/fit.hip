@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kGramThreads) gram_kernel(const GramArgs a) {
   const GramWork w = a.work[blockIdx.x];
   const int tid = threadIdx.x;
   const int nb = (E + kBlk - 1) / kBlk;
-  const int nblocks = nb * nb;
+  const int nblocks = nb * (nb + 1) / 2;   // blocks on and below the diagonal (Z^T Z is symmetric)
   const int64_t stride = (int64_t)E * E + 2 * E + 2;
   double* out = a.partial + (int64_t)blockIdx.x * stride;
 
@@ -45,7 +45,14 @@ __global__ void __launch_bounds__(kGramThreads) gram_kernel(const GramArgs a) {
   for (int pass = 0; pass * kGramThreads < nblocks; ++pass) {
     const int blk = pass * kGramThreads + tid;
     const bool active = blk < nblocks;
-    const int bi = active ? blk / nb : 0, bj = active ? blk % nb : 0;
+    // lower-triangle block t = bi (bi + 1) / 2 + bj, bj <= bi
+    int bi = 0, bj = 0;
+    if (active) {
+      bi = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+      while (bi * (bi + 1) / 2 > blk) --bi;
+      while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+      bj = blk - bi * (bi + 1) / 2;
+    }
     double acc[kBlk][kBlk];
 #pragma unroll
     for (int i = 0; i < kBlk; ++i)
@@ -173,7 +180,7 @@ __global__ void __launch_bounds__(kSolveThreads) solve_kernel(const SolveArgs a,
   for (int idx = tid; idx < n1 * n1; idx += kSolveThreads) {
     const int i = idx / n1, j = idx - i * n1;
     int64_t off;
-    if (i < E && j < E) off = (int64_t)i * E + j;
+    if (i < E && j < E) off = i >= j ? (int64_t)i * E + j : (int64_t)j * E + i;   // lower triangle
     else if (i < E) off = (int64_t)E * E + i;          // column sums
     else if (j < E) off = (int64_t)E * E + j;
     else off = (int64_t)E * E + 2 * E + 1;             // sample count
