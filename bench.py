@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--ibk", action="store_true", help="also run the IBK section with --no-extra")
     ap.add_argument("--paths", action="store_true", help="also run the all-paths/greedy section with --no-extra")
     ap.add_argument("--serving", action="store_true", help="also run the serving section with --no-extra")
+    ap.add_argument("--surrogate", action="store_true", help="also run the surrogate section with --no-extra")
     ap.add_argument("--launch", default=None,
                     help="WAVES,UNROLL: force the scoring kernel's launch shape (no tuning)")
     ap.add_argument("--retune", action="store_true",
@@ -216,6 +217,7 @@ def main():
         out["paths"] = paths_extra(G, ctx, dev)
     if not args.no_extra:
         out["ragged_16384"] = ragged_extra(G, ctx, dev)
+    if not args.no_extra or args.surrogate:
         out["surrogate"] = surrogate_extra(G, dev)
     if not args.no_extra or args.serving:
         out["serving"] = serving_extra(G, dev)

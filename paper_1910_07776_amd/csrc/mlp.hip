@@ -26,6 +26,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kKStep = 32;    // K per LDS stage (two MFMAs of K 16)
+constexpr int kKVec = kKStep / 32;   // 8-element vectors per thread and tile row per stage
 constexpr int kLdsRow = kKStep + 8;   // padded LDS row (bf16 elements)
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
@@ -61,7 +62,8 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs g) {
   const int split = blockIdx.z;
   const int kb = split * g.k_per_split;
   const int ke = min(g.K, kb + g.k_per_split);
-  // staging: thread t moves 8 elements of tile rows t/4 + 64 i, K offset (t%4)*8
+  // staging: thread t moves 8 elements at K offsets (t%4)*8 + 32 v of tile
+  // rows t/4 + 64 i
   const int lr = tid >> 2, lk = (tid & 3) * 8;
 
   floatx16 acc[TM][TN];
@@ -72,24 +74,30 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
-  bf16x8 ra[TM], rb[TN];
+  bf16x8 ra[TM][kKVec], rb[TN][kKVec];
+  auto fetch = [&](int k0) {
 #pragma unroll
-  for (int i = 0; i < TM; ++i) ra[i] = load8(g.A, g.lda, m0 + lr + 64 * i, g.M, kb + lk, ke);
+    for (int v = 0; v < kKVec; ++v) {
 #pragma unroll
-  for (int i = 0; i < TN; ++i) rb[i] = load8(g.Bt, g.ldb, n0 + lr + 64 * i, g.N, kb + lk, ke);
+      for (int i = 0; i < TM; ++i) ra[i][v] = load8(g.A, g.lda, m0 + lr + 64 * i, g.M, k0 + lk + 32 * v, ke);
+#pragma unroll
+      for (int i = 0; i < TN; ++i) rb[i][v] = load8(g.Bt, g.ldb, n0 + lr + 64 * i, g.N, k0 + lk + 32 * v, ke);
+    }
+  };
+  fetch(kb);
   int buf = 0;
   for (int k0 = kb; k0 < ke; k0 += kKStep) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i) *reinterpret_cast<bf16x8*>(&As[buf][(lr + 64 * i) * kLdsRow + lk]) = ra[i];
+    for (int v = 0; v < kKVec; ++v) {
 #pragma unroll
-    for (int i = 0; i < TN; ++i) *reinterpret_cast<bf16x8*>(&Bs[buf][(lr + 64 * i) * kLdsRow + lk]) = rb[i];
-    __syncthreads();
-    if (k0 + kKStep < ke) {
+      for (int i = 0; i < TM; ++i)
+        *reinterpret_cast<bf16x8*>(&As[buf][(lr + 64 * i) * kLdsRow + lk + 32 * v]) = ra[i][v];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) ra[i] = load8(g.A, g.lda, m0 + lr + 64 * i, g.M, k0 + kKStep + lk, ke);
-#pragma unroll
-      for (int i = 0; i < TN; ++i) rb[i] = load8(g.Bt, g.ldb, n0 + lr + 64 * i, g.N, k0 + kKStep + lk, ke);
+      for (int i = 0; i < TN; ++i)
+        *reinterpret_cast<bf16x8*>(&Bs[buf][(lr + 64 * i) * kLdsRow + lk + 32 * v]) = rb[i][v];
     }
+    __syncthreads();
+    if (k0 + kKStep < ke) fetch(k0 + kKStep);
 #pragma unroll
     for (int s = 0; s < kKStep; s += 16) {
       const int kk = s + (lane >> 5) * 8;
