@@ -93,6 +93,7 @@ def main():
     ap.add_argument("--paths", action="store_true", help="also run the all-paths/greedy section with --no-extra")
     ap.add_argument("--serving", action="store_true", help="also run the serving section with --no-extra")
     ap.add_argument("--surrogate", action="store_true", help="also run the surrogate section with --no-extra")
+    ap.add_argument("--m5p", action="store_true", help="also run the M5P model-tree section with --no-extra")
     ap.add_argument("--launch", default=None,
                     help="WAVES,UNROLL: force the scoring kernel's launch shape (no tuning)")
     ap.add_argument("--retune", action="store_true",
@@ -215,6 +216,8 @@ def main():
         out["ibk"] = ibk_extra(G, dev, train, test)
     if not args.no_extra or args.paths:
         out["paths"] = paths_extra(G, ctx, dev)
+    if not args.no_extra or args.m5p:
+        out["m5p"] = m5p_extra(G, dev, train, test, no_cpu=args.no_cpu)
     if not args.no_extra:
         out["ragged_16384"] = ragged_extra(G, ctx, dev)
     if not args.no_extra or args.surrogate:
@@ -397,6 +400,79 @@ def ibk_extra(G, dev, train, test, reps: int = 10):
             "predictions_per_s": queries / (ms / 1e3), "suggestions_per_s": plan.K / (ms / 1e3),
             "distance_tflops": tf, "mfma_fp32_frac": tf / 157.3, "fit_s_host_incl": fit_s,
             "mape_ibk": mape_ibk, "mape_linear": mape_lin}
+
+
+def m5p_extra(G, dev, train, test, reps: int = 50, no_cpu: bool = False):
+    """The paper's model-tree Tier 2 model (M5P) on the headline shape: trees
+    induced from 512 training kernels (16,384 pairs per optimisation), then
+    scoring 512 kernels x 64 versions (32,256 chain-edge tree walks and leaf
+    models, composition, top-3)."""
+    import torch
+    from synthgen import make_batch
+    ctx = G.Context(0)
+    ptr = G.Plan(ctx, train.nopts, train.opt_ids, E, D)
+    tc, tcy = torch.from_numpy(train.counters).to(dev), torch.from_numpy(train.cycles).to(dev)
+    t0 = time.perf_counter()
+    G.m5p_fit(ctx, ptr, tc, tcy)
+    fit_s = time.perf_counter() - t0
+    trees = [G.m5p_tree(ctx, o) for o in range(D)]
+    nodes = int(sum(len(t["feat"]) for t in trees))
+    leaves = int(sum(int((t["feat"] < 0).sum()) for t in trees))
+    one = make_batch(1910, range(K_BATCH), E, D)
+    plan = G.Plan(ctx, one.nopts, one.opt_ids, E, D)
+    c, cy = torch.from_numpy(one.counters).to(dev), torch.from_numpy(one.cycles).to(dev)
+    res = G.m5p_suggest(ctx, plan, c, cy)
+    G.sync(ctx)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        res = G.m5p_suggest(ctx, plan, c, cy)
+    e1.record()
+    torch.cuda.synchronize()
+    G.sync(ctx)
+    ms = e0.elapsed_time(e1) / reps
+    preds = int(plan.N - plan.K)
+    tab = res[3].cpu().numpy().astype(np.float64)
+    mape = speedup_mape(tab, one.truth, one.row_off)
+    # algorithmic bytes: the counter stream and the outputs, the edge buffer
+    # written and read back, the model (nodes, thresholds, leaf rows) once
+    model_bytes = nodes * (16 + 4) + leaves * (128 + 1) * 4
+    by = path_bytes(int(plan.N), E, K_BATCH, 3) + 2 * int(plan.N) * 4 + model_bytes
+    gbs = by / (ms / 1e3) / 1e9
+    log(f"m5p: {nodes} nodes, {leaves} leaves over {D} trees, fit {fit_s:.2f} s; {ms * 1e3:.1f} us/pass "
+        f"({gbs:.0f} GB/s), MAPE {mape:.4f}")
+    out = {"trees": D, "nodes": nodes, "leaves": leaves, "max_depth": int(max(_depth(t) for t in trees)),
+           "fit_s_host_incl": fit_s, "us_per_pass": ms * 1e3, "predictions_per_s": preds / (ms / 1e3),
+           "suggestions_per_s": plan.K / (ms / 1e3), "bytes_per_pass": by, "hbm_gbs": gbs,
+           "hbm_frac": gbs / HBM_PEAK_GBS, "mape_m5p": mape}
+    ctx.close()
+    if not no_cpu:
+        from oracle import m5p as M
+        from oracle import plain as P
+        sub = P.SubBatch(train, range(128))
+        model = M.fit(sub, D)
+        z = P.standardize(P.features(one.counters, one.cycles), model["mu"], model["sigma"])
+        n, r, t0 = 0, 0, time.perf_counter()
+        while time.perf_counter() - t0 < 10.0:
+            S = r % 64
+            for b in range(D):
+                if not (S >> b) & 1:
+                    M.predict_one(model["trees"][b], z[r])
+                    n += 1
+            r = (r + 1) % int(plan.N)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": n / dt, "unit": "predictions/s", "cores": 1, "kind": "oracle",
+                             "sample": f"FP64 numpy oracle tree walks with smoothing, {n} predictions in {dt:.1f} s, "
+                                       "trees induced from the first 128 training kernels"}
+    return out
+
+
+def _depth(t):
+    d = np.zeros(len(t["feat"]), dtype=np.int64)
+    for i, f in enumerate(t["feat"]):
+        if f >= 0:
+            d[t["left"][i]] = d[t["right"][i]] = d[i] + 1
+    return int(d.max())
 
 
 def ragged_extra(G, ctx, dev):

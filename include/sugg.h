@@ -296,6 +296,48 @@ SUGG_API int32_t sugg_ibk_suggest(sugg_ctx* ctx, const sugg_plan* plan, const vo
                                   void* table_out, int32_t* idx_out, void* score_out, int32_t* count_out,
                                   hipStream_t stream);
 
+/* ---- Model-tree Tier 2 model (M5P) ------------------------------------------
+ * Section 3.4's model tree, after Quinlan's M5: per global id a regression
+ * tree over the standardised Tier 1 features of the before versions, grown
+ * by standard-deviation reduction (binary splits z_j <= t, t halfway between
+ * adjacent distinct training values; no split of a node with fewer than
+ * 2 * min_leaf pairs or with label sd at most 5 % of the root's; each side
+ * keeps min_leaf pairs); least-squares linear models with an intercept at
+ * every node on the features tested in its subtree; bottom-up pruning by the
+ * M5 error estimate (mean |residual| * (n + v) / (n - v)); smoothing from
+ * the leaf up, p <- (n_c p + smooth_k q) / (n_c + smooth_k), folded into one
+ * linear model per leaf.  Ties: split gains within 1e-9 of the root's label
+ * sd are equal (first feature, then lowest threshold wins); a pruning
+ * comparison within the same margin prunes.  The M5P model lives beside the
+ * linear and IBK models in the context.  E <= 256.
+ *
+ * sugg_m5p_fit: FP64 column statistics and standardised features of the
+ *   training rows on the GPU, then the trees on the host (one thread per id,
+ *   up to 16), uploaded.  Synchronous; replaces a previous M5P model.
+ *   min_leaf >= 1 (the paper's tool, Weka's M5P, uses 4), smooth_k >= 0 (15;
+ *   0 disables smoothing).  SUGG_E_BAD_COUNTER if a training counter or
+ *   cycle count is not positive and finite; SUGG_E_BUDGET above 2^22 pairs
+ *   per id.
+ * sugg_m5p_tree: the pruned tree of global id opt, preorder (a node, its left
+ *   subtree, its right subtree), into host arrays of cap entries: feat (-1 at
+ *   a leaf), thr (go left when z[feat] <= thr; NaN at a leaf), left and right
+ *   child (-1 at a leaf), count (training pairs reaching the node);
+ *   *n_nodes receives the node count (call with cap = 0 to size the arrays).
+ * sugg_m5p_predict / sugg_m5p_suggest: as sugg_predict / sugg_suggest with
+ *   the M5P model for Tier 2 (same layouts); every id of the plan needs a
+ *   tree (else SUGG_E_UNTRAINED_OPT).  Tests compare in the plan dtype: FP32
+ *   plans walk the trees on FP32 features.  A plan's first M5P call builds
+ *   its row tiles and workspace (not inside a graph capture). */
+SUGG_API int32_t sugg_m5p_fit(sugg_ctx* ctx, const sugg_plan* train, const void* counters, const void* cycles,
+                              int32_t min_leaf, double smooth_k, hipStream_t stream);
+SUGG_API int32_t sugg_m5p_tree(sugg_ctx* ctx, int32_t opt, int32_t cap, int32_t* feat, double* thr, int32_t* left,
+                               int32_t* right, int64_t* count, int32_t* n_nodes);
+SUGG_API int32_t sugg_m5p_predict(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                                  void* grid_out, void* table_out, hipStream_t stream);
+SUGG_API int32_t sugg_m5p_suggest(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                                  void* table_out, int32_t* idx_out, void* score_out, int32_t* count_out,
+                                  hipStream_t stream);
+
 /* ---- Learned surrogate ------------------------------------------------------
  * An extension of the paper's Tier 2 (which predicts one optimisation at a
  * time): an MLP in -> hidden -> hidden -> out with exact-erf GELU after both

@@ -74,6 +74,10 @@ SIGNATURES = {
     "sugg_ibk_counts": (_I32, [_P, _P, _I32]),
     "sugg_ibk_predict": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
     "sugg_ibk_suggest": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "sugg_m5p_fit": (_I32, [_P, _P, _P, _P, _I32, C.c_double, _P]),
+    "sugg_m5p_tree": (_I32, [_P, _I32, _I32, _P, _P, _P, _P, _P, _PI32]),
+    "sugg_m5p_predict": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
+    "sugg_m5p_suggest": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "sugg_capture_begin": (_I32, [_P, _P]),
     "sugg_capture_end": (_I32, [_P, _P, C.POINTER(_P)]),
     "sugg_graph_launch": (_I32, [_P, _P, _P]),

@@ -400,6 +400,7 @@ void sugg_destroy(sugg_ctx* ctx) {
   (void)device_ok(ctx);
   ctx->free_model();
   ibk_model_free(ctx->ibk);
+  m5p_model_free(ctx->m5p);
   dfree(ctx->d_status);
   delete ctx;
 }

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "ibk.hpp"
+#include "m5p.hpp"
 #include "kernels.hpp"
 #include "sugg.h"
 
@@ -37,6 +38,8 @@ struct sugg_ctx {
   std::vector<int64_t> counts;
   // instance-based model (separate from the linear one)
   IbkModel* ibk = nullptr;
+  // model-tree (M5P) model (separate from the linear one)
+  M5pModel* m5p = nullptr;
   int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;

@@ -1,0 +1,109 @@
+// Internal: the model-tree Tier 2 learner (M5P, Section 3.4, after Quinlan's
+// M5): per optimisation a regression tree grown by standard-deviation
+// reduction, linear models at the nodes on the features tested below them,
+// pruned bottom-up by the M5 error estimate and smoothed towards the root.
+//
+// The tree is induced on the host from FP64 features computed on the GPU; a
+// prediction walks it on the GPU and evaluates one linear model per leaf,
+// into which the smoothing along the leaf's path has been folded (a chain of
+// convex combinations of linear models is a linear model).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace sugg {
+
+// One optimisation's pruned tree on the host, in preorder (a node, then its
+// left subtree, then its right subtree).
+struct M5pHostTree {
+  std::vector<int32_t> feat;    // tested feature; -1 at a leaf
+  std::vector<double> thr;      // go left when z[feat] <= thr
+  std::vector<int32_t> left, right;   // child nodes; -1 at a leaf
+  std::vector<int32_t> leaf;    // leaf ordinal at a leaf, -1 inside
+  std::vector<int64_t> count;   // training cases reaching the node
+  std::vector<double> lw;       // [leaves, E + 1]: smoothed leaf models, intercept last
+  int leaves = 0;
+  int depth = 0;                // longest root-to-leaf path (edges)
+};
+
+struct M5pParams {
+  int min_leaf = 4;             // fewest training cases on each side of a split
+  double sd_frac = 0.05;        // no split below this fraction of the root's label sd
+  double smooth_k = 15.0;       // smoothing constant
+  double tie = 1e-9;            // ties, relative to the root's label sd
+};
+
+// Induce one tree.  Z: FP64 standardised rows with row stride ldz; rows[i]:
+// the row of training case i; y[i]: its label.  Cases are numbered in the
+// order given (ties between equal feature values follow it).
+M5pHostTree m5p_induce(const double* Z, int64_t ldz, const int32_t* rows, const double* y, int64_t n, int E,
+                       const M5pParams& prm);
+
+struct M5pNode {
+  int32_t feat, left, right, leaf;
+};
+
+// Device form of a fitted model: every optimisation's tree concatenated.
+struct M5pModel {
+  int E = 0, D = 0, ldl = 0, max_depth = 0;
+  M5pParams prm;
+  std::vector<M5pHostTree> trees;     // per global id (empty when untrained)
+  std::vector<int32_t> root;          // per global id: first node, -1 when untrained
+  int32_t* d_root = nullptr;
+  M5pNode* nodes = nullptr;
+  float* thr32 = nullptr;
+  double* thr64 = nullptr;
+  float* lw32 = nullptr;              // [leaves, ldl], columns >= E zero
+  double* lw64 = nullptr;
+  float* lb32 = nullptr;              // [leaves] intercepts
+  double* lb64 = nullptr;
+  float *mu32 = nullptr, *isg32 = nullptr;    // column constants for the features
+  double *mu64 = nullptr, *isg64 = nullptr;
+};
+
+struct M5pPlan {
+  int32_t* tiles = nullptr;           // [n_tiles, 2]: kernel, first version
+  int n_tiles = 0;
+  void* edges = nullptr;              // [N] plan dtype
+};
+
+template <typename T>
+struct M5pArgs {
+  const T* counters;
+  const T* cycles;
+  const int64_t* row_off;
+  const int32_t* nopts;
+  const int64_t* opt_off;
+  const int32_t* opt_ids;
+  const int32_t* tiles;
+  const T* mu;
+  const T* isg;
+  const int32_t* root;
+  const M5pNode* nodes;
+  const T* thr;
+  const T* lw;
+  const T* lb;
+  int32_t ldl;
+  int32_t max_depth;
+  int32_t E;
+  int32_t Bmax;
+  T* grid;      // grid mode when non-null: every b not in S
+  T* edges;     // else chain edges: e[row(k, S | 2^b)] for b above the top bit of S
+  int32_t* status;
+};
+
+constexpr int kM5pRows = 16;          // versions per workgroup (16 lanes each)
+
+template <typename T>
+hipError_t launch_m5p(const M5pArgs<T>& a, int n_tiles, hipStream_t s);
+
+}  // namespace sugg
+
+using sugg::M5pModel;
+using sugg::M5pPlan;
+
+void m5p_model_free(M5pModel*& m);
+void m5p_plan_free(M5pPlan*& p);

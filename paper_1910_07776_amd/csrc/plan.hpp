@@ -71,11 +71,13 @@ struct sugg_plan {
   int n_gwork = 0;
   // instance-based (IBK) scoring workspace, built on its first use
   IbkPlan* ibk = nullptr;
+  M5pPlan* m5p = nullptr;
   ServeWs* serve = nullptr;
 
   ~sugg_plan() {
     delete serve;
     ibk_plan_free(ibk);
+    m5p_plan_free(m5p);
     dfree(d_items); dfree(d_recs); dfree(d_row_off); dfree(d_opt_off); dfree(d_opt_ids); dfree(d_nopts);
     dfree(d_queue); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
     dfree(d_solveA); dfree(d_reduced); dfree(d_gwork); dfree(d_pair_base); dfree(d_pair_row0); dfree(d_pair_bit);

@@ -289,6 +289,52 @@ def ibk_suggest(ctx: Context, plan: Plan, counters, cycles, table: bool = True, 
     return out["idx"], out["score"], out["count"], out["table"]
 
 
+def m5p_fit(ctx: Context, plan: Plan, counters, cycles, min_leaf: int = 4, smooth_k: float = 15.0):
+    """Induce an M5P model tree per global id from the plan's before/after
+    pairs; replaces the context's M5P model.  Synchronous."""
+    plan.check_inputs(counters, cycles)
+    A.check(ctx.h, A.lib().sugg_m5p_fit(ctx.h, plan.h, _ptr(counters), _ptr(cycles), int(min_leaf),
+                                        float(smooth_k), _stream()))
+
+
+def m5p_tree(ctx: Context, opt: int) -> dict:
+    """The pruned tree of global id ``opt`` in preorder: feat (-1 at a leaf),
+    thr (NaN at a leaf), left, right (-1 at a leaf), count."""
+    n = C.c_int32(0)
+    A.check(ctx.h, A.lib().sugg_m5p_tree(ctx.h, int(opt), 0, None, None, None, None, None, C.byref(n)))
+    out = {"feat": np.zeros(n.value, np.int32), "thr": np.zeros(n.value, np.float64),
+           "left": np.zeros(n.value, np.int32), "right": np.zeros(n.value, np.int32),
+           "count": np.zeros(n.value, np.int64)}
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    A.check(ctx.h, A.lib().sugg_m5p_tree(ctx.h, int(opt), n.value, vp(out["feat"]), vp(out["thr"]), vp(out["left"]),
+                                         vp(out["right"]), vp(out["count"]), C.byref(n)))
+    return out
+
+
+def m5p_predict(ctx: Context, plan: Plan, counters, cycles, grid: bool = False):
+    """Returns (table [N], grid [N, Bmax] or None) with M5P as Tier 2."""
+    plan.check_inputs(counters, cycles)
+    table = torch.empty(plan.N, dtype=plan.dtype, device=ctx.device)
+    g = torch.empty((plan.N, plan.Bmax), dtype=plan.dtype, device=ctx.device) if grid else None
+    A.check(ctx.h, A.lib().sugg_m5p_predict(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(g), _ptr(table),
+                                            _stream()))
+    return table, g
+
+
+def m5p_suggest(ctx: Context, plan: Plan, counters, cycles, table: bool = True, out=None):
+    """``suggest`` with M5P as Tier 2; returns (idx, score, count, table or None)."""
+    plan.check_inputs(counters, cycles)
+    n = ctx.params["n_suggest"]
+    if out is None:
+        out = {"idx": torch.empty((plan.K, n), dtype=torch.int32, device=ctx.device),
+               "score": torch.empty((plan.K, n), dtype=plan.dtype, device=ctx.device),
+               "count": torch.empty(plan.K, dtype=torch.int32, device=ctx.device),
+               "table": torch.empty(plan.N, dtype=plan.dtype, device=ctx.device) if table else None}
+    A.check(ctx.h, A.lib().sugg_m5p_suggest(ctx.h, plan.h, _ptr(counters), _ptr(cycles), _ptr(out["table"]),
+                                            _ptr(out["idx"]), _ptr(out["score"]), _ptr(out["count"]), _stream()))
+    return out["idx"], out["score"], out["count"], out["table"]
+
+
 def rank_suggest(ctx: Context, scores, seg_off, n: int = 3, tau: float = TAU, skip_head: int = 0, out=None):
     """Tier 3 over segments scores[seg_off[i]:seg_off[i+1]]; returns (idx, score, count),
     written into ``out`` = (idx [nseg, n], score [nseg, n], count [nseg]) when given."""
