@@ -42,20 +42,28 @@ struct M5pParams {
 M5pHostTree m5p_induce(const double* Z, int64_t ldz, const int32_t* rows, const double* y, int64_t n, int E,
                        const M5pParams& prm);
 
-struct M5pNode {
-  int32_t feat, left, right, leaf;
+// Device form of a tree: blocks of three levels in one 128-byte line, so one
+// load decides three tests of a walk.  Positions 0..6 hold a node and its
+// descendants down two levels (children of position p at 2p+1, 2p+2); a
+// leaf position has feat = -1 and its leaf ordinal in thr's bits.  The eight
+// exits below positions 3..6 name the next block (>= 0) or a leaf (-1 - id).
+template <typename T>
+struct alignas(128) M5pBlock {
+  int16_t feat[8];
+  int32_t exit[8];
+  T thr[8];
 };
 
 // Device form of a fitted model: every optimisation's tree concatenated.
 struct M5pModel {
-  int E = 0, D = 0, ldl = 0, max_depth = 0;
+  int E = 0, D = 0, ldl = 0;
   M5pParams prm;
   std::vector<M5pHostTree> trees;     // per global id (empty when untrained)
-  std::vector<int32_t> root;          // per global id: first node, -1 when untrained
+  std::vector<int32_t> root;          // per global id: first block, -1 when untrained
   int32_t* d_root = nullptr;
-  M5pNode* nodes = nullptr;
-  float* thr32 = nullptr;
-  double* thr64 = nullptr;
+  M5pBlock<float>* blk32 = nullptr;
+  M5pBlock<double>* blk64 = nullptr;
+  int max_blocks = 0;                 // longest chain of blocks of a walk
   float* lw32 = nullptr;              // [leaves, ldl], columns >= E zero
   double* lw64 = nullptr;
   float* lb32 = nullptr;              // [leaves] intercepts
@@ -82,12 +90,11 @@ struct M5pArgs {
   const T* mu;
   const T* isg;
   const int32_t* root;
-  const M5pNode* nodes;
-  const T* thr;
+  const M5pBlock<T>* blocks;
   const T* lw;
   const T* lb;
   int32_t ldl;
-  int32_t max_depth;
+  int32_t max_blocks;
   int32_t E;
   int32_t Bmax;
   T* grid;      // grid mode when non-null: every b not in S
@@ -99,6 +106,12 @@ constexpr int kM5pRows = 16;          // versions per workgroup (16 lanes each)
 
 template <typename T>
 hipError_t launch_m5p(const M5pArgs<T>& a, int n_tiles, hipStream_t s);
+// Kernels of at most 64 versions, chain edges only: the whole pass (edges,
+// composition, top-n) in one launch, one workgroup per kernel.
+constexpr int kM5pSmallB = 6;
+template <typename T>
+hipError_t launch_m5p_small(const M5pArgs<T>& a, int K, T* table, int32_t* idx, T* score, int32_t* count, int n,
+                            T tau, hipStream_t s);
 
 }  // namespace sugg
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstring>
 #include <new>
 #include <thread>
 #include <vector>
@@ -20,7 +21,7 @@ using namespace sugg;
 
 void m5p_model_free(M5pModel*& m) {
   if (!m) return;
-  dfree(m->d_root); dfree(m->nodes); dfree(m->thr32); dfree(m->thr64); dfree(m->lw32); dfree(m->lw64);
+  dfree(m->d_root); dfree(m->blk32); dfree(m->blk64); dfree(m->lw32); dfree(m->lw64);
   dfree(m->lb32); dfree(m->lb64); dfree(m->mu32); dfree(m->isg32); dfree(m->mu64); dfree(m->isg64);
   delete m;
   m = nullptr;
@@ -97,31 +98,95 @@ int induce_all(sugg_ctx* ctx, const sugg_plan* p, const std::vector<double>& z, 
   return SUGG_OK;
 }
 
+// Leaf ordinal stored in a threshold slot's bits (read back the same way).
+void put_leaf(float& slot, int32_t id) { std::memcpy(&slot, &id, sizeof id); }
+void put_leaf(double& slot, int32_t id) {
+  const int64_t v = id;
+  std::memcpy(&slot, &v, sizeof v);
+}
+
+// Pack one tree into three-level blocks (see M5pBlock), breadth first from
+// the root; leaf ordinals offset by leaf_base, block indices by the blocks
+// already present.  Returns the root block; *chain receives the longest run
+// of blocks a walk loads.
+int pack_tree(const M5pHostTree& t, int leaf_base, std::vector<M5pBlock<float>>& b32,
+              std::vector<M5pBlock<double>>& b64, int* chain) {
+  struct Todo {
+    int node, block, level;
+  };
+  auto fresh = [&]() {
+    M5pBlock<float> f{};
+    M5pBlock<double> d{};
+    for (int p = 0; p < 8; ++p) {
+      f.feat[p] = d.feat[p] = -1;
+      f.exit[p] = d.exit[p] = -1;
+      put_leaf(f.thr[p], leaf_base);   // unreachable slots name a valid leaf
+      put_leaf(d.thr[p], leaf_base);
+    }
+    b32.push_back(f);
+    b64.push_back(d);
+    return (int)b32.size() - 1;
+  };
+  std::vector<Todo> todo{{0, fresh(), 1}};
+  *chain = 1;
+  for (size_t q = 0; q < todo.size(); ++q) {
+    const Todo td = todo[q];
+    *chain = std::max(*chain, td.level);
+    int pos[7];
+    std::fill(pos, pos + 7, -1);
+    pos[0] = td.node;
+    for (int p = 0; p < 7; ++p) {
+      const int m = pos[p];
+      if (m < 0) continue;
+      M5pBlock<float>& f = b32[td.block];
+      M5pBlock<double>& d = b64[td.block];
+      if (t.feat[m] < 0) {
+        put_leaf(f.thr[p], leaf_base + t.leaf[m]);
+        put_leaf(d.thr[p], leaf_base + t.leaf[m]);
+        continue;
+      }
+      f.feat[p] = d.feat[p] = (int16_t)t.feat[m];
+      f.thr[p] = (float)t.thr[m];
+      d.thr[p] = t.thr[m];
+      if (p < 3) {
+        pos[2 * p + 1] = t.left[m];
+        pos[2 * p + 2] = t.right[m];
+        continue;
+      }
+      const int kids[2] = {t.left[m], t.right[m]};
+      for (int side = 0; side < 2; ++side) {
+        const int c = kids[side];
+        int ref;
+        if (t.feat[c] < 0) {
+          ref = -1 - (leaf_base + t.leaf[c]);
+        } else {
+          ref = fresh();
+          todo.push_back({c, ref, td.level + 1});
+        }
+        b32[td.block].exit[2 * (p - 3) + side] = ref;
+        b64[td.block].exit[2 * (p - 3) + side] = ref;
+      }
+    }
+  }
+  return todo[0].block;
+}
+
 // Concatenate the trees into the device arrays.
 int upload_model(sugg_ctx* ctx, M5pModel* m) {
   const int E = m->E, ldl = m->ldl;
-  std::vector<M5pNode> nodes;
-  std::vector<float> thr32, lw32, lb32;
-  std::vector<double> thr64, lw64, lb64;
+  std::vector<M5pBlock<float>> b32;
+  std::vector<M5pBlock<double>> b64;
+  std::vector<float> lw32, lb32;
+  std::vector<double> lw64, lb64;
   m->root.assign(m->D, -1);
-  m->max_depth = 0;
+  m->max_blocks = 1;
   int leaf_base = 0;
   for (int o = 0; o < m->D; ++o) {
     const M5pHostTree& t = m->trees[o];
     if (t.feat.empty()) continue;
-    const int base = (int)nodes.size();
-    m->root[o] = base;
-    m->max_depth = std::max(m->max_depth, t.depth);
-    for (size_t i = 0; i < t.feat.size(); ++i) {
-      M5pNode nd;
-      nd.feat = t.feat[i];
-      nd.left = t.left[i] >= 0 ? base + t.left[i] : -1;
-      nd.right = t.right[i] >= 0 ? base + t.right[i] : -1;
-      nd.leaf = t.leaf[i] >= 0 ? leaf_base + t.leaf[i] : -1;
-      nodes.push_back(nd);
-      thr64.push_back(t.thr[i]);
-      thr32.push_back((float)t.thr[i]);
-    }
+    int chain = 1;
+    m->root[o] = pack_tree(t, leaf_base, b32, b64, &chain);
+    m->max_blocks = std::max(m->max_blocks, chain);
     for (int l = 0; l < t.leaves; ++l) {
       const double* w = t.lw.data() + (size_t)l * (E + 1);
       for (int j = 0; j < ldl; ++j) {
@@ -135,9 +200,8 @@ int upload_model(sugg_ctx* ctx, M5pModel* m) {
     leaf_base += t.leaves;
   }
   hipError_t e = put(m->d_root, m->root);
-  if (e == hipSuccess) e = put(m->nodes, nodes);
-  if (e == hipSuccess) e = put(m->thr32, thr32);
-  if (e == hipSuccess) e = put(m->thr64, thr64);
+  if (e == hipSuccess) e = put(m->blk32, b32);
+  if (e == hipSuccess) e = put(m->blk64, b64);
   if (e == hipSuccess) e = put(m->lw32, lw32);
   if (e == hipSuccess) e = put(m->lw64, lw64);
   if (e == hipSuccess) e = put(m->lb32, lb32);
@@ -261,18 +325,21 @@ int score_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, T* grid, T* t
   a.mu = (const T*)(f32 ? (const void*)m->mu32 : (const void*)m->mu64);
   a.isg = (const T*)(f32 ? (const void*)m->isg32 : (const void*)m->isg64);
   a.root = m->d_root;
-  a.nodes = m->nodes;
-  a.thr = (const T*)(f32 ? (const void*)m->thr32 : (const void*)m->thr64);
+  a.blocks = (const M5pBlock<T>*)(f32 ? (const void*)m->blk32 : (const void*)m->blk64);
   a.lw = (const T*)(f32 ? (const void*)m->lw32 : (const void*)m->lw64);
   a.lb = (const T*)(f32 ? (const void*)m->lb32 : (const void*)m->lb64);
   a.ldl = m->ldl;
-  a.max_depth = m->max_depth;
+  a.max_blocks = m->max_blocks;
   a.E = p->E;
   a.Bmax = p->Bmax;
   a.grid = grid;
   a.edges = (T*)p->m5p->edges;
   a.status = ctx->d_status;
   hipError_t e = hipSuccess;
+  if (!grid && p->Bmax <= kM5pSmallB) {
+    e = launch_m5p_small<T>(a, p->K, table, idx, score, count, ctx->params.n_suggest, (T)ctx->params.tau, s);
+    return ctx->hip(e, "M5P scoring");
+  }
   if (grid) e = launch_ibk_nan<T>(grid, p->N * p->Bmax, s);
   if (e == hipSuccess) e = launch_m5p<T>(a, p->m5p->n_tiles, s);
   if (e == hipSuccess)

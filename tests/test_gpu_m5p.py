@@ -108,6 +108,31 @@ def test_m5p_matches_oracle(G, ctx, dtype, E, min_leaf, smooth_k):
     assert checked >= te.K // 2
 
 
+def test_m5p_kernels_above_64_versions(G, ctx):
+    """Plans with kernels of up to 256 versions take the tiled path with a
+    separate composition; tables and lists as in the oracle."""
+    tr = make_batch(45, range(6000, 6024), 64, 8, brange=(3, 8))
+    te = make_batch(45, range(12), 64, 8, brange=(5, 8))
+    G.m5p_fit(ctx, G.Plan(ctx, tr.nopts, tr.opt_ids, 64, 8), dev(tr.counters), dev(tr.cycles))
+    model = M.fit(tr, 8)
+    p = G.Plan(ctx, te.nopts, te.opt_ids, 64, 8)
+    assert p.Bmax > 6
+    idx, score, count, table = G.m5p_suggest(ctx, p, dev(te.counters), dev(te.cycles))
+    G.sync(ctx)
+    go, margin = M.predict_grid(model, te, Bmax=p.Bmax)
+    to = P.compose(go, te)
+    rows = edge_decided(margin, te, MARGIN[torch.float32])
+    assert rows.mean() > 0.9
+    t = table.cpu().numpy().astype(np.float64)
+    assert close(t[rows], to[rows], 3 * RTOL[torch.float32]).all()
+    idx, score, count = idx.cpu().numpy(), score.cpu().numpy(), count.cpu().numpy()
+    for kk in range(te.K):
+        r0, r1 = int(te.row_off[kk]), int(te.row_off[kk + 1])
+        if rows[r0:r1].all():
+            assert not check_list(idx[kk, :count[kk]], score[kk, :count[kk]], to[r0:r1], P.TAU, 3,
+                                  3 * RTOL[torch.float32], first=1)
+
+
 def test_m5p_full_size_sampled(G, ctx):
     """512 training kernels of 64 versions x 128 FP32 events (16,384 pairs per
     optimisation): trees of two optimisations node for node, and sampled
