@@ -65,6 +65,16 @@ def measured_traffic():
     return float(kv["traffic_bytes_per_launch"])
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(model_o, batch, budget_s=12.0):
     from threadpoolctl import threadpool_info
     from oracle import plain as P
@@ -79,7 +89,8 @@ def cpu_baseline(model_o, batch, budget_s=12.0):
     threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
     return {"value": entries / dt, "unit": "predictions/s", "cores": int(threads), "kind": "oracle",
             "sample": f"FP64 numpy oracle (grid, composition, ranking) on one 512-kernel batch, "
-                      f"{reps} repetitions in {dt:.1f} s; BLAS threads {threads} of {os.cpu_count()} host CPUs"}
+                      f"{reps} repetitions in {dt:.1f} s; BLAS threads {threads} of {os.cpu_count()} host CPUs "
+                      f"({cpu_model()})"}
 
 
 def main():
