@@ -46,16 +46,17 @@ def path_bytes(N, E, K, n, table=True, tsize=4):
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1910_07776_amd", "csrc", "path_impl.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "path_kernel_512x64x128_traffic.txt")
 
 
-def measured_traffic():
+def measured_traffic(kernel: str = "path_kernel"):
     """HBM bytes per launch of the scoring kernel from rocprofv3 FETCH_SIZE and
     WRITE_SIZE (scaled by a 1 GiB copy's readings), recorded in profiles/ with
-    the kernel source's hash; None if the kernel changed since."""
+    the fused kernel source's hash; None if the kernel changed since or is
+    another form (the split form has no record)."""
     import hashlib
     try:
-        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+        path = os.path.join(ROOT, "profiles", f"{kernel}_512x64x128_traffic.txt")
+        kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
@@ -202,6 +203,7 @@ def main():
     sugg_rate = K_BATCH * steps / (gpu_ms / 1e3)
     by = path_bytes(nb_rows, E, K_BATCH, n)
     achieved = by / (ms_per_step / 1e3) / 1e9
+    kernel = "path_split_kernel" if tuned.get("unroll") == 0 else "path_kernel"
     log(f"{ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s, wall {wall:.2f} s")
     timing = pass_timing(G, ctx, plan, views, outs, g, stream)
     accuracy = plain_accuracy(outs[0]["table"].cpu().numpy().astype(np.float64), test, K_BATCH)
@@ -216,8 +218,8 @@ def main():
                    "autotuned": {k: tuned[k] for k in ("waves", "unroll", "source", "times_ms") if k in tuned}},
         "suggestions_per_s": sugg_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "path_kernel", "bytes_per_launch": by},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel),
+                     "kernel": kernel, "bytes_per_launch": by},
         "fit_ms": fit_ms,
         "pass_timing": timing,
         "accuracy": accuracy,

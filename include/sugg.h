@@ -100,15 +100,21 @@ SUGG_API int32_t sugg_plan_max_opts(const sugg_plan* plan); /* max B_k, or -1 */
 
 /* Launch shape of the plan's scoring kernel: waves per workgroup (1-8),
  * rows per lane group and pipeline stage (1, 2 or 4), workgroups (0 = as
- * many as fit on the device at once).  Results do not depend on it. */
+ * many as fit on the device at once).  unroll = 0 selects the split form for
+ * plans whose kernels all have the same B <= 6 and the same ids: 16 versions
+ * per workgroup, the last of a kernel's workgroups composing and ranking it
+ * (per-plan counters, re-armed by each launch; used by sugg_suggest and
+ * sugg_predict without a grid; other calls take the fused form with unroll 1).
+ * Results do not depend on it. */
 SUGG_API int32_t sugg_plan_set_launch(sugg_plan* plan, int32_t waves, int32_t unroll, int32_t grid);
 SUGG_API int32_t sugg_plan_get_launch(const sugg_plan* plan, int32_t* waves, int32_t* unroll, int32_t* grid);
 
 /* Autotuner: times the fused scoring pass (sugg_suggest) of this plan on the
  * given inputs for every candidate launch shape (waves 2, 4, 8 x unroll
- * 1, 2, 4, in that order; reps timed passes each after one warm-up) and keeps
- * the fastest in the plan.  times_ms (nullable, 9 floats) receives the mean
- * pass time of each candidate.  Needs a fitted model; allocates and frees
+ * 1, 2, 4, in that order, then the split form where the plan has one; reps
+ * timed passes each after one warm-up) and keeps the fastest in the plan.
+ * times_ms (nullable, 10 floats) receives the mean pass time of each
+ * candidate (-1 for a split form the plan does not have).  Needs a fitted model; allocates and frees
  * temporary outputs; synchronises the stream. */
 SUGG_API int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, const void* cycles,
                                int32_t reps, float* times_ms, hipStream_t stream);

@@ -285,7 +285,11 @@ int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* gri
   a.n = n;
   a.tau = (T)ctx->params.tau;
   a.status = ctx->d_status;
-  return ctx->hip(launch_path<T>(a, p->max_item_rows, p->max_item_kernels, std::max(1, p->Bmax), p->cfg, s),
+  if (p->cfg.unroll == 0 && p->split_ok() && !grid && !kmask)
+    return ctx->hip(launch_path_split<T>(a, p->d_arrivals, (T*)p->d_split_edges, s), "scoring kernel");
+  PathLaunch cfg = p->cfg;
+  if (cfg.unroll == 0) cfg.unroll = 1;   // the split form does not apply: fused, one row per stage
+  return ctx->hip(launch_path<T>(a, p->max_item_rows, p->max_item_kernels, std::max(1, p->Bmax), cfg, s),
                   "scoring kernel");
 }
 
@@ -515,6 +519,11 @@ int32_t sugg_plan_create(sugg_ctx* ctx, int32_t K, int32_t E, int32_t D, int32_t
   if (e == hipSuccess) e = upload(p->d_recs, recs.data(), sizeof(KRec) * recs.size());
   if (e == hipSuccess) e = upload(p->d_queue, nullptr, 64);
   if (e == hipSuccess) e = hipMemset(p->d_queue, 0, 64);
+  if (e == hipSuccess && p->uni_B >= 0 && p->uni_B <= 6 && p->uni_ops) {
+    e = upload(p->d_arrivals, nullptr, sizeof(int32_t) * K);
+    if (e == hipSuccess) e = hipMemset(p->d_arrivals, 0, sizeof(int32_t) * K);
+    if (e == hipSuccess) e = upload(p->d_split_edges, nullptr, (dtype == SUGG_F32 ? 4 : 8) * (size_t)p->N);
+  }
   if (e != hipSuccess) {
     delete p;
     return ctx->hip(e, "plan upload");
@@ -839,7 +848,8 @@ int32_t sugg_sync(sugg_ctx* ctx, hipStream_t stream) {
 
 int32_t sugg_plan_set_launch(sugg_plan* plan, int32_t waves, int32_t unroll, int32_t grid) {
   if (!plan) return SUGG_E_ARG;
-  if (waves < 1 || waves > 8 || (unroll != 1 && unroll != 2 && unroll != 4) || grid < 0) return SUGG_E_ARG;
+  if (waves < 1 || waves > 8 || (unroll != 0 && unroll != 1 && unroll != 2 && unroll != 4) || grid < 0)
+    return SUGG_E_ARG;
   plan->cfg.waves = waves;
   plan->cfg.unroll = unroll;
   plan->cfg.grid = grid;
@@ -902,6 +912,31 @@ int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, cons
         best = plan->cfg;
       }
       ++ci;
+    }
+  }
+  // the split form (equal kernels of at most 64 versions): one more candidate
+  if (times_ms) times_ms[ci] = -1.f;
+  if (e == hipSuccess && plan->split_ok()) {
+    plan->cfg = PathLaunch{4, 0, 0};
+    float ms = 0.f;
+    for (int rep = -1; rep < reps && e == hipSuccess; ++rep) {
+      if (rep == 0) e = hipEventRecord(e0, stream);
+      if (e != hipSuccess) break;
+      rc = plan->dtype == SUGG_F32
+               ? run_path<float>(ctx, plan, (const float*)counters, (const float*)cycles, nullptr, (float*)table,
+                                 (int32_t*)idx, (float*)score, (int32_t*)count, n, stream)
+               : run_path<double>(ctx, plan, (const double*)counters, (const double*)cycles, nullptr,
+                                  (double*)table, (int32_t*)idx, (double*)score, (int32_t*)count, n, stream);
+      if (rc) e = hipErrorUnknown;
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    if (times_ms) times_ms[ci] = ms;
+    if (e == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = plan->cfg;
     }
   }
   plan->cfg = e == hipSuccess ? best : keep;

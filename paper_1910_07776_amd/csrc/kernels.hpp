@@ -92,6 +92,13 @@ struct PathLaunch {
 template <typename T, int VPL>
 hipError_t launch_path_vpl(const PathArgs<T>& a, int max_item_rows, int max_item_kernels, int max_B,
                            const PathLaunch& cfg, hipStream_t s);
+// Split form for batches of equal kernels (same B <= 6, same ids, rows kernel
+// after kernel): 16-version workgroups write chain edges to edges[N]; the
+// last of a kernel's workgroups (arrivals[k], zero between launches, re-armed
+// by that workgroup) composes and ranks.  Same results as the fused kernel.
+template <typename T>
+hipError_t launch_path_split(const PathArgs<T>& a, int32_t* arrivals, T* edges, hipStream_t s);
+
 template <typename T>
 hipError_t launch_path(const PathArgs<T>& a, int max_item_rows, int max_item_kernels,
                        int max_B, const PathLaunch& cfg, hipStream_t s);

@@ -398,12 +398,14 @@ def autotune(ctx: Context, plan: Plan, counters, cycles, reps: int = 5, cache=No
         plan.set_launch(cfg["waves"], cfg["unroll"], 0)
         return cfg
     plan.check_inputs(counters, cycles)
-    times = (C.c_float * (len(TUNE_WAVES) * len(TUNE_UNROLL)))()
+    times = (C.c_float * (len(TUNE_WAVES) * len(TUNE_UNROLL) + 1))()
     A.check(ctx.h, A.lib().sugg_autotune(ctx.h, plan.h, _ptr(counters), _ptr(cycles), int(reps), times,
                                          _stream()))
     cfg = plan.get_launch()
     cfg["times_ms"] = {f"w{w}u{u}": float(times[i * len(TUNE_UNROLL) + j])
                        for i, w in enumerate(TUNE_WAVES) for j, u in enumerate(TUNE_UNROLL)}
+    if times[len(TUNE_WAVES) * len(TUNE_UNROLL)] >= 0:
+        cfg["times_ms"]["split"] = float(times[len(TUNE_WAVES) * len(TUNE_UNROLL)])
     if cache is not None:
         cache[key] = cfg
     return cfg

@@ -399,3 +399,79 @@ def test_graph_replays_match_eager(G, ctx, ragged):
         G.suggest(ctx, po, *gpu_inputs(other))
     G.sync(ctx)
     g.close()
+
+
+def _same(x, y):
+    return torch.equal(torch.nan_to_num(x.double(), nan=-7.0), torch.nan_to_num(y.double(), nan=-7.0))
+
+
+@pytest.mark.parametrize("E,B,dtype,n", [(128, 6, torch.float32, 3), (128, 6, torch.float64, 3),
+                                         (37, 5, torch.float32, 8), (200, 4, torch.float64, 3),
+                                         (64, 3, torch.float32, 2), (128, 1, torch.float32, 3)])
+def test_split_form_bit_identical_to_fused(G, E, B, dtype, n):
+    """The split form (16 versions per workgroup, the last of a kernel's
+    workgroups composing and ranking) against the fused kernel, bit for bit,
+    over repeated launches (the arrival counters re-arm themselves) and graph
+    replays with eager work in between."""
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    tr = make_batch(88, range(3000, 3064), E, B, dtype=npdt)
+    te = make_batch(88, range(200), E, B, dtype=npdt)
+    c_ = G.Context(0, n_suggest=n)
+    try:
+        G.fit(c_, plan_of(G, c_, tr, B, dtype), *gpu_inputs(tr, dtype))
+        pte = plan_of(G, c_, te, B, dtype)
+        c, cy = gpu_inputs(te, dtype)
+        pte.set_launch(4, 1, 0)
+        ref = [t.clone() for t in G.suggest(c_, pte, c, cy)]
+        ref_tab = G.predict(c_, pte, c, cy)[0].clone()
+        pte.set_launch(4, 0, 0)
+        assert pte.get_launch()["unroll"] == 0
+        for _ in range(3):
+            out = G.suggest(c_, pte, c, cy)
+            assert all(_same(x, y) for x, y in zip(ref, out))
+        assert _same(G.predict(c_, pte, c, cy)[0], ref_tab)
+        # the grid form falls back to the fused kernel and agrees too
+        tab_g, _ = G.predict(c_, pte, c, cy, grid=True)
+        assert _same(tab_g, ref_tab)
+        bufs = {"idx": torch.empty((te.K, n), dtype=torch.int32, device="cuda"),
+                "score": torch.empty((te.K, n), dtype=dtype, device="cuda"),
+                "count": torch.empty(te.K, dtype=torch.int32, device="cuda"),
+                "table": torch.empty(te.N, dtype=dtype, device="cuda")}
+        g = G.Graph(c_)
+        with g.capture():
+            G.suggest(c_, pte, c, cy, out=bufs)
+        for _ in range(3):
+            for t in bufs.values():
+                t.zero_()
+            g.launch()
+            torch.cuda.synchronize()
+            assert all(_same(x, bufs[k]) for x, k in zip(ref, ("idx", "score", "count", "table")))
+            G.suggest(c_, pte, c, cy)   # eager launches between replays
+        G.sync(c_)
+        g.close()
+    finally:
+        c_.close()
+
+
+def test_split_form_512_kernels_against_oracle(G):
+    """The headline batch (512 kernels x 64 versions x 128 FP32 events) in the
+    split form against the oracle; the autotuner includes the form."""
+    tr = make_batch(1910, range(10 ** 6, 10 ** 6 + 512), 128, 6)
+    te = make_batch(1910, range(512), 128, 6)
+    om = P.fit(tr, 6)
+    _, otab, _ = P.run(om, te)
+    c_ = G.Context(0)
+    try:
+        G.fit(c_, plan_of(G, c_, tr, 6), *gpu_inputs(tr))
+        pte = plan_of(G, c_, te, 6)
+        c, cy = gpu_inputs(te)
+        pte.set_launch(4, 0, 0)
+        idx, score, count, table = G.suggest(c_, pte, c, cy)
+        G.sync(c_)
+        assert_scores(table.cpu().numpy(), otab, RTOL32, "table")
+        check_suggestions(idx, score, count, otab, te.row_off, P.TAU, 3, RTOL32)
+        cfg = G.autotune(c_, pte, c, cy, reps=2)
+        assert len(cfg["times_ms"]) == 10 and cfg["times_ms"]["split"] > 0
+        assert cfg["unroll"] in (0, 1, 2, 4)
+    finally:
+        c_.close()
