@@ -475,3 +475,33 @@ def test_split_form_512_kernels_against_oracle(G):
         assert cfg["unroll"] in (0, 1, 2, 4)
     finally:
         c_.close()
+
+
+@pytest.mark.parametrize("E,dtype,D,brange", [(1, torch.float32, 4, (0, 4)), (37, torch.float32, 6, (0, 6)),
+                                              (64, torch.float64, 5, (2, 5)), (200, torch.float32, 8, (0, 8)),
+                                              (256, torch.float32, 6, None), (256, torch.float64, 10, (4, 10))])
+def test_event_counts_against_oracle(G, E, dtype, D, brange):
+    """The fused path over the event counts the kernels are built for (one
+    event up to the maximum of 256; chunked and scalar loads), both dtypes,
+    mixed and uniform B: table, grid and suggestions against the oracle."""
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    rtol = RTOL32 if dtype == torch.float32 else RTOL64
+    tr = make_batch(91, range(7000, 7048), E, D, brange=brange, dtype=npdt)
+    te = make_batch(91, range(60), E, D, brange=brange, dtype=npdt)
+    om = P.fit(tr, D)
+    ogrid, otab, _ = P.run(om, te)
+    c_ = G.Context(0)
+    try:
+        G.fit(c_, plan_of(G, c_, tr, D, dtype), *gpu_inputs(tr, dtype))
+        pte = plan_of(G, c_, te, D, dtype)
+        c, cy = gpu_inputs(te, dtype)
+        idx, score, count, table = G.suggest(c_, pte, c, cy)
+        tab, grid = G.predict(c_, pte, c, cy, grid=True)
+        G.sync(c_)
+        assert_scores(table.cpu().numpy(), otab, rtol, f"table E={E}")
+        assert torch.equal(table, tab)
+        g = grid.cpu().numpy()[:, :ogrid.shape[1]]
+        assert_scores(g, ogrid, rtol, f"grid E={E}")
+        check_suggestions(idx, score, count, otab, te.row_off, P.TAU, 3, rtol)
+    finally:
+        c_.close()
