@@ -49,8 +49,10 @@ __device__ __forceinline__ bf16x8 load8(const __bf16* p, int ld, int row, int ro
 }
 
 // Workgroup of 4 waves in a 2 x 2 arrangement; each wave computes TM x TN
-// MFMA tiles of 32 x 32, so the workgroup tile is (64 TM) x (64 TN).
-template <int EPI, int TM, int TN>
+// MFMA tiles of 32 x 32, so the workgroup tile is (64 TM) x (64 TN).  EX: the
+// tiles cover M, N and each K range exactly and rows are 16-byte aligned, so
+// operand loads and output stores need no bounds checks.
+template <int EPI, int TM, int TN, bool EX>
 __global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs g) {
   constexpr int WGM = 64 * TM, WGN = 64 * TN;
   __shared__ __align__(16) __bf16 As[2][WGM * kLdsRow];
@@ -79,9 +81,13 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs g) {
 #pragma unroll
     for (int v = 0; v < kKVec; ++v) {
 #pragma unroll
-      for (int i = 0; i < TM; ++i) ra[i][v] = load8(g.A, g.lda, m0 + lr + 64 * i, g.M, k0 + lk + 32 * v, ke);
+      for (int i = 0; i < TM; ++i)
+        ra[i][v] = EX ? *reinterpret_cast<const bf16x8*>(g.A + (int64_t)(m0 + lr + 64 * i) * g.lda + k0 + lk + 32 * v)
+                      : load8(g.A, g.lda, m0 + lr + 64 * i, g.M, k0 + lk + 32 * v, ke);
 #pragma unroll
-      for (int i = 0; i < TN; ++i) rb[i][v] = load8(g.Bt, g.ldb, n0 + lr + 64 * i, g.N, k0 + lk + 32 * v, ke);
+      for (int i = 0; i < TN; ++i)
+        rb[i][v] = EX ? *reinterpret_cast<const bf16x8*>(g.Bt + (int64_t)(n0 + lr + 64 * i) * g.ldb + k0 + lk + 32 * v)
+                      : load8(g.Bt, g.ldb, n0 + lr + 64 * i, g.N, k0 + lk + 32 * v, ke);
     }
   };
   fetch(kb);
@@ -127,7 +133,7 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs g) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + wm * 32 * TM + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        if (row >= g.M || col >= g.N) continue;
+        if (!EX && (row >= g.M || col >= g.N)) continue;
         const float v = acc[a][b][r];
         if (EPI == kEpiWgrad) {
           g.Cf[(int64_t)split * g.M * g.N + (int64_t)row * g.N + col] = v;
@@ -167,7 +173,13 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs g) {
 template <int EPI, int TM, int TN>
 void launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s) {
   const dim3 grid((g.N + 64 * TN - 1) / (64 * TN), (g.M + 64 * TM - 1) / (64 * TM), splits);
-  hipLaunchKernelGGL((gemm_nt_kernel<EPI, TM, TN>), grid, dim3(256), 0, s, g);
+  // every split's K range non-empty and a whole number of stages
+  const bool ex = g.M % (64 * TM) == 0 && g.N % (64 * TN) == 0 && g.K > 0 && g.K % kKStep == 0 &&
+                  g.k_per_split % kKStep == 0 && (int64_t)g.k_per_split * (splits - 1) < g.K && g.lda % 8 == 0 &&
+                  g.ldb % 8 == 0 && reinterpret_cast<uintptr_t>(g.A) % 16 == 0 &&
+                  reinterpret_cast<uintptr_t>(g.Bt) % 16 == 0;
+  if (ex) hipLaunchKernelGGL((gemm_nt_kernel<EPI, TM, TN, true>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((gemm_nt_kernel<EPI, TM, TN, false>), grid, dim3(256), 0, s, g);
 }
 
 template <int EPI>
