@@ -53,7 +53,7 @@ __device__ __forceinline__ bf16x8 load8(const __bf16* p, int ld, int row, int ro
 // tiles cover M, N and each K range exactly and rows are 16-byte aligned, so
 // operand loads and output stores need no bounds checks.
 template <int EPI, int TM, int TN, bool EX>
-__global__ void __launch_bounds__(256) gemm_nt_kernel(const GemmArgs g) {
+__global__ void __launch_bounds__(256, 3) gemm_nt_kernel(const GemmArgs g) {
   constexpr int WGM = 64 * TM, WGN = 64 * TN;
   __shared__ __align__(16) __bf16 As[2][WGM * kLdsRow];
   __shared__ __align__(16) __bf16 Bs[2][WGN * kLdsRow];
