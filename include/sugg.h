@@ -322,8 +322,9 @@ SUGG_API int32_t sugg_ibk_suggest(sugg_ctx* ctx, const sugg_plan* plan, const vo
  *   up to 16), uploaded.  Synchronous; replaces a previous M5P model.
  *   min_leaf >= 1 (the paper's tool, Weka's M5P, uses 4), smooth_k >= 0 (15;
  *   0 disables smoothing).  SUGG_E_BAD_COUNTER if a training counter or
- *   cycle count is not positive and finite; SUGG_E_BUDGET above 2^22 pairs
- *   per id.
+ *   cycle count is not positive and finite; SUGG_E_BUDGET above 2^20 pairs
+ *   per id or 8 GiB of FP64 training features (N x E x 8 bytes).  Trees are
+ *   induced in as many host threads as 16 GiB of sort buffers allow.
  * sugg_m5p_tree: the pruned tree of global id opt, preorder (a node, its left
  *   subtree, its right subtree), into host arrays of cap entries: feat (-1 at
  *   a leaf), thr (go left when z[feat] <= thr; NaN at a leaf), left and right

@@ -37,7 +37,9 @@ void m5p_plan_free(M5pPlan*& p) {
 
 namespace {
 
-constexpr int64_t kM5pMaxCases = (int64_t)1 << 22;   // training pairs per optimisation
+constexpr int64_t kM5pMaxCases = (int64_t)1 << 20;    // training pairs per optimisation
+constexpr int64_t kM5pHostBudget = (int64_t)16 << 30;  // bytes of host memory for the induction
+constexpr int64_t kM5pMaxFeatureBytes = (int64_t)8 << 30;   // FP64 training features copied to the host
 
 int m5p_ldl(int E) { return E <= 64 ? 64 : E <= 128 ? 128 : 256; }
 
@@ -88,8 +90,14 @@ int induce_all(sugg_ctx* ctx, const sugg_plan* p, const std::vector<double>& z, 
       }
     }
   };
+  // each tree holds every feature's sorted case order and values (12 B per
+  // case and feature): as many trees at once as the host budget allows
+  int64_t biggest = 1;
+  for (int o : work) biggest = std::max<int64_t>(biggest, (int64_t)before[o].size());
+  const int64_t per_tree = biggest * p->E * 12 + ((int64_t)64 << 20);
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int nt = (int)std::min<size_t>(std::min<unsigned>(hw, 16u), work.size());
+  const int by_mem = (int)std::max<int64_t>(1, kM5pHostBudget / per_tree);
+  const int nt = (int)std::min<size_t>(std::min<unsigned>(std::min<unsigned>(hw, 16u), (unsigned)by_mem), work.size());
   std::vector<std::thread> pool;
   for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
   worker();
@@ -369,6 +377,8 @@ int32_t sugg_m5p_fit(sugg_ctx* ctx, const sugg_plan* train, const void* counters
   if (train->E > 256) return ctx->fail(SUGG_E_SHAPE, "M5P supports at most 256 events (E=%d)", train->E);
   if (train->N == 0) return ctx->fail(SUGG_E_SHAPE, "M5P needs at least one training row");
   if (train->N >= ((int64_t)1 << 31)) return ctx->fail(SUGG_E_BUDGET, "too many training rows for M5P");
+  if (train->N * (int64_t)train->E * 8 > kM5pMaxFeatureBytes)
+    return ctx->fail(SUGG_E_BUDGET, "M5P training features exceed %lld bytes", (long long)kM5pMaxFeatureBytes);
   M5pParams prm;
   prm.min_leaf = min_leaf;
   prm.smooth_k = smooth_k;
