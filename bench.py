@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--serving", action="store_true", help="also run the serving section with --no-extra")
     ap.add_argument("--surrogate", action="store_true", help="also run the surrogate section with --no-extra")
     ap.add_argument("--m5p", action="store_true", help="also run the M5P model-tree section with --no-extra")
+    ap.add_argument("--real", action="store_true", help="also run the real MI355X profiles section with --no-extra")
     ap.add_argument("--launch", default=None,
                     help="WAVES,UNROLL: force the scoring kernel's launch shape (no tuning)")
     ap.add_argument("--retune", action="store_true",
@@ -231,6 +232,8 @@ def main():
         out["paths"] = paths_extra(G, ctx, dev)
     if not args.no_extra or args.m5p:
         out["m5p"] = m5p_extra(G, dev, train, test, no_cpu=args.no_cpu)
+    if not args.no_extra or args.real:
+        out["real_profiles"] = real_extra(G, dev)
     if not args.no_extra:
         out["ragged_16384"] = ragged_extra(G, ctx, dev)
     if not args.no_extra or args.surrogate:
@@ -244,7 +247,20 @@ def main():
         om = P.fit(train, D)
         one = P.SubBatch(test, range(K_BATCH))
         out["cpu_baseline"] = cpu_baseline(om, one)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(finite(out)), flush=True)
+
+
+def finite(x):
+    """The JSON line carries no NaN or Infinity (null instead)."""
+    if isinstance(x, dict):
+        return {k: finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [finite(v) for v in x]
+    if isinstance(x, float) and not np.isfinite(x):
+        return None
+    if isinstance(x, np.floating):
+        return float(x) if np.isfinite(x) else None
+    return x
 
 
 TUNE_DB = os.path.join(ROOT, "paper_1910_07776_amd", "tuning_db.json")
@@ -477,6 +493,62 @@ def m5p_extra(G, dev, train, test, reps: int = 50, no_cpu: bool = False):
         out["cpu_oracle"] = {"value": n / dt, "unit": "predictions/s", "cores": 1, "kind": "oracle",
                              "sample": f"FP64 numpy oracle tree walks with smoothing, {n} predictions in {dt:.1f} s, "
                                        "trees induced from the first 128 training kernels"}
+    return out
+
+
+def real_extra(G, dev):
+    """The tool on real MI355X counters (two programs x 64 versions x 3 inputs
+    x 3 runs, profiled with rocprofv3; paper_1910_07776_amd/profiling): the
+    paper's experiment structure (train on some profiles, test on others) with
+    the ridge, IBK (k = 10) and M5P models.  Sign accuracy: predicted and
+    measured single-optimisation speedups on the same side of 1 (Table 3's
+    measure); MAPE: the composed table against the measured subset speedups."""
+    import torch
+    from paper_1910_07776_amd.profiling import dataset as R
+    data = R.load()
+    exps = {"1 run -> 3 runs (n-body)": (R.sweeps(0, runs=(0,)), R.sweeps(0)),
+            "1 run -> 3 runs (gather)": (R.sweeps(1, runs=(0,)), R.sweeps(1)),
+            "inputs 0,1 -> input 2": (R.sweeps(None, inputs=(0, 1)), R.sweeps(None, inputs=(2,))),
+            "n-body -> gather": (R.sweeps(0), R.sweeps(1)),
+            "gather -> n-body": (R.sweeps(1), R.sweeps(0))}
+    out = {}
+    for name, (tr_s, te_s) in exps.items():
+        tr, te = R.batch(data, tr_s), R.batch(data, te_s)
+        ctx = G.Context(0)
+        ptr = G.Plan(ctx, tr.nopts, tr.opt_ids, tr.E, 6)
+        tc, tcy = torch.from_numpy(tr.counters).to(dev), torch.from_numpy(tr.cycles).to(dev)
+        p = G.Plan(ctx, te.nopts, te.opt_ids, te.E, 6)
+        c, cy = torch.from_numpy(te.counters).to(dev), torch.from_numpy(te.cycles).to(dev)
+        lc = np.log(te.cycles.astype(np.float64))
+        true_tab = np.concatenate([lc[r0] - lc[r0:r0 + 64] for r0 in te.row_off[:-1]])
+        row = {}
+        for model in ("ridge", "ibk", "m5p"):
+            if model == "ridge":
+                G.fit(ctx, ptr, tc, tcy)
+                tab, grid = G.predict(ctx, p, c, cy, grid=True)
+            elif model == "ibk":
+                G.ibk_fit(ctx, ptr, tc, tcy, k=10)
+                tab, grid = G.ibk_predict(ctx, p, c, cy, grid=True)
+            else:
+                G.m5p_fit(ctx, ptr, tc, tcy)
+                tab, grid = G.m5p_predict(ctx, p, c, cy, grid=True)
+            G.sync(ctx)
+            g = grid.cpu().numpy().astype(np.float64)
+            signs, hits = 0, 0
+            for k in range(te.K):
+                r0 = int(te.row_off[k])
+                for S in range(64):
+                    for b in range(6):
+                        if not (S >> b) & 1:
+                            meas = lc[r0 + S] - lc[r0 + (S | (1 << b))]
+                            signs += 1
+                            hits += (g[r0 + S, b] > 0) == (meas > 0)
+            t = tab.cpu().numpy().astype(np.float64)
+            row[model] = {"sign_accuracy": hits / signs, "mape": speedup_mape(t, true_tab, te.row_off)}
+        ctx.close()
+        out[name] = row
+        log(f"real profiles, {name}: " + ", ".join(f"{m} sign {v['sign_accuracy']:.3f} MAPE {v['mape']:.3f}"
+                                                  for m, v in row.items()))
     return out
 
 

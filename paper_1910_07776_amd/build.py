@@ -42,13 +42,31 @@ def _compile(src: str) -> str:
     return obj
 
 
+VERSIONS_SRC = os.path.join(PKG, "profiling", "versions.hip")
+VERSIONS_BIN = os.path.join(LIBDIR, "sugg_versions")
+
+
+def _build_versions() -> str:
+    """The profiled-versions program (real Tier 1 data), an executable."""
+    tmp = VERSIONS_BIN + ".tmp"
+    cmd = [HIPCC, *[f for f in FLAGS if f not in ("-fPIC", "-fvisibility=hidden")], VERSIONS_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {VERSIONS_SRC}:\n{r.stderr}")
+    os.replace(tmp, VERSIONS_BIN)
+    return VERSIONS_BIN
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source and link the shared library; returns its path."""
+    """Compile every source and link the shared library (and the profiled-
+    versions program); returns the library's path."""
     os.makedirs(OBJDIR, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
     srcs = sources()
-    with ThreadPoolExecutor(min(int(os.environ.get("MAX_JOBS", "8")), len(srcs))) as ex:
+    with ThreadPoolExecutor(min(int(os.environ.get("MAX_JOBS", "8")), len(srcs) + 1)) as ex:
+        vfut = ex.submit(_build_versions)
         objs = list(ex.map(_compile, srcs))
+        vfut.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
