@@ -33,7 +33,11 @@ Readings of the paper taken here:
   * inputs: the standardised Tier 1 features and the before/after log-speedup
     labels of the linear model (Sections 2, 3.3);
   * node models are ordinary least squares with an intercept (no penalty), and
-    M5's greedy deletion of model terms is not applied;
+    M5's greedy deletion of model terms is not applied; a feature of A whose
+    node-centred column lies in the span of the features kept before it (its
+    residual sum of squares after regressing on them is at most DROP times its
+    own) is left out, so the solution is unique even when counters are
+    collinear, and the error estimate counts the kept parameters only;
   * MIN_LEAF = 4 cases, SD_FRAC = 0.05, K = 15;
   * ties: split candidates whose SDR is within TIE * sd(root) of the best are
     equal and the first in (feature, threshold) order wins; a pruning
@@ -55,6 +59,7 @@ MIN_LEAF = 4
 SD_FRAC = 0.05
 SMOOTH_K = 15.0
 TIE = 1e-9
+DROP = 1e-9
 
 
 def label_sd(y: np.ndarray) -> float:
@@ -137,16 +142,39 @@ def subtree_features(nodes):
     return [sorted(a) for a in A]
 
 
+def independent_features(Z: np.ndarray, A):
+    """The features of A, in order, whose node-centred column is not (up to
+    DROP) in the span of the features kept before it."""
+    Xc = Z[:, A] - Z[:, A].mean(axis=0)
+    keep, basis = [], np.zeros((len(Xc), 0))    # orthonormal basis of the kept columns
+    for q in range(len(A)):
+        x = Xc[:, q]
+        ss = float(x @ x)
+        res = x.copy()
+        for _ in range(2):                        # projected out twice, for accuracy
+            res -= basis @ (basis.T @ res)
+        rss = float(res @ res)
+        if ss > 0 and rss > DROP * ss:
+            keep.append(q)
+            basis = np.hstack([basis, (res / np.sqrt(rss))[:, None]])
+    return [A[q] for q in keep]
+
+
 def fit_node_model(Z: np.ndarray, y: np.ndarray, A):
-    """Least-squares model on the features A with an intercept, and its M5
+    """Least-squares model with an intercept on the independent features of A
+    (see independent_features; coefficient 0 for the others), and its M5
     error estimate."""
     n = len(y)
-    X = np.hstack([Z[:, A], np.ones((n, 1))])
+    K = independent_features(Z, A) if A else []
+    X = np.hstack([Z[:, K], np.ones((n, 1))])
     coef = np.linalg.lstsq(X, y, rcond=None)[0]
+    w = np.zeros(len(A))
+    for j, f in enumerate(K):
+        w[A.index(f)] = coef[j]
     mae = float(np.mean(np.abs(y - X @ coef)))
-    v = len(A) + 1
+    v = len(K) + 1
     est = (n + v) / (n - v) * mae if n > v else np.inf
-    return {"A": list(A), "w": coef[:-1], "b": float(coef[-1]), "est": est}
+    return {"A": list(A), "w": w, "b": float(coef[-1]), "est": est}
 
 
 def build(Z: np.ndarray, y: np.ndarray, min_leaf: int = MIN_LEAF, sd_frac: float = SD_FRAC):

@@ -10,8 +10,11 @@
 //           with label sd at most sd_frac of the root's are leaves.
 //  models   least squares with an intercept at every node, on the features
 //           tested inside its subtree (a constant at a leaf), from centred
-//           normal equations and a Cholesky factorisation; estimated error
-//           mean |residual| * (n + v) / (n - v), v parameters.
+//           normal equations and a Cholesky factorisation taken in feature
+//           order, which leaves out a feature whose pivot (its residual sum
+//           of squares given the features kept before it) is at most 1e-9 of
+//           its own sum of squares; estimated error mean |residual| *
+//           (n + v) / (n - v), v the kept parameters.
 //  prune    bottom-up: a node whose own model's estimate is no larger than
 //           the case-weighted estimate of its pruned children becomes a leaf.
 //  smooth   from a leaf up to the root, p <- (n_c p + K q) / (n_c + K) with q
@@ -42,9 +45,10 @@ struct GNode {
 
 struct NodeModel {
   std::vector<int32_t> A;   // features
-  std::vector<double> w;    // coefficients on A
+  std::vector<double> w;    // coefficients on A (0 for a feature left out)
   double b = 0.0;           // intercept
   double est = 0.0;         // M5 error estimate
+  int kept = 0;             // features with a coefficient
 };
 
 class Grower {
@@ -245,7 +249,7 @@ class Grower {
           r[q] += xq * yc;
         }
       }
-      solve_spd(G, r, a);
+      md.kept = solve_dropping(G, r, a);
       md.w = r;
     }
     md.b = ym;
@@ -257,54 +261,57 @@ class Grower {
       for (int q = 0; q < a; ++q) pr += md.w[q] * z(i, md.A[q]);
       sae += std::fabs(y_[i] - pr);
     }
-    const double v = (double)(a + 1);
+    const double v = (double)(md.kept + 1);
     md.est = (double)m > v ? ((double)m + v) / ((double)m - v) * (sae / (double)m)
                            : std::numeric_limits<double>::infinity();
     return md;
   }
 
-  // G x = r for the symmetric positive definite G (lower triangle filled);
-  // a singular G is regularised by a relative 1e-10 of its mean diagonal.
-  static void solve_spd(std::vector<double> G, std::vector<double>& r, int a) {
-    const std::vector<double> G0 = G;
-    double jitter = 0.0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      G = G0;
-      for (int q = 0; q < a; ++q) G[(size_t)q * a + q] += jitter;
-      bool ok = true;
-      for (int q = 0; q < a && ok; ++q) {
-        for (int t = 0; t <= q; ++t) {
-          double s = G[(size_t)q * a + t];
-          for (int u = 0; u < t; ++u) s -= G[(size_t)q * a + u] * G[(size_t)t * a + u];
-          if (t == q) {
-            if (!(s > 1e-13 * G0[(size_t)q * a + q])) {
-              ok = false;
-              break;
-            }
-            G[(size_t)q * a + q] = std::sqrt(s);
-          } else {
-            G[(size_t)q * a + t] = s / G[(size_t)t * a + t];
-          }
-        }
+  // G x = r for the centred Gram matrix G (lower triangle filled), by a
+  // Cholesky factorisation in feature order that leaves out every feature
+  // whose pivot is at most kDrop of its diagonal (x = 0 there).  Returns the
+  // number of features kept.
+  static int solve_dropping(std::vector<double>& G, std::vector<double>& r, int a) {
+    constexpr double kDrop = 1e-9;
+    std::vector<char> keep(a, 0);
+    std::vector<double> diag(a);
+    for (int q = 0; q < a; ++q) diag[q] = G[(size_t)q * a + q];
+    int kept = 0;
+    for (int q = 0; q < a; ++q) {
+      for (int t = 0; t < q; ++t) {
+        if (!keep[t]) continue;
+        double s = G[(size_t)q * a + t];
+        for (int u = 0; u < t; ++u)
+          if (keep[u]) s -= G[(size_t)q * a + u] * G[(size_t)t * a + u];
+        G[(size_t)q * a + t] = s / G[(size_t)t * a + t];
       }
-      if (ok) {
-        for (int q = 0; q < a; ++q) {
-          double s = r[q];
-          for (int u = 0; u < q; ++u) s -= G[(size_t)q * a + u] * r[u];
-          r[q] = s / G[(size_t)q * a + q];
-        }
-        for (int q = a - 1; q >= 0; --q) {
-          double s = r[q];
-          for (int u = q + 1; u < a; ++u) s -= G[(size_t)u * a + q] * r[u];
-          r[q] = s / G[(size_t)q * a + q];
-        }
-        return;
+      double s = diag[q];
+      for (int u = 0; u < q; ++u)
+        if (keep[u]) s -= G[(size_t)q * a + u] * G[(size_t)q * a + u];
+      if (diag[q] > 0.0 && s > kDrop * diag[q]) {
+        keep[q] = 1;
+        G[(size_t)q * a + q] = std::sqrt(s);
+        ++kept;
       }
-      double tr = 0.0;
-      for (int q = 0; q < a; ++q) tr += G0[(size_t)q * a + q];
-      jitter = 1e-10 * std::max(tr / a, 1e-300);
     }
-    std::fill(r.begin(), r.end(), 0.0);
+    for (int q = 0; q < a; ++q) {
+      if (!keep[q]) continue;
+      double s = r[q];
+      for (int u = 0; u < q; ++u)
+        if (keep[u]) s -= G[(size_t)q * a + u] * r[u];
+      r[q] = s / G[(size_t)q * a + q];
+    }
+    for (int q = a - 1; q >= 0; --q) {
+      if (!keep[q]) {
+        r[q] = 0.0;
+        continue;
+      }
+      double s = r[q];
+      for (int u = q + 1; u < a; ++u)
+        if (keep[u]) s -= G[(size_t)u * a + q] * r[u];
+      r[q] = s / G[(size_t)q * a + q];
+    }
+    return kept;
   }
 
   void models() {

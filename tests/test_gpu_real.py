@@ -118,14 +118,10 @@ def effective_weights(tree, z, k, E):
 
 
 def test_m5p_on_real_profiles(G, data):
-    """Trees node for node, and predictions, for one program's runs.  Real
-    counters include exactly collinear columns, so a node's least-squares
-    system can be singular; the oracle then takes the minimum-norm solution
-    and the library a slightly regularised one.  The two agree on the span of
-    the training features (every version of the same program) but may differ
-    when extrapolating to another program, so predictions are compared for
-    the program the trees were grown on."""
-    tr, te = R.batch(data, R.sweeps(0, runs=(0,))), R.batch(data, R.sweeps(0))
+    """Trees grown on the n-body program node for node, and their predictions
+    for the gather program's versions (extrapolation: the node models' unique
+    solutions matter when counters are collinear, as real ones are)."""
+    tr, te = R.batch(data, R.sweeps(0)), R.batch(data, R.sweeps(1))
     model = M.fit(tr, 6)
     ctx = G.Context(0)
     try:

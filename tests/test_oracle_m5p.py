@@ -146,3 +146,20 @@ def test_fit_and_run_on_a_synthetic_batch():
     assert np.isfinite(table).all() and len(res) == te.K
     _, margin = M.predict_grid(model, te)
     assert (margin > 0).all()
+
+
+def test_collinear_features_are_dropped_in_order():
+    # z1 = 2 z0 exactly and z2 constant: only z0 of A = [0, 1, 2] is kept, so
+    # y = 3 z0 + 1 is fitted by w = (3, 0, 0), b = 1, with two parameters
+    rng = np.random.default_rng(11)
+    z0 = rng.normal(size=40)
+    Z = np.stack([z0, 2 * z0, np.full(40, 0.7)], axis=1)
+    y = 3 * z0 + 1
+    assert M.independent_features(Z, [0, 1, 2]) == [0]
+    assert M.independent_features(Z, [1, 0]) == [1]
+    m = M.fit_node_model(Z, y, [0, 1, 2])
+    np.testing.assert_allclose(m["w"], [3, 0, 0], atol=1e-12)
+    assert abs(m["b"] - 1) < 1e-12 and m["est"] < 1e-12
+    # an independent third column is kept
+    Z[:, 2] = rng.normal(size=40)
+    assert M.independent_features(Z, [0, 1, 2]) == [0, 2]
