@@ -309,8 +309,11 @@ SUGG_API int32_t sugg_ibk_suggest(sugg_ctx* ctx, const sugg_plan* plan, const vo
  * adjacent distinct training values; no split of a node with fewer than
  * 2 * min_leaf pairs or with label sd at most 5 % of the root's; each side
  * keeps min_leaf pairs); least-squares linear models with an intercept at
- * every node on the features tested in its subtree; bottom-up pruning by the
- * M5 error estimate (mean |residual| * (n + v) / (n - v)); smoothing from
+ * every node on the features tested in its subtree (in feature order, a
+ * feature whose centred column lies within 1e-9 of the span of those kept
+ * before it is left out, so collinear counters give a unique model);
+ * bottom-up pruning by the M5 error estimate (mean |residual| * (n + v) /
+ * (n - v), v kept parameters); smoothing from
  * the leaf up, p <- (n_c p + smooth_k q) / (n_c + smooth_k), folded into one
  * linear model per leaf.  Ties: split gains within 1e-9 of the root's label
  * sd are equal (first feature, then lowest threshold wins); a pruning
