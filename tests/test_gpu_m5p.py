@@ -66,7 +66,8 @@ def edge_decided(margin, batch, thr):
 
 @pytest.mark.parametrize("dtype,E,min_leaf,smooth_k", [(torch.float32, 128, 4, 15.0), (torch.float64, 128, 4, 15.0),
                                                        (torch.float32, 37, 4, 15.0), (torch.float64, 40, 2, 0.0),
-                                                       (torch.float32, 200, 6, 5.0)])
+                                                       (torch.float32, 200, 6, 5.0), (torch.float32, 1, 4, 15.0),
+                                                       (torch.float64, 16, 100000, 15.0)])
 def test_m5p_matches_oracle(G, ctx, dtype, E, min_leaf, smooth_k):
     npdt = np.float32 if dtype == torch.float32 else np.float64
     tr = make_batch(41, range(5000, 5048), E, 6, brange=(2, 6), dtype=npdt)
