@@ -106,6 +106,17 @@ def test_512_kernels_fit_predict_suggest(G, ctx):
     assert torch.equal(table, tab)
     assert_scores(grid.cpu().numpy(), ogrid, RTOL32, "grid")
     check_suggestions(idx, score, count, otab, te.row_off, P.TAU, 3, RTOL32)
+    # the launch shape the benchmark times (its tuning-database entry for this
+    # plan) gives the same bits
+    from paper_1910_07776_amd import tuning
+    db = tuning.TuneCache(os.path.join(os.path.dirname(HERE), "paper_1910_07776_amd", "tuning_db.json"))
+    key = tuning.plan_key(pte, 3)
+    assert key in db, key
+    pte.set_launch(db[key]["waves"], db[key]["unroll"], 0)
+    again = G.suggest(ctx, pte, c, cy)
+    G.sync(ctx)
+    for x, y in zip((idx, score, count, table), again):
+        assert torch.equal(torch.nan_to_num(x.double(), nan=-7.0), torch.nan_to_num(y.double(), nan=-7.0))
 
 
 def test_two_kernel_cross_program_folds_fp64(G, ctx):
