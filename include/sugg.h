@@ -131,6 +131,24 @@ SUGG_API int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* count
 SUGG_API int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* counters,
                                     const void* cycles, int32_t mode, void* z_out, hipStream_t stream);
 
+/* sugg_load_features for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, modes, results (bit-identical) and errors,
+ * but the call allocates nothing.  The FP64 column-statistics partials of
+ * SUGG_FIT_STATS (2 x E x min(1024, ceil(N / 256)) doubles) live in a static
+ * device array of SUGG_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends (its address is looked up by
+ * sugg_create); a plan whose partials would not fit is rejected with
+ * SUGG_E_BUDGET (never the case within SUGG_MAX_EVENTS).  With
+ * SUGG_FIT_STATS the context's model storage must already hold the plan's E
+ * columns (one earlier sugg_load_features, sugg_fit or sugg_model_set of
+ * that E), else SUGG_E_STATE.  Every call on one GPU shares that GPU's
+ * array and the array keeps the last call's partials: calls that overlap in
+ * time on one GPU (from any context or stream) race. */
+#define SUGG_NOALLOC_SCRATCH_BYTES (4 << 20)
+SUGG_API int32_t sugg_load_features_noalloc(sugg_ctx* ctx, const sugg_plan* plan, const void* counters,
+                                            const void* cycles, int32_t mode, void* z_out, hipStream_t stream);
+
 /* Tier 2 training (Section 2; Sections 3.3-3.4): column statistics from the
  * training rows, then for every global optimisation o with at least one
  * before/after pair (version S without o, the same kernel's version S with o)

@@ -57,6 +57,7 @@ SIGNATURES = {
     "sugg_plan_get_launch": (_I32, [_P, _PI32, _PI32, _PI32]),
     "sugg_autotune": (_I32, [_P, _P, _P, _P, _I32, C.POINTER(C.c_float), _P]),
     "sugg_load_features": (_I32, [_P, _P, _P, _P, _I32, _P, _P]),
+    "sugg_load_features_noalloc": (_I32, [_P, _P, _P, _P, _I32, _P, _P]),
     "sugg_fit": (_I32, [_P, _P, _P, _P, _P]),
     "sugg_predict": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
     "sugg_rank_suggest": (_I32, [_P, _I32, _P, _P, _I32, _I32, _I32, C.c_double, _P, _P, _P, _P]),

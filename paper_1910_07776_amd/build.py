@@ -33,8 +33,16 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    hs += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(src), _headers_mtime()):
+        return obj
     cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -57,16 +65,18 @@ def _build_versions() -> str:
     return VERSIONS_BIN
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
     """Compile every source and link the shared library (and the profiled-
-    versions program); returns the library's path."""
+    versions program); returns the library's path.  incremental: recompile
+    only sources older than their object (or than any header)."""
     os.makedirs(OBJDIR, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(min(int(os.environ.get("MAX_JOBS", "8")), len(srcs) + 1)) as ex:
-        vfut = ex.submit(_build_versions)
-        objs = list(ex.map(_compile, srcs))
-        vfut.result()
+        vfut = ex.submit(_build_versions) if not (incremental and os.path.exists(VERSIONS_BIN)) else None
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
+        if vfut:
+            vfut.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -79,5 +89,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -391,7 +391,7 @@ int32_t sugg_create(sugg_ctx** out, int32_t device, const sugg_params* params) {
     c->params = *params;
   }
   if (hipSetDevice(device) != hipSuccess || hipMalloc((void**)&c->d_status, sizeof(int32_t)) != hipSuccess ||
-      hipMemset(c->d_status, 0, sizeof(int32_t)) != hipSuccess) {
+      hipMemset(c->d_status, 0, sizeof(int32_t)) != hipSuccess || noalloc_scratch_setup(device) != SUGG_OK) {
     delete c;
     return SUGG_E_HIP;
   }
@@ -542,8 +542,15 @@ void sugg_plan_destroy(sugg_plan* plan) {
 int64_t sugg_plan_rows(const sugg_plan* plan) { return plan ? plan->N : -1; }
 int32_t sugg_plan_max_opts(const sugg_plan* plan) { return plan ? plan->Bmax : -1; }
 
-int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
-                           int32_t mode, void* z_out, hipStream_t stream) {
+}  // extern "C"
+
+// sugg_load_features and its variant without allocation: with partial ==
+// nullptr the column-statistics partials go to the plan's workspace and the
+// model storage is (re)allocated as needed; otherwise they go to `partial`
+// (a device buffer of at least 2 * E * stat_chunks doubles) and the call
+// allocates nothing, so the model storage must already hold E columns.
+int load_features_core(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles, int32_t mode,
+                       void* z_out, hipStream_t stream, double* partial) {
   if (!ctx) return SUGG_E_ARG;
   if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
   if (mode & ~(SUGG_FIT_STATS | SUGG_APPLY | SUGG_BASELINE) || mode == 0 ||
@@ -555,16 +562,23 @@ int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* cou
   int rc = SUGG_OK;
   if (mode & SUGG_FIT_STATS) {
     if (p->N == 0) return ctx->fail(SUGG_E_SHAPE, "statistics need at least one row");
-    rc = ctx->ensure_model(p->E, (ctx->has_model && ctx->E == p->E) ? ctx->D : 0);
-    if (!rc) rc = ensure_stat_ws(ctx, p);
-    if (rc) return rc;
+    if (partial) {
+      if (!ctx->mu64 || ctx->E != p->E)
+        return ctx->fail(SUGG_E_STATE, "model storage for E=%d not set up (one sugg_load_features, sugg_fit or "
+                         "sugg_model_set of this E first)", p->E);
+    } else {
+      rc = ctx->ensure_model(p->E, (ctx->has_model && ctx->E == p->E) ? ctx->D : 0);
+      if (!rc) rc = ensure_stat_ws(ctx, p);
+      if (rc) return rc;
+      partial = p->d_stat_partial;
+    }
     if (p->dtype == SUGG_F32)
-      rc = ctx->hip(launch_colstats<float>((const float*)counters, (const float*)cycles, p->N, p->E, p->d_stat_partial,
+      rc = ctx->hip(launch_colstats<float>((const float*)counters, (const float*)cycles, p->N, p->E, partial,
                                            p->stat_chunks, ctx->mu64, ctx->sig64, ctx->mu32, ctx->isg32,
                                            ctx->d_status, stream), "column statistics");
     else
       rc = ctx->hip(launch_colstats<double>((const double*)counters, (const double*)cycles, p->N, p->E,
-                                            p->d_stat_partial, p->stat_chunks, ctx->mu64, ctx->sig64, ctx->mu64,
+                                            partial, p->stat_chunks, ctx->mu64, ctx->sig64, ctx->mu64,
                                             ctx->isg64, ctx->d_status, stream), "column statistics");
     if (rc) return rc;
     (void)hipGetLastError();
@@ -601,6 +615,13 @@ int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* cou
     }
   }
   return rc;
+}
+
+extern "C" {
+
+int32_t sugg_load_features(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
+                           int32_t mode, void* z_out, hipStream_t stream) {
+  return load_features_core(ctx, plan, counters, cycles, mode, z_out, stream, nullptr);
 }
 
 int32_t sugg_fit(sugg_ctx* ctx, const sugg_plan* train, const void* counters, const void* cycles, hipStream_t stream) {

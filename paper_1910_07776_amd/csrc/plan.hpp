@@ -30,6 +30,14 @@ struct ServeWs {
 };
 
 int mlp_infer(sugg_ctx* ctx, sugg_mlp* m, const float* x, int B, float* y, hipStream_t s);
+struct sugg_plan;
+// sugg_load_features with the column-statistics partials in `partial` (null:
+// the plan's workspace, allocated on first use) (api.cpp)
+int load_features_core(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles, int32_t mode,
+                       void* z_out, hipStream_t stream, double* partial);
+// looks up, once per device, the address of the library's static scratch
+// array on the current device (noalloc.hip); SUGG_OK or SUGG_E_HIP
+int noalloc_scratch_setup(int device);
 void mlp_dims(const sugg_mlp* m, int* in, int* out, int* max_batch);
 
 struct sugg_plan {

@@ -148,6 +148,21 @@ def load_features(ctx: Context, plan: Plan, counters, cycles, fit_stats: bool = 
     return z
 
 
+def load_features_noalloc(ctx: Context, plan: Plan, counters, cycles, fit_stats: bool = False,
+                          apply: bool = True, baseline: bool = False, z=None):
+    """load_features through the entry point that allocates no device memory
+    (statistics partials in the library's static scratch); z (optional) is a
+    preallocated output, so the call itself allocates nothing."""
+    plan.check_inputs(counters, cycles)
+    mode = (A.SUGG_FIT_STATS if fit_stats else 0) | (A.SUGG_APPLY if apply else 0) | \
+        (A.SUGG_BASELINE if baseline else 0)
+    if apply and z is None:
+        z = torch.empty((plan.K if baseline else plan.N, plan.E), dtype=plan.dtype, device=ctx.device)
+    A.check(ctx.h, A.lib().sugg_load_features_noalloc(ctx.h, plan.h, _ptr(counters), _ptr(cycles), mode,
+                                                      _ptr(z), _stream()))
+    return z
+
+
 def fit(ctx: Context, plan: Plan, counters, cycles):
     """Tier 2 training on every before/after pair of the plan's kernels."""
     plan.check_inputs(counters, cycles)
