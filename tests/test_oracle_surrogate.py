@@ -104,3 +104,81 @@ def test_bf16_round_ties_to_even():
     assert M.bf16_round(3.14159) == 3.140625
     assert M.bf16_round(-2.0 ** -130) == -2.0 ** -130        # subnormal kept exactly
     assert math.isnan(M.bf16_round(np.nan))
+
+
+def test_adam_constant_gradient_steps_lr_every_step():
+    """With a constant gradient g, the moments after t steps are
+    (1 - beta1^t) g and (1 - beta2^t) g^2, so the bias-corrected estimates are
+    g and g^2 at every step and each update moves a parameter by exactly
+    -lr g / (|g| + eps): a bias correction with the wrong power of beta at
+    t >= 2 would shrink or grow these steps."""
+    params = [(np.array([[0.25, -1.5]]), np.array([3.0]))]
+    g = [(np.array([[0.3, -2.0]]), np.array([1e-3]))]
+    st = M.adam_init(params)
+    p = params
+    for t in range(1, 7):
+        new = M.adam_step(p, g, st, lr=1e-2)
+        for (W, b), (nW, nb), (gW, gb) in zip(p, new, g):
+            np.testing.assert_allclose(nW - W, -1e-2 * gW / (np.abs(gW) + 1e-8), rtol=1e-9)
+            np.testing.assert_allclose(nb - b, -1e-2 * gb / (np.abs(gb) + 1e-8), rtol=1e-9)
+        p = new
+        assert st["t"] == t
+
+
+def test_adam_three_steps_hand_worked():
+    """Gradients 1, -1, 2 on one parameter (beta 0.9 / 0.999, lr 1e-3,
+    eps 1e-8), worked by hand in exact fractions:
+      t=1: m = 1/10,      v = 1/1000;           m/(1-0.9)   = 1,       v/(1-0.999)     = 1
+      t=2: m = -1/100,    v = 1999/10^6;        m/(1-0.81)  = -1/19,   v/(1-0.998001)  = 1
+      t=3: m = 191/1000,  v = 5997001/10^9;     m/(1-0.729) = 191/271, v/(1-0.997002999) = 5997001/2997001
+    so the parameter moves by -1e-3 * 1/(1 + 1e-8), then +1e-3 * (1/19)/(1 + 1e-8),
+    then -1e-3 * (191/271)/(sqrt(5997001/2997001) + 1e-8)."""
+    steps = [-1e-3 * 1.0 / (1.0 + 1e-8),
+             1e-3 * (1.0 / 19.0) / (1.0 + 1e-8),
+             -1e-3 * (191.0 / 271.0) / (math.sqrt(5997001.0 / 2997001.0) + 1e-8)]
+    p = [(np.array([[0.5]]), np.array([0.0]))]
+    st = M.adam_init(p)
+    want = 0.5
+    for g, d in zip((1.0, -1.0, 2.0), steps):
+        p = M.adam_step(p, [(np.array([[g]]), np.array([0.0]))], st, lr=1e-3)
+        want += d
+        assert abs(p[0][0][0, 0] - want) <= 1e-15, (st["t"], p[0][0][0, 0], want)
+    # the second and third moments by themselves
+    assert abs(st["m"][0][0][0, 0] - 0.191) <= 1e-16
+    assert abs(st["v"][0][0][0, 0] - 5997001e-9) <= 2e-17
+
+
+def test_backward_full_size_network_sampled_central_differences():
+    """The 128 -> 512 -> 512 -> 64 network itself: the hand-written
+    gradient of 24 sampled coordinates (four of every weight and bias
+    tensor, including the largest-gradient entry of each) against FP64
+    central differences, h = 1e-6."""
+    rng = np.random.default_rng(31)
+    params = M.init_params(rng, (128, 512, 512, 64))
+    x = rng.normal(size=(4, 128))
+    tgt = rng.normal(0.1, 0.3, size=(4, 64))
+
+    def loss(ps):
+        return M.mse(M.forward(ps, x)[0], tgt)[0]
+
+    y, cache = M.forward(params, x)
+    _, dy = M.mse(y, tgt)
+    grads = M.backward(params, cache, dy)
+    h = 1e-6
+    checked = 0
+    for li in range(3):
+        for j in range(2):
+            arr, g = params[li][j], grads[li][j]
+            flat, gf = arr.reshape(-1), g.reshape(-1)
+            picks = [int(np.argmax(np.abs(gf)))] + [int(i) for i in rng.choice(flat.size, 3, replace=False)]
+            for idx in picks:
+                old = flat[idx]
+                flat[idx] = old + h
+                lp = loss(params)
+                flat[idx] = old - h
+                lm = loss(params)
+                flat[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(gf[idx] - fd) <= 1e-6 * abs(fd) + 1e-10, (li, j, idx, gf[idx], fd)
+                checked += 1
+    assert checked == 24
