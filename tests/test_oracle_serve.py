@@ -34,6 +34,27 @@ def test_hand_worked_two_bit_kernel():
     assert fb
 
 
+def test_kept_answer_obeys_the_threshold_and_the_plain_order():
+    """Tier 3's contract on a kept answer (Section 2: only choices above the
+    threshold, sorted by expected benefit), judged by the plain values."""
+    # S=3 is listed (surrogate 0.12) and within the tolerance of its plain
+    # value 0.048, which is not above tau = 0.04879: fall back
+    fb, ans, _ = V.serve_kernel([0.0, 0.20, 0.01, 0.12], [0.0, 0.25, 0.02, 0.048], n=3)
+    assert fb and ans == [(1, 0.25)]
+    # the same with plain 0.049 (above tau): kept
+    fb, ans, _ = V.serve_kernel([0.0, 0.20, 0.01, 0.12], [0.0, 0.25, 0.02, 0.049], n=3)
+    assert not fb and ans == [(1, 0.25), (3, 0.049)]
+    # listed 3 before 1, but the plain values order them 1 before 3: fall back
+    fb, ans, _ = V.serve_kernel([0.0, 0.20, 0.01, 0.30], [0.0, 0.29, 0.02, 0.22], n=3)
+    assert fb and ans == [(1, 0.29), (3, 0.22)]
+    # equal plain values: the smaller subset first, so listing 3 before 1 falls back
+    fb, _, _ = V.serve_kernel([0.0, 0.20, 0.01, 0.30], [0.0, 0.25, 0.02, 0.25], n=3)
+    assert fb
+    # a band subset (S=2, surrogate 0.01) whose plain value 0.06 is above tau
+    fb, ans, _ = V.serve_kernel([0.0, 0.20, 0.01, 0.30], [0.0, 0.25, 0.06, 0.28], n=3)
+    assert fb and ans == [(3, 0.28), (1, 0.25), (2, 0.06)]
+
+
 def test_band_is_below_threshold_and_ascending():
     sur = [0.0, -0.06, 0.0, 0.04, 0.2, -0.2, 0.03, 0.049]
     listed = [S for S, _ in P.rank(sur, TAU, 3, first=1)]
@@ -81,4 +102,8 @@ def test_kept_answers_are_confirmed_by_the_plain_values():
             assert [S for S, _ in ans] == listed
             assert all(abs(sur[S] - t[S]) <= 0.1 and v == t[S] for S, v in ans)
             assert set(listed) <= set(judged)
+            # the kept answer is Tier 3's ranking of the plain values over the judged subsets
+            sub = np.full(t.shape, -np.inf)
+            sub[judged] = t[judged]
+            assert ans == P.rank(sub, TAU, 3, first=1)
     assert kept > 0
