@@ -256,11 +256,15 @@ SUGG_API int32_t sugg_greedy(sugg_ctx* ctx, const sugg_plan* plan, const void* c
  *      with SUGG_BASELINE), 2. the surrogate's table, 3. its top n_suggest
  *      above tau, 4. the threshold band of short lists (sugg_band_select, at
  *      most cap subsets), 5. the judge of the listed and band subsets
- *      against the plain composed values, 6. the plain fused path for the
- *      kernels flagged (difference above tol, or band overflow).
+ *      against the plain composed values, 6. Tier 3's contract checked on
+ *      the plain values (every listed subset above tau, the list in
+ *      descending plain order with equal values by smaller subset, no band
+ *      subset above tau), 7. the plain fused path for the kernels flagged
+ *      (difference above tol, band overflow, or a broken contract).
  * idx_out [K x n] / score_out [K x n] / count_out [K]: the answer (subsets of
- * the surrogate's list with their plain values, or the plain answer where
- * flagged); flag_out [K]: 1 where the plain path answered.  A learned
+ * the surrogate's list with their plain values, which is then Tier 3's
+ * ranking of the plain values over the judged subsets, or the plain answer
+ * where flagged); flag_out [K]: 1 where the plain path answered.  A learned
  * surrogate is an extension of the paper's Tier 2, which stays the judge.
  * The plan keeps a workspace for its queries (allocated on its first call,
  * not inside a graph capture). */
@@ -386,6 +390,13 @@ SUGG_API int32_t sugg_mlp_create(sugg_ctx* ctx, int32_t in, int32_t hidden, int3
                                  sugg_mlp** out_mlp);
 SUGG_API void sugg_mlp_destroy(sugg_mlp* mlp);
 SUGG_API int64_t sugg_mlp_param_count(const sugg_mlp* mlp);
+/* The matrix-core kernel instances the object's last forward and backward
+ * launched, host array info [8 x 4]: rows are the forward's layers 1-3, then
+ * the backward's dW3, dA2, dW2, dA1, dW1 products; columns are workgroup tile
+ * rows, tile columns, K splits, and 1 where the variant without bounds
+ * checks ran (zeros for a product not launched yet).  Lets a caller (a
+ * test) see which instances a given batch size exercises. */
+SUGG_API int32_t sugg_mlp_launch_info(const sugg_mlp* mlp, int32_t* info);
 /* Keeps a copy of params for inference (sugg_serve_query): the BF16 working
  * weights are packed from it once, and again only after another call
  * packed other parameters. */

@@ -67,6 +67,7 @@ SIGNATURES = {
     "sugg_judge": (_I32, [_P, _P, _P, _P, _P, _I32, _P, _P, C.c_double, _P, _I32, _P]),
     "sugg_band_select": (_I32, [_P, _I32, _P, _P, _I32, _I32, _P, _P, _I32, C.c_double, C.c_double, _I32, _P,
                                 _P, _P, _P]),
+    "sugg_mlp_launch_info": (_I32, [_P, _PI32]),
     "sugg_mlp_freeze": (_I32, [_P, _P, _P, _P]),
     "sugg_serve_query": (_I32, [_P, _P, _P, _P, _P, C.c_double, C.c_double, _I32, _P, _P, _P, _P, _P]),
     "sugg_predict_allpaths": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),

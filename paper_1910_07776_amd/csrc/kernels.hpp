@@ -115,6 +115,10 @@ template <typename T>
 hipError_t launch_band(const T* scores, const int64_t* seg_off, int32_t nseg, int32_t skip_head,
                        const int32_t* top_idx, const int32_t* top_count, int32_t n, double lo, int32_t C,
                        int32_t* cand_out, T* ref_out, int32_t* flag_out, hipStream_t s);
+// serving: flag kernels whose kept answer breaks Tier 3's contract by the plain values
+hipError_t launch_confirm(int32_t K, int32_t n, const int32_t* idx, const float* plain, const int32_t* count,
+                          const int32_t* band_idx, const float* band_plain, int32_t C, float tau, int32_t* flag,
+                          hipStream_t s);
 
 // FP64 column statistics of x = ln(c / cyc) over all N rows.
 template <typename T>
@@ -242,7 +246,9 @@ struct GemmArgs {
   float scale;           // dY = scale * (Y - T)
 };
 
-hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s);
+// info (nullable, 4 ints): the launched instance as (tile rows, tile columns,
+// K splits, 1 if the variant without bounds checks ran)
+hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s, int32_t* info = nullptr);
 hipError_t launch_pack(const float* src, int rows, int cols, __bf16* dst, int ldd, __bf16* dst_t, int ldt,
                        hipStream_t s);
 hipError_t launch_splitk_sum(const float* part, int64_t n, int splits, float* out, hipStream_t s);

@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256, 3) gemm_nt_kernel(const GemmArgs g) {
 }
 
 template <int EPI, int TM, int TN>
-void launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s) {
+void launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
   const dim3 grid((g.N + 64 * TN - 1) / (64 * TN), (g.M + 64 * TM - 1) / (64 * TM), splits);
   // every split's K range non-empty and a whole number of stages
   const bool ex = g.M % (64 * TM) == 0 && g.N % (64 * TN) == 0 && g.K > 0 && g.K % kKStep == 0 &&
@@ -180,28 +180,34 @@ void launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s) {
                   reinterpret_cast<uintptr_t>(g.Bt) % 16 == 0;
   if (ex) hipLaunchKernelGGL((gemm_nt_kernel<EPI, TM, TN, true>), grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL((gemm_nt_kernel<EPI, TM, TN, false>), grid, dim3(256), 0, s, g);
+  if (info) {
+    info[0] = 64 * TM;
+    info[1] = 64 * TN;
+    info[2] = splits;
+    info[3] = ex ? 1 : 0;
+  }
 }
 
 template <int EPI>
-void launch_gemm_e(const GemmArgs& g, int splits, hipStream_t s) {
+void launch_gemm_e(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
   // largest tile that still gives at least 256 workgroups; the loss partials
   // of a training forward are laid out per 64 x 64 tile
   const int64_t t22 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * splits;
   const int64_t t21 = (int64_t)((g.N + 63) / 64) * ((g.M + 127) / 128) * splits;
-  if (EPI == kEpiFwdOut && g.target) launch_gemm_t<EPI, 1, 1>(g, splits, s);
-  else if (t22 >= 256) launch_gemm_t<EPI, 2, 2>(g, splits, s);
-  else if (t21 >= 256) launch_gemm_t<EPI, 2, 1>(g, splits, s);
-  else launch_gemm_t<EPI, 1, 1>(g, splits, s);
+  if (EPI == kEpiFwdOut && g.target) launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
+  else if (t22 >= 256) launch_gemm_t<EPI, 2, 2>(g, splits, s, info);
+  else if (t21 >= 256) launch_gemm_t<EPI, 2, 1>(g, splits, s, info);
+  else launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
 }
 
-hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s) {
+hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s, int32_t* info) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   (void)hipGetLastError();  // report only this launch's status
   switch (epi) {
-    case kEpiWgrad: launch_gemm_e<kEpiWgrad>(g, splits, s); break;
-    case kEpiFwdHidden: launch_gemm_e<kEpiFwdHidden>(g, splits, s); break;
-    case kEpiFwdOut: launch_gemm_e<kEpiFwdOut>(g, splits, s); break;
-    default: launch_gemm_e<kEpiBwdHidden>(g, splits, s); break;
+    case kEpiWgrad: launch_gemm_e<kEpiWgrad>(g, splits, s, info); break;
+    case kEpiFwdHidden: launch_gemm_e<kEpiFwdHidden>(g, splits, s, info); break;
+    case kEpiFwdOut: launch_gemm_e<kEpiFwdOut>(g, splits, s, info); break;
+    default: launch_gemm_e<kEpiBwdHidden>(g, splits, s, info); break;
   }
   return hipGetLastError();
 }

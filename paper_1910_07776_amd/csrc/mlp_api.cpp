@@ -25,6 +25,7 @@ struct sugg_mlp {
   int64_t part_n = 0;
   float* frozen = nullptr;      // inference copy of the parameters (sugg_mlp_freeze)
   bool packed_frozen = false;   // the BF16 working weights hold the frozen parameters
+  int32_t info[8][4] = {};   // launched GEMM instances: forward layers 1-3, then the backward's five
   int kept_batch = -1;    // batch of the last forward that kept activations
   bool have_dy = false;   // dY of that batch is in dy/dyt (from sugg_mlp_loss)
   ~sugg_mlp() {
@@ -59,13 +60,13 @@ GemmArgs gemm(const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, int N,
 
 // weight gradient dW[M x N] = A[M x K] . Bt[N x K]^T with K split across workgroups
 hipError_t wgrad(sugg_mlp* m, const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, int N, int K, float* dW,
-                 hipStream_t s) {
+                 hipStream_t s, int32_t* info) {
   GemmArgs g = gemm(A, lda, Bt, ldb, M, N, K);
   const int sp = splits_for(M, N, K);
   g.k_per_split = ((K + sp - 1) / sp + 31) / 32 * 32;
   const int used = (K + g.k_per_split - 1) / g.k_per_split;
   g.Cf = m->part;
-  hipError_t e = launch_gemm(g, kEpiWgrad, used, s);
+  hipError_t e = launch_gemm(g, kEpiWgrad, used, s, info);
   if (e != hipSuccess) return e;
   return launch_splitk_sum(m->part, (int64_t)M * N, used, dW, s);
 }
@@ -98,7 +99,7 @@ int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int
   g.ldcb = hid;
   g.Ct = keep ? m->h1t : nullptr;
   g.ldct = bm;
-  e = launch_gemm(g, kEpiFwdHidden, 1, s);
+  e = launch_gemm(g, kEpiFwdHidden, 1, s, m->info[0]);
   if (e != hipSuccess) return ctx->hip(e, "mlp layer 1");
   g = gemm(m->h1, hid, m->w2, hid, B, hid, hid);
   g.bias = params + m->off_b2;
@@ -108,7 +109,7 @@ int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int
   g.ldcb = hid;
   g.Ct = keep ? m->h2t : nullptr;
   g.ldct = bm;
-  e = launch_gemm(g, kEpiFwdHidden, 1, s);
+  e = launch_gemm(g, kEpiFwdHidden, 1, s, m->info[1]);
   if (e != hipSuccess) return ctx->hip(e, "mlp layer 2");
   g = gemm(m->h2, hid, m->w3, hid, B, out, hid);
   g.bias = params + m->off_b3;
@@ -124,7 +125,7 @@ int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int
     g.loss_part = m->loss_part;
     g.scale = 2.0f / ((float)B * (float)out);
   }
-  e = launch_gemm(g, kEpiFwdOut, 1, s);
+  e = launch_gemm(g, kEpiFwdOut, 1, s, m->info[2]);
   if (e != hipSuccess) return ctx->hip(e, "mlp layer 3");
   if (target) {
     const int tiles = ((B + 63) / 64) * ((out + 63) / 64);
@@ -139,7 +140,7 @@ int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int
 int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grads, hipStream_t s) {
   (void)params;
   const int in = m->in, hid = m->hid, out = m->out, bm = m->bm;
-  hipError_t e = wgrad(m, m->dyt, bm, m->h2t, bm, out, hid, B, grads + m->off_w3, s);
+  hipError_t e = wgrad(m, m->dyt, bm, m->h2t, bm, out, hid, B, grads + m->off_w3, s, m->info[3]);
   if (e == hipSuccess) e = launch_rowsum(m->dyt, out, B, bm, grads + m->off_b3, s);
   if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 3");
   GemmArgs g = gemm(m->dy, out, m->w3t, out, B, hid, out);
@@ -149,8 +150,8 @@ int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grad
   g.ldcb = hid;
   g.Ct = m->da2t;
   g.ldct = bm;
-  e = launch_gemm(g, kEpiBwdHidden, 1, s);
-  if (e == hipSuccess) e = wgrad(m, m->da2t, bm, m->h1t, bm, hid, hid, B, grads + m->off_w2, s);
+  e = launch_gemm(g, kEpiBwdHidden, 1, s, m->info[4]);
+  if (e == hipSuccess) e = wgrad(m, m->da2t, bm, m->h1t, bm, hid, hid, B, grads + m->off_w2, s, m->info[5]);
   if (e == hipSuccess) e = launch_rowsum(m->da2t, hid, B, bm, grads + m->off_b2, s);
   if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 2");
   g = gemm(m->da2, hid, m->w2t, hid, B, hid, hid);
@@ -158,8 +159,8 @@ int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grad
   g.ldg = hid;
   g.Ct = m->da1t;
   g.ldct = bm;
-  e = launch_gemm(g, kEpiBwdHidden, 1, s);
-  if (e == hipSuccess) e = wgrad(m, m->da1t, bm, m->xt, bm, hid, in, B, grads + m->off_w1, s);
+  e = launch_gemm(g, kEpiBwdHidden, 1, s, m->info[6]);
+  if (e == hipSuccess) e = wgrad(m, m->da1t, bm, m->xt, bm, hid, in, B, grads + m->off_w1, s, m->info[7]);
   if (e == hipSuccess) e = launch_rowsum(m->da1t, hid, B, bm, grads + m->off_b1, s);
   if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 1");
   return SUGG_OK;
@@ -252,6 +253,13 @@ void sugg_mlp_destroy(sugg_mlp* mlp) {
 }
 
 int64_t sugg_mlp_param_count(const sugg_mlp* mlp) { return mlp ? mlp->nparam : -1; }
+
+int32_t sugg_mlp_launch_info(const sugg_mlp* mlp, int32_t* info) {
+  if (!mlp || !info) return SUGG_E_ARG;
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 4; ++j) info[4 * i + j] = mlp->info[i][j];
+  return SUGG_OK;
+}
 
 int32_t sugg_mlp_freeze(sugg_ctx* ctx, sugg_mlp* mlp, const float* params, hipStream_t stream) {
   if (!ctx) return SUGG_E_ARG;

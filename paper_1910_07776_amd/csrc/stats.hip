@@ -333,6 +333,42 @@ hipError_t launch_band(const T* scores, const int64_t* seg_off, int32_t nseg, in
   return hipGetLastError();
 }
 
+// Tier 3's contract on a served kernel's kept answer (Section 2: only choices
+// above the threshold, sorted by expected benefit), judged by the plain
+// values: each listed subset's plain value above tau, the list in descending
+// plain order (equal values: smaller subset first), and no band subset's
+// plain value above tau.  A kernel that breaks it is flagged (flags already
+// set stay set).  One thread per kernel.
+__global__ void confirm_kernel(int K, int n, const int32_t* __restrict__ idx, const float* __restrict__ plain,
+                               const int32_t* __restrict__ count, const int32_t* __restrict__ band_idx,
+                               const float* __restrict__ band_plain, int C, float tau, int32_t* flag) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K || flag[k]) return;
+  const int cnt = count[k] < n ? count[k] : n;
+  bool bad = false;
+  for (int i = 0; i < cnt; ++i) {
+    const float v = plain[(int64_t)k * n + i];
+    bad |= !(v > tau);
+    if (i > 0) {
+      const float u = plain[(int64_t)k * n + i - 1];
+      bad |= !(u > v || (u == v && idx[(int64_t)k * n + i - 1] < idx[(int64_t)k * n + i]));
+    }
+  }
+  for (int j = 0; j < C; ++j)
+    if (band_idx[(int64_t)k * C + j] >= 0) bad |= band_plain[(int64_t)k * C + j] > tau;
+  if (bad) flag[k] = 1;
+}
+
+hipError_t launch_confirm(int32_t K, int32_t n, const int32_t* idx, const float* plain, const int32_t* count,
+                          const int32_t* band_idx, const float* band_plain, int32_t C, float tau, int32_t* flag,
+                          hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  (void)hipGetLastError();  // report only this launch's status
+  hipLaunchKernelGGL(confirm_kernel, dim3((K + 255) / 256), dim3(256), 0, s, K, n, idx, plain, count, band_idx,
+                     band_plain, C, tau, flag);
+  return hipGetLastError();
+}
+
 #define SUGG_INST(T)                                                                                     \
   template hipError_t launch_colstats<T>(const T*, const T*, int64_t, int32_t, double*, int32_t, double*, \
                                          double*, T*, T*, int32_t*, hipStream_t);                         \
