@@ -2,19 +2,23 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
 
-A step is one whole scoring pass over one batch of 512 profiled kernels x 64
-versions (all subsets of 6 optimisations) x 128 FP32 counter events:
-cycle-normalised features, per-optimisation ridge predictions, subset
-composition and top-3 ranking above the 1.05x threshold (one persistent HIP
-kernel).  32 distinct batches are resident in HBM (540 MB, more than the
-256 MB last-level cache) and the timed steps cycle through them from a
-captured hipGraph; the model is fitted beforehand on 512 other kernels.
+A step is one whole scoring pass over the ragged batch of 16,384 profiled
+kernels with 4-10 of 10 optimisations each (all 2^B versions of every kernel,
+4,821,136 versions in all) x 128 FP32 counter events, resident in HBM
+(2.5 GB): cycle-normalised features, per-optimisation ridge predictions,
+subset composition and top-3 ranking above the 1.05x threshold in one
+persistent HIP kernel, replayed from a captured hipGraph.  W untimed passes,
+then exactly K timed ones; the model is fitted beforehand on 16,384 other
+kernels.
 
 Printed: one JSON line.  value = candidate speedup predictions (subset-table
 entries, kernel x S != 0) per second; suggestions/s = kernels ranked per
 second.  roofline = the scoring kernel's algorithmic bytes per launch over its
-average duration in the timed region.  cpu_baseline = the FP64 oracle on the
-host cores on one batch.
+average duration in the timed region (HIP events on its stream).
+cpu_baseline = the FP64 oracle on the host cores over the same 16,384
+kernels.  Further sections (each with its own rates and, where it has one,
+the oracle timed beside it): the 512-kernel x 64-version batch, IBK, all-paths
+and greedy, M5P, real MI355X profiles, the learned surrogate, serving.
 """
 from __future__ import annotations
 
@@ -48,14 +52,14 @@ def path_bytes(N, E, K, n, table=True, tsize=4):
 KERNEL_SRC = os.path.join(ROOT, "paper_1910_07776_amd", "csrc", "path_impl.hpp")
 
 
-def measured_traffic(kernel: str = "path_kernel"):
+def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of the scoring kernel from rocprofv3 FETCH_SIZE and
     WRITE_SIZE (scaled by a 1 GiB copy's readings), recorded in profiles/ with
-    the fused kernel source's hash; None if the kernel changed since or is
-    another form (the split form has no record)."""
+    the fused kernel source's hash; None if the kernel changed since or no
+    record exists for this form and workload."""
     import hashlib
     try:
-        path = os.path.join(ROOT, "profiles", f"{kernel}_512x64x128_traffic.txt")
+        path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
         kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
@@ -76,8 +80,14 @@ def cpu_model() -> str:
     return "unknown CPU"
 
 
-def cpu_baseline(model_o, batch, budget_s=12.0):
+def blas_threads() -> int:
     from threadpoolctl import threadpool_info
+    return int(max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1]))
+
+
+def cpu_baseline(model_o, batch, budget_s=12.0, what="the batch"):
+    """The FP64 oracle (grid, composition, ranking) repeated on ``batch`` for
+    about budget_s seconds: subset-table entries per second."""
     from oracle import plain as P
     reps, t0 = 0, time.perf_counter()
     while True:
@@ -86,21 +96,21 @@ def cpu_baseline(model_o, batch, budget_s=12.0):
         dt = time.perf_counter() - t0
         if dt >= budget_s or reps >= 200:
             break
-    entries = reps * len(batch.nopts) * ((1 << B) - 1)
-    threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    return {"value": entries / dt, "unit": "predictions/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"FP64 numpy oracle (grid, composition, ranking) on one 512-kernel batch, "
-                      f"{reps} repetitions in {dt:.1f} s; BLAS threads {threads} of {os.cpu_count()} host CPUs "
-                      f"({cpu_model()})"}
+    entries = reps * int(sum((1 << int(b)) - 1 for b in batch.nopts))
+    threads = blas_threads()
+    return {"value": entries / dt, "unit": "predictions/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 numpy oracle (grid, composition, ranking) on {what}, {reps} repetitions in "
+                      f"{dt:.1f} s; BLAS threads {threads} of {os.cpu_count()} host CPUs ({cpu_model()})"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3200)
-    ap.add_argument("--warmup", type=int, default=320)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--plain512", action="store_true", help="also run the 512-kernel section with --no-extra")
     ap.add_argument("--ibk", action="store_true", help="also run the IBK section with --no-extra")
     ap.add_argument("--paths", action="store_true", help="also run the all-paths/greedy section with --no-extra")
     ap.add_argument("--serving", action="store_true", help="also run the serving section with --no-extra")
@@ -112,7 +122,7 @@ def main():
     ap.add_argument("--retune", action="store_true",
                     help="re-run the autotuner for every plan and rewrite the tuning database")
     ap.add_argument("--ragged-only", action="store_true",
-                    help="only the 16,384-kernel ragged measurement (for profiling it alone)")
+                    help="only the 16,384-kernel ragged measurement, no CPU leg (for profiling it alone)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="only run N device-to-device copies of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -136,23 +146,59 @@ def main():
     from paper_1910_07776_amd import plain as G
     if args.ragged_only:
         ctx = G.Context(0)
-        print(json.dumps({"ragged_16384": ragged_extra(G, ctx, torch.device("cuda", 0))}), flush=True)
+        res = ragged_headline(G, ctx, torch.device("cuda", 0), max(1, args.steps), max(0, args.warmup), no_cpu=True)
+        print(json.dumps(finite({"ragged_16384": res})), flush=True)
         return
 
-    steps = max(N_BATCHES, (args.steps + N_BATCHES - 1) // N_BATCHES * N_BATCHES)
-    warm = (args.warmup + N_BATCHES - 1) // N_BATCHES
+    steps, warm = max(1, args.steps), max(0, args.warmup)
     dev = torch.device("cuda", 0)
+    ctx = G.Context(0)
+    head = ragged_headline(G, ctx, dev, steps, warm, no_cpu=args.no_cpu)
+    cpu = head.pop("cpu_baseline", None)
+    out = {
+        "metric": METRIC, "value": head.pop("value"), "unit": "predictions/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": head.pop("ms_per_step"), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": head.pop("config"),
+        "suggestions_per_s": head.pop("suggestions_per_s"),
+        "roofline": head.pop("roofline"),
+    }
+    out.update(head)
 
-    log("generating inputs")
+    log("generating the 512-kernel batches")
     train = make_batch(1910, range(10 ** 6, 10 ** 6 + K_BATCH), E, D)
     test = make_batch(1910, range(K_BATCH * N_BATCHES), E, D)
+    if not args.no_extra or args.plain512:
+        out["plain_512x64"] = plain512_extra(G, dev, train, test, no_cpu=args.no_cpu)
+    if not args.no_extra or args.ibk:
+        out["ibk"] = ibk_extra(G, dev, train, test)
+    if not args.no_extra or args.paths:
+        out["paths"] = paths_extra(G, G.Context(0), dev, train)
+    if not args.no_extra or args.m5p:
+        out["m5p"] = m5p_extra(G, dev, train, test, no_cpu=args.no_cpu)
+    if not args.no_extra or args.real:
+        out["real_profiles"] = real_extra(G, dev)
+    if not args.no_extra or args.surrogate:
+        out["surrogate"] = surrogate_extra(G, dev, no_cpu=args.no_cpu)
+    if not args.no_extra or args.serving:
+        out["serving"] = serving_extra(G, dev)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(finite(out)), flush=True)
+
+
+def plain512_extra(G, dev, train, test, no_cpu=False):
+    """512 kernels x 64 versions x 128 FP32 events (all subsets of 6
+    optimisations), 32 distinct resident batches (540 MB, more than the
+    256 MB last-level cache) replayed from one captured hipGraph of 32
+    passes; the model fitted on 512 other kernels."""
+    import torch
     nb_rows = K_BATCH << B
     ctx = G.Context(0)
     ptr = G.Plan(ctx, train.nopts, train.opt_ids, E, D)
     tc, tcy = torch.from_numpy(train.counters).to(dev), torch.from_numpy(train.cycles).to(dev)
     G.fit(ctx, ptr, tc, tcy)
     G.sync(ctx)
-    # GPU fit time (column statistics, features, Gram, Cholesky)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     for _ in range(10):
@@ -160,7 +206,6 @@ def main():
     ev1.record()
     G.sync(ctx)
     fit_ms = ev0.elapsed_time(ev1) / 10
-
     cnt_all = torch.from_numpy(test.counters).to(dev)
     cyc_all = torch.from_numpy(test.cycles).to(dev)
     plan = G.Plan(ctx, test.nopts[:K_BATCH], test.opt_ids[:K_BATCH * D], E, D)
@@ -172,8 +217,6 @@ def main():
     views = [(cnt_all[i * nb_rows:(i + 1) * nb_rows], cyc_all[i * nb_rows:(i + 1) * nb_rows])
              for i in range(N_BATCHES)]
     tuned = tune(G, ctx, plan, *views[0], reps=10)
-    log(f"launch: {tuned['waves']} waves x unroll {tuned['unroll']} ({tuned['source']})")
-    # eager pass first (validates arguments), then capture all batches once
     for i in range(N_BATCHES):
         G.suggest(ctx, plan, *views[i], out=outs[i])
     G.sync(ctx)
@@ -182,72 +225,39 @@ def main():
         for i in range(N_BATCHES):
             G.suggest(ctx, plan, *views[i], out=outs[i])
     stream = torch.cuda.current_stream()
-    log(f"warmup {warm * N_BATCHES} steps")
-    for _ in range(warm):
+    for _ in range(10):
         g.launch()
     torch.cuda.synchronize()
-    log(f"timing {steps} steps")
+    reps = 100
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(steps // N_BATCHES):
+    for _ in range(reps):
         g.launch()
     e1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     G.sync(ctx)
-    gpu_ms = e0.elapsed_time(e1)
-    ms_per_step = gpu_ms / steps
-    entries = K_BATCH * ((1 << B) - 1)
-    value = entries * steps / (gpu_ms / 1e3)
-    sugg_rate = K_BATCH * steps / (gpu_ms / 1e3)
+    us = e0.elapsed_time(e1) / (reps * N_BATCHES) * 1e3
     by = path_bytes(nb_rows, E, K_BATCH, n)
-    achieved = by / (ms_per_step / 1e3) / 1e9
     kernel = "path_split_kernel" if tuned.get("unroll") == 0 else "path_kernel"
-    log(f"{ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s, wall {wall:.2f} s")
     timing = pass_timing(G, ctx, plan, views, outs, g, stream)
     accuracy = plain_accuracy(outs[0]["table"].cpu().numpy().astype(np.float64), test, K_BATCH)
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "predictions/s", "n_gpus": 1, "steps": steps,
-        "warmup": warm * N_BATCHES, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "plain method, 512 kernels x 64 versions x 128 FP32 events, top-3 per kernel",
-                   "kernels_per_step": K_BATCH, "versions_per_kernel": 1 << B, "events": E,
-                   "distinct_resident_batches": N_BATCHES, "launch": "hipGraph of 32 passes",
-                   "autotuned": {k: tuned[k] for k in ("waves", "unroll", "source", "times_ms") if k in tuned}},
-        "suggestions_per_s": sugg_rate,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel),
-                     "kernel": kernel, "bytes_per_launch": by},
-        "fit_ms": fit_ms,
-        "pass_timing": timing,
-        "accuracy": accuracy,
-    }
-
-    if not args.no_extra or args.ibk:
-        out["ibk"] = ibk_extra(G, dev, train, test)
-    if not args.no_extra or args.paths:
-        out["paths"] = paths_extra(G, ctx, dev)
-    if not args.no_extra or args.m5p:
-        out["m5p"] = m5p_extra(G, dev, train, test, no_cpu=args.no_cpu)
-    if not args.no_extra or args.real:
-        out["real_profiles"] = real_extra(G, dev)
-    if not args.no_extra:
-        out["ragged_16384"] = ragged_extra(G, ctx, dev)
-    if not args.no_extra or args.surrogate:
-        out["surrogate"] = surrogate_extra(G, dev)
-    if not args.no_extra or args.serving:
-        out["serving"] = serving_extra(G, dev)
-
-    if not args.no_cpu:
-        log("cpu baseline (oracle)")
+    res = {"workload": "512 kernels x 64 versions x 128 FP32 events, top-3 per kernel",
+           "us_per_pass": us, "predictions_per_s": K_BATCH * ((1 << B) - 1) / (us * 1e-6),
+           "suggestions_per_s": K_BATCH / (us * 1e-6), "launch": "hipGraph of 32 passes over 32 resident batches",
+           "autotuned": {k: tuned[k] for k in ("waves", "unroll", "source", "times_ms") if k in tuned},
+           "roofline": {"bound": "hbm", "achieved": by / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": measured_traffic(kernel, "512x64x128"), "kernel": kernel,
+                        "bytes_per_launch": by},
+           "fit_ms": fit_ms, "pass_timing": timing, "accuracy": accuracy}
+    log(f"512-kernel batch: {us:.2f} us/pass, {res['roofline']['achieved']:.0f} GB/s")
+    if not no_cpu:
         from oracle import plain as P
         om = P.fit(train, D)
-        one = P.SubBatch(test, range(K_BATCH))
-        out["cpu_baseline"] = cpu_baseline(om, one)
-    print(json.dumps(finite(out)), flush=True)
+        res["cpu_oracle"] = cpu_baseline(om, P.SubBatch(test, range(K_BATCH)), budget_s=8.0,
+                                         what="one 512-kernel batch")
+    ctx.close()
+    return res
 
 
 def finite(x):
@@ -285,12 +295,14 @@ def tune(G, ctx, plan, c, cy, reps):
     return cfg
 
 
-def paths_extra(G, ctx, dev, reps: int = 50):
+def paths_extra(G, ctx, dev, train, reps: int = 50):
     """All-paths composition and greedy re-profiling on 512 kernels x 64
-    versions x 128 events (the headline batch; the linear model fitted on the
-    512 training kernels)."""
+    versions x 128 events (the linear model fitted on the 512 training
+    kernels)."""
     import torch
     from synthgen import make_batch
+    G.fit(ctx, G.Plan(ctx, train.nopts, train.opt_ids, E, D), torch.from_numpy(train.counters).to(dev),
+          torch.from_numpy(train.cycles).to(dev))
     one = make_batch(1910, range(K_BATCH), E, D)
     plan = G.Plan(ctx, one.nopts, one.opt_ids, E, D)
     c, cy = torch.from_numpy(one.counters).to(dev), torch.from_numpy(one.cycles).to(dev)
@@ -559,14 +571,17 @@ def _depth(t):
     return int(d.max())
 
 
-def ragged_extra(G, ctx, dev):
-    """The 16,384-kernel ragged batch (4-10 of 10 optimisations, 4.8M versions,
-    2.5 GB of counters) in one persistent launch."""
+def ragged_headline(G, ctx, dev, steps, warm, no_cpu=False):
+    """The ragged batch: 16,384 kernels with 4-10 of 10 optimisations (B
+    uniform, ids a sorted random subset), 4,821,136 versions x 128 FP32
+    events (2.5 GB), one persistent launch per pass replayed from a captured
+    hipGraph; the model is fitted on 16,384 other kernels of the same world.
+    warm untimed passes, then exactly ``steps`` timed ones."""
     import torch
     from synthgen import make_batch
     log("ragged batch: generating 2 x 16384 kernels")
-    tr = make_batch(1910, range(10 ** 6, 10 ** 6 + 16384), 128, 10, brange=(4, 10))
-    ptr = G.Plan(ctx, tr.nopts, tr.opt_ids, 128, 10)
+    tr = make_batch(1910, range(10 ** 6, 10 ** 6 + 16384), E, 10, brange=(4, 10))
+    ptr = G.Plan(ctx, tr.nopts, tr.opt_ids, E, 10)
     c, cy = torch.from_numpy(tr.counters).to(dev), torch.from_numpy(tr.cycles).to(dev)
     G.fit(ctx, ptr, c, cy)
     G.sync(ctx)
@@ -576,9 +591,10 @@ def ragged_extra(G, ctx, dev):
     e1.record()
     G.sync(ctx)
     fit_ms = e0.elapsed_time(e1)
+    tr_ids = [int(tr.kernel_ids[0]), int(tr.kernel_ids[-1]) + 1]
     del c, cy, ptr, tr
-    te = make_batch(1910, range(16384), 128, 10, brange=(4, 10))
-    plan = G.Plan(ctx, te.nopts, te.opt_ids, 128, 10)
+    te = make_batch(1910, range(16384), E, 10, brange=(4, 10))
+    plan = G.Plan(ctx, te.nopts, te.opt_ids, E, 10)
     c, cy = torch.from_numpy(te.counters).to(dev), torch.from_numpy(te.cycles).to(dev)
     n = ctx.params["n_suggest"]
     out = {"idx": torch.empty((te.K, n), dtype=torch.int32, device=dev),
@@ -592,28 +608,77 @@ def ragged_extra(G, ctx, dev):
     g = G.Graph(ctx)
     with g.capture():
         G.suggest(ctx, plan, c, cy, out=out)
-    for _ in range(3):
+    stream = torch.cuda.current_stream()
+    log(f"warmup {warm} passes")
+    for _ in range(warm):
         g.launch()
-    reps = 20
     torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
+    log(f"timing {steps} passes")
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
         g.launch()
-    e1.record()
+    e1.record(stream)
     torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     G.sync(ctx)
-    ms = e0.elapsed_time(e1) / reps
+    ms = e0.elapsed_time(e1) / steps
+    # per-pass distribution (one replay each, events on the scoring stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for a, b in ev:
+        a.record(stream)
+        g.launch()
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in ev])
     entries = int(te.N - te.K)
-    by = path_bytes(te.N, 128, te.K, n)
+    by = path_bytes(te.N, E, te.K, n)
     gbs = by / (ms / 1e3) / 1e9
-    log(f"ragged: {ms:.3f} ms/pass, {gbs:.0f} GB/s")
-    return {"kernels": te.K, "versions": int(te.N), "ms_per_pass": ms,
-            "predictions_per_s": entries / (ms / 1e3), "suggestions_per_s": te.K / (ms / 1e3),
-            "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_pass": by, "fit_ms": fit_ms,
-            "autotuned": {k: tuned[k] for k in ("waves", "unroll", "source", "times_ms") if k in tuned}}
+    kernel = "path_split_kernel" if tuned.get("unroll") == 0 else "path_kernel"
+    log(f"ragged: {ms:.3f} ms/pass, {gbs:.0f} GB/s, wall {wall:.2f} s")
+    table = out["table"].cpu().numpy().astype(np.float64)
+    bs = np.bincount(te.nopts, minlength=11)
+    res = {"value": entries / (ms / 1e3), "ms_per_step": ms, "suggestions_per_s": te.K / (ms / 1e3),
+           "config": {"workload": "ragged batch: 16,384 kernels x 4-10 of 10 optimisations (all 2^B versions, "
+                                  f"{te.N:,} in all) x 128 FP32 counter events, top-3 subsets per kernel",
+                      "kernels": te.K, "versions": int(te.N), "events": E, "global_optimisations": 10,
+                      "kernels_per_B": {str(b): int(bs[b]) for b in range(4, 11)},
+                      "launch": "one persistent launch per pass, replayed from a hipGraph",
+                      "autotuned": {k: tuned[k] for k in ("waves", "unroll", "source", "times_ms") if k in tuned}},
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kernel, "ragged_16384"),
+                        "kernel": kernel, "bytes_per_launch": by},
+           "pass_ms_p10_p50_p90": [float(np.percentile(per, q)) for q in (10, 50, 90)],
+           "fit_ms": fit_ms,
+           "accuracy": plain_accuracy(table, te, te.K)}
+    if not no_cpu:
+        from oracle import plain as P
+        log("cpu baseline: the oracle over all 16,384 kernels")
+        om = oracle_model_ragged(tr_ids)
+        t0 = time.perf_counter()
+        for c0 in range(0, te.K, 2048):
+            P.run(om, P.SubBatch(te, range(c0, min(te.K, c0 + 2048))))
+        dt = time.perf_counter() - t0
+        th = blas_threads()
+        res["cpu_baseline"] = {"value": entries / dt, "unit": "predictions/s", "cores": th, "kind": "oracle",
+                               "sample": f"FP64 numpy oracle (grid, composition, ranking) over all 16,384 kernels "
+                                         f"({te.N:,} versions) in 2048-kernel chunks, one run of {dt:.1f} s; BLAS "
+                                         f"threads {th} of {os.cpu_count()} host CPUs ({cpu_model()}); model fitted "
+                                         f"by the oracle on the training kernels (not timed)"}
+    ctx.close()
+    return res
 
 
-def surrogate_extra(G, dev):
+def oracle_model_ragged(tr_ids):
+    """The oracle's fit on the ragged training kernels: the stored one
+    (written by tests/golden/make_golden.py, which calls only the oracle)."""
+    path = os.path.join(ROOT, "tests", "golden", "ragged16384_model.json")
+    gold = json.load(open(path))
+    assert gold["train_ids"] == list(tr_ids), "stored fit of other kernels"
+    return {k: np.asarray(gold[k]) for k in ("mu", "sigma", "W", "counts")} | {"lam": 1e-2}
+
+
+def surrogate_extra(G, dev, no_cpu=False):
     """The learned surrogate (MLP 128-512-512-64, BF16 matrix cores): trained
     on 1M kernels labelled by the plain path until its speedup MAPE on 64K
     held-out kernels is within 1.02x of the plain composed table's, then
@@ -709,10 +774,65 @@ def surrogate_extra(G, dev):
     }
     log(f"surrogate: {res['surrogate_predictions_per_s']:.3e} vs plain {res['plain_predictions_per_s']:.3e} "
         f"predictions/s; MAPE {m_sur:.4f} vs {m_plain:.4f}; forward {res['forward_tflops']:.1f} TFLOP/s")
+    if not no_cpu:
+        res["cpu_oracle"] = surrogate_cpu_legs(mlp, tr, counters, cycles, K)
     inf.close()
     mlp.close()
     ctx.close()
     return res
+
+
+def surrogate_cpu_legs(mlp, tr, counters, cycles, K, slice_k: int = 2048):
+    """The FP64 oracle beside the surrogate's GPU figures: (1) training, one
+    forward + backward of the 128-512-512-64 network on a 4,096-sample slice,
+    extrapolated to a 2^20-sample epoch; (2) the 65,536-kernel comparison,
+    plain path (grid, composition, ranking) and the surrogate's forward on the
+    first ``slice_k`` kernels of that batch, rates per subset-table entry."""
+    from oracle import plain as P
+    from oracle import surrogate as M
+    th = blas_threads()
+    u = mlp.unflatten(mlp.params.cpu().numpy().astype(np.float64))
+    op = [(u["W1"].T, u["b1"]), (u["W2"].T, u["b2"]), (u["W3"].T, u["b3"])]
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(4096, E))
+    t = rng.normal(0.1, 0.3, size=(4096, 1 << B))
+    t0 = time.perf_counter()
+    y, cache = M.forward(op, x)
+    _, dy = M.mse(y, t)
+    M.backward(op, cache, dy)
+    dt_train = time.perf_counter() - t0
+    om = P.fit(tr, D)
+    n = slice_k
+    hb = _UniformHostBatch(counters[:n << B].cpu().numpy(), cycles[:n << B].cpu().numpy(), n, B)
+    t0 = time.perf_counter()
+    P.run(om, hb)
+    dt_plain = time.perf_counter() - t0
+    z0 = P.standardize(P.features(hb.counters[hb.row_off[:-1]], hb.cycles[hb.row_off[:-1]]), om["mu"], om["sigma"])
+    t0 = time.perf_counter()
+    M.forward_bf16(op, z0)
+    dt_sur = time.perf_counter() - t0
+    entries = n * ((1 << B) - 1)
+    return {"training": {"value": 4096 / dt_train, "unit": "training samples/s (forward + backward)",
+                         "cores": th, "kind": "oracle",
+                         "sample": f"FP64 numpy forward + backward of one 4,096-sample batch in {dt_train:.2f} s; "
+                                   f"extrapolated epoch of 2^20 samples {dt_train * 256:.0f} s"},
+            "plain": {"value": entries / dt_plain, "unit": "predictions/s", "cores": th, "kind": "oracle",
+                      "sample": f"FP64 numpy oracle on the first {n} of the {K} comparison kernels, {dt_plain:.1f} s"},
+            "surrogate_forward": {"value": entries / dt_sur, "unit": "predictions/s", "cores": th, "kind": "oracle",
+                                  "sample": f"FP64 numpy forward (bfloat16 rounding points) of the same {n} kernels' "
+                                            f"baseline rows, {dt_sur:.2f} s"},
+            "host": f"BLAS threads {th} of {os.cpu_count()} host CPUs ({cpu_model()})"}
+
+
+class _UniformHostBatch:
+    """K kernels of B optimisations (ids 0..B-1) in host arrays, for the oracle."""
+
+    def __init__(self, counters, cycles, K, Bk):
+        self.nopts = np.full(K, Bk, np.int64)
+        self.opt_ids = np.tile(np.arange(Bk, dtype=np.int64), K)
+        self.opt_off = np.arange(K + 1, dtype=np.int64) * Bk
+        self.row_off = np.arange(K + 1, dtype=np.int64) << Bk
+        self.counters, self.cycles = counters, cycles
 
 
 def serving_extra(G, dev, n_queries: int = 10000):

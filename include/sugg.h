@@ -300,7 +300,8 @@ SUGG_API void sugg_graph_destroy(sugg_graph* graph);
  * paper's "mode" of real-valued labels read as their mean; equal distances:
  * the earlier stored sample, samples stored kernel by kernel, then by
  * version).  The IBK model lives beside the linear one in the context.
- * E <= 128.  Distances are evaluated in FP32, labels averaged in FP64.
+ * E <= 256.  Candidate distances are evaluated in FP32, the final ones in
+ * FP64, labels averaged in FP64.
  *
  * sugg_ibk_fit: column statistics of the training rows (as sugg_load_features
  *   FIT_STATS, kept with the IBK model), their standardised vectors, and the
@@ -314,10 +315,17 @@ SUGG_API void sugg_graph_destroy(sugg_graph* graph);
  *   (else SUGG_E_UNTRAINED_OPT).  A plan's first IBK call per output form
  *   (with or without the grid) builds and uploads its query lists and
  *   allocates its workspace (not inside a graph capture); later calls only
- *   enqueue kernels. */
+ *   enqueue kernels.
+ *   The neighbours are exact: the FP32 search keeps k plus a margin of
+ *   candidates (at least 6), which are re-ranked by FP64 distance between
+ *   FP64 standardised features; where a bound on the FP32 error cannot
+ *   certify that the k nearest are among them, the query is searched again
+ *   over all its samples in FP64 (sugg_ibk_exact_count reports how many were,
+ *   in the plan's last IBK call; synchronous). */
 SUGG_API int32_t sugg_ibk_fit(sugg_ctx* ctx, const sugg_plan* train, const void* counters, const void* cycles,
                               int32_t k, hipStream_t stream);
 SUGG_API int32_t sugg_ibk_counts(sugg_ctx* ctx, int64_t* counts, int32_t D);
+SUGG_API int32_t sugg_ibk_exact_count(sugg_ctx* ctx, const sugg_plan* plan, int64_t* n);
 SUGG_API int32_t sugg_ibk_predict(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
                                   void* grid_out, void* table_out, hipStream_t stream);
 SUGG_API int32_t sugg_ibk_suggest(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,

@@ -74,6 +74,7 @@ SIGNATURES = {
     "sugg_greedy": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "sugg_ibk_fit": (_I32, [_P, _P, _P, _P, _I32, _P]),
     "sugg_ibk_counts": (_I32, [_P, _P, _I32]),
+    "sugg_ibk_exact_count": (_I32, [_P, _P, _PI64]),
     "sugg_ibk_predict": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
     "sugg_ibk_suggest": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "sugg_m5p_fit": (_I32, [_P, _P, _P, _P, _I32, C.c_double, _P]),

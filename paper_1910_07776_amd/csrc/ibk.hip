@@ -123,6 +123,40 @@ hipError_t launch_ibk_gather(const float* Z, const int32_t* srow, int64_t Ns, in
   return hipGetLastError();
 }
 
+// ---- the FP32 rounding of the stored vectors, per column ----------------------
+// Non-negative floats order as their bit patterns, so a column maximum is an
+// unsigned maximum; each workgroup reduces its rows in LDS first.
+__global__ void __launch_bounds__(256) ibk_dz_kernel(const float* __restrict__ z32, int Epad,
+                                                     const double* __restrict__ z64, int64_t N, int E,
+                                                     uint32_t* __restrict__ out) {
+  __shared__ uint32_t m[256];
+  for (int j = threadIdx.x; j < E; j += blockDim.x) m[j] = 0u;
+  __syncthreads();
+  const int64_t total = N * E;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / E;
+    const int j = (int)(i - r * E);
+    const double d = fabs((double)z32[r * Epad + j] - z64[i]);
+    const float f = __builtin_isfinite(d) ? (float)d : INFINITY;
+    // round up so the float never understates the double
+    const float fu = (double)f < d ? __uint_as_float(__float_as_uint(f) + 1u) : f;   // next float up
+    atomicMax(&m[j], __float_as_uint(fu));
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < E; j += blockDim.x)
+    if (m[j]) atomicMax(&out[j], m[j]);
+}
+
+hipError_t launch_ibk_dz(const float* z32, int32_t Epad, const double* z64, int64_t N, int32_t E, uint32_t* out,
+                         hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  int64_t blocks = (N * E + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(ibk_dz_kernel, dim3((unsigned)blocks), dim3(256), 0, s, z32, (int)Epad, z64, N, (int)E, out);
+  return hipGetLastError();
+}
+
 // ---- the k-nearest-neighbour search ------------------------------------------
 // A lane's KT nearest samples so far, ascending by (distance, sample index),
 // in registers.  Insertion is a fixed compare-exchange pass (no indexing by
@@ -157,7 +191,7 @@ __device__ __forceinline__ void knn_insert(float (&ld)[KT], int (&li)[KT], float
 // l holds query (l mod 32)'s feature half h = l / 32: the matrix core's
 // k-slot h of step j carries feature h*EH + j, for samples (A) and queries
 // (B) alike, so the block product is the full dot product.
-template <int EH, int KT, typename T>
+template <int EH, int KT>
 __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
   constexpr int EP = 2 * EH;
   constexpr int LS = EP + 4;                           // padded LDS row (floats)
@@ -308,38 +342,21 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
 #pragma unroll
   for (int j = 0; j < KT; ++j)
     if (knn_better<KT>(od[j], oi[j], ld[KT - 1], li[KT - 1])) knn_insert<KT>(ld, li, od[j], oi[j]);
-  if (a.split > 1) {   // partial list of this share; merged by ibk_merge_kernel
-    if (h == 0 && qvalid) {
-      const int64_t base = ((int64_t)(q0 + qloc) * a.split + part) * kIbkList;
-#pragma unroll
-      for (int j = 0; j < kIbkList; ++j) {
-        a.part_d[base + j] = j < KT ? ld[j] : INFINITY;
-        a.part_i[base + j] = j < KT ? li[j] : INT_MAX;
-      }
-    }
-    return;
-  }
+  // the candidate list of this share (the whole database when split = 1):
+  // re-ranked in FP64 by ibk_refine_kernel after the shares are merged
   if (h == 0 && qvalid) {
-    // a non-finite query or sample (bad counters, reported through the status
-    // word) leaves slots unfilled: the prediction is then NaN, and no label
-    // is read outside the optimisation's samples
-    const int kk = a.k < ns ? a.k : ns;
-    double sum = 0.0;
-    bool full = true;
+    const int64_t base = ((int64_t)(q0 + qloc) * a.split + part) * kIbkList;
 #pragma unroll
-    for (int j = 0; j < KT; ++j)
-      if (j < kk) {
-        const bool ok = li[j] >= 0 && li[j] < ns;
-        full = full && ok;
-        sum += ok ? a.y[s0 + li[j]] : 0.0;
-      }
-    reinterpret_cast<T*>(a.out)[a.q_dst[q0 + qloc]] = full ? (T)(sum / (double)kk) : qnan<T>();
+    for (int j = 0; j < kIbkList; ++j) {
+      a.part_d[base + j] = j < KT ? ld[j] : INFINITY;
+      a.part_i[base + j] = j < KT ? li[j] : INT_MAX;
+    }
   }
 }
 
-// Merge of the partial lists of one query (one thread per query): the KT
-// nearest over all shares, then the mean of their labels.
-template <int KT, typename T>
+// Merge of the shares' candidate lists of one query (one thread per query):
+// the KT best by FP32 distance over all shares, written over share 0's list.
+template <int KT>
 __global__ void __launch_bounds__(256) ibk_merge_kernel(const IbkKnnArgs a) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q >= a.n_queries) return;
@@ -359,37 +376,251 @@ __global__ void __launch_bounds__(256) ibk_merge_kernel(const IbkKnnArgs a) {
       knn_insert<KT>(ld, li, d, s);
     }
   }
-  // the query's optimisation: the tile that holds it (tiles ascend in q)
+  const int64_t base = q * a.split * kIbkList;
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    a.part_d[base + j] = ld[j];
+    a.part_i[base + j] = li[j];
+  }
+}
+
+// The global optimisation of query q: the tile that holds it (tiles ascend in q).
+__device__ __forceinline__ int ibk_query_opt(const IbkKnnArgs& a, int64_t q) {
   int lo = 0, hi = a.n_tiles - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (a.tiles[mid * 4 + 1] <= q) lo = mid;
     else hi = mid - 1;
   }
-  const int o = a.tiles[lo * 4 + 0];
+  return a.tiles[lo * 4 + 0];
+}
+
+constexpr int kIbkMaxCols = 16;   // FP64 feature columns per lane (16 lanes x 16 = 256 events)
+
+// This lane's FP64 standardised features of plan row r, columns l16 + 16 i
+// (zero past E): z = (ln c - ln cyc - mu) / sigma, as the training rows.
+template <typename T>
+__device__ __forceinline__ void ibk_query64(const IbkKnnArgs& a, int64_t r, int l16, double (&q)[kIbkMaxCols]) {
+  const T* c = reinterpret_cast<const T*>(a.counters) + r * a.E;
+  const double lc = log((double)reinterpret_cast<const T*>(a.cycles)[r]);
+#pragma unroll
+  for (int i = 0; i < kIbkMaxCols; ++i) {
+    const int j = l16 + 16 * i;
+    q[i] = j < a.E ? (log((double)c[j]) - lc - a.mu64[j]) / a.sig64[j] : 0.0;
+  }
+}
+
+// FP64 squared distance between this lane group's query and training row
+// `row`, summed over the 16 lanes of the group (every lane receives it).
+__device__ __forceinline__ double ibk_dist64(const IbkKnnArgs& a, int32_t row, int l16,
+                                             const double (&q)[kIbkMaxCols]) {
+  const double* t = a.Z64 + (int64_t)row * a.E;
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < kIbkMaxCols; ++i) {
+    const int j = l16 + 16 * i;
+    if (j < a.E) {
+      const double d = q[i] - t[j];
+      acc = fma(d, d, acc);
+    }
+  }
+  return row_sum16(acc);
+}
+
+// Re-ranking (16 lanes per query): the KT FP32 candidates' exact FP64
+// distances, the k nearest of them by (distance, sample index), and the mean
+// of their labels.  Every sample outside the candidates has an FP32 distance
+// of at least the list's last, dlast; its FP64 distance then exceeds
+// dlast - err(dlast), err bounding the FP32 error (the features' FP32
+// rounding and the accumulation in |q|^2 + |t|^2 - 2 q.t), so when the k-th
+// FP64 distance lies below that the k nearest are certain.  Otherwise the
+// query goes to the queue of ibk_exact_kernel.
+template <typename T, int KT>
+__global__ void __launch_bounds__(256) ibk_refine_kernel(const IbkKnnArgs a) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15;
+  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  if (q >= a.n_queries) return;   // whole 16-lane groups leave together
+  const int o = ibk_query_opt(a, q);
   const int64_t s0 = a.off[o];
   const int ns = (int)(a.off[o + 1] - s0);
   const int kk = a.k < ns ? a.k : ns;
-  double sum = 0.0;
+  double qv[kIbkMaxCols];
+  ibk_query64<T>(a, a.q_src[q], l16, qv);
+  const int64_t base = q * a.split * kIbkList;
+  double dd[KT];
+  int di[KT];
+  float dlast = INFINITY;
   bool full = true;
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    const float d32 = a.part_d[base + j];
+    const int s = a.part_i[base + j];
+    const bool ok = s >= 0 && s < ns;
+    full = full && ok;
+    dlast = d32;
+    dd[j] = ok ? ibk_dist64(a, a.srow[s0 + s], l16, qv) : INFINITY;
+    di[j] = ok ? s : INT_MAX;
+  }
+  // selection of the k nearest (insertion, ties by the smaller sample index)
+#pragma unroll
+  for (int j = 1; j < KT; ++j) {
+#pragma unroll
+    for (int i = j; i > 0; --i) {
+      const bool sw = dd[i] < dd[i - 1] || (dd[i] == dd[i - 1] && di[i] < di[i - 1]);
+      const double td = dd[i - 1];
+      const int ti = di[i - 1];
+      dd[i - 1] = sw ? dd[i] : td;
+      di[i - 1] = sw ? di[i] : ti;
+      dd[i] = sw ? td : dd[i];
+      di[i] = sw ? ti : di[i];
+    }
+  }
+  double dk = 0.0, sum = 0.0;
+  bool have = true;
 #pragma unroll
   for (int j = 0; j < KT; ++j)
     if (j < kk) {
-      const bool ok = li[j] >= 0 && li[j] < ns;
-      full = full && ok;
-      sum += ok ? a.y[s0 + li[j]] : 0.0;
+      dk = dd[j];
+      have = have && di[j] != INT_MAX;
+      sum += di[j] != INT_MAX ? a.y[s0 + di[j]] : 0.0;
     }
-  reinterpret_cast<T*>(a.out)[a.q_dst[q]] = full ? (T)(sum / (double)kk) : qnan<T>();
+  // every sample is a candidate when the list is not full (ns < KT)
+  bool certain = !full || ns <= KT;
+  if (!certain && have) {
+    // Dz bounds the FP32 rounding of query minus sample vectors (the query's
+    // own, measured here, plus the stored vectors' worst); an outsider o
+    // with FP64 distance u <= dk would have an FP32 distance of at most
+    // g(u) = u + err(u) <= g(dk) < dlast and so be on the list
+    const float* zr = a.zq + (int64_t)a.q_src[q] * a.Epad;
+    double qn = 0.0, dq = 0.0;
+#pragma unroll
+    for (int i = 0; i < kIbkMaxCols; ++i) {
+      const int j = l16 + 16 * i;
+      qn = fma(qv[i], qv[i], qn);
+      if (j < a.E) {
+        const double e = (double)zr[j] - qv[i];
+        dq = fma(e, e, dq);
+      }
+    }
+    qn = row_sum16(qn);
+    dq = row_sum16(dq);
+    const double Dz = sqrt(dq) * (1.0 + 1e-12) + a.dt_norm;
+    const double rk = sqrt(dk), rq = sqrt(qn);
+    // FP32 sums of Epad products with |q32| + |t32| <= 2 |q| + sqrt(dk) + Dz
+    const double eps = 1.01 * (double)(a.Epad + 2) * 5.9604644775390625e-8;
+    const double span = 2.0 * rq + rk + Dz;
+    const double err = 2.0 * rk * Dz + Dz * Dz + eps * span * span + 1e-12 * (1.0 + dk);
+    certain = __builtin_isfinite((double)dlast) && __builtin_isfinite(err) && dk + err < (double)dlast;
+  }
+  if (l16 == 0) {
+    if (certain && have) {
+      reinterpret_cast<T*>(a.out)[a.q_dst[q]] = (T)(sum / (double)kk);
+    } else if (!certain) {
+      const int slot = atomicAdd(a.exact_n, 1);
+      a.exact_q[slot] = (int32_t)q;
+    } else {
+      reinterpret_cast<T*>(a.out)[a.q_dst[q]] = qnan<T>();
+    }
+  }
+}
+
+// FP64 search over every sample of the query's optimisation for the queries
+// whose candidates were not certain (queue from ibk_refine_kernel); one
+// workgroup per query, taken in turn; 16 groups of 16 lanes each keep the
+// k nearest of every 16th sample, merged by one thread at the end.
+template <typename T>
+__global__ void __launch_bounds__(256) ibk_exact_kernel(const IbkKnnArgs a) {
+  __shared__ double sd[16 * kIbkMaxK];
+  __shared__ int si[16 * kIbkMaxK];
+  const int tid = threadIdx.x, l16 = tid & 15, g = tid >> 4;
+  const int n = *a.exact_n;
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int64_t q = a.exact_q[w];
+    const int o = ibk_query_opt(a, q);
+    const int64_t s0 = a.off[o];
+    const int ns = (int)(a.off[o + 1] - s0);
+    const int kk = a.k < ns ? a.k : ns;
+    double qv[kIbkMaxCols];
+    ibk_query64<T>(a, a.q_src[q], l16, qv);
+    double ld[kIbkMaxK];
+    int li[kIbkMaxK];
+#pragma unroll
+    for (int j = 0; j < kIbkMaxK; ++j) {
+      ld[j] = INFINITY;
+      li[j] = INT_MAX;
+    }
+    for (int s = g; s < ns; s += 16) {   // uniform within the 16-lane group
+      const double d = ibk_dist64(a, a.srow[s0 + s], l16, qv);
+      if (d < ld[kIbkMaxK - 1] || (d == ld[kIbkMaxK - 1] && s < li[kIbkMaxK - 1])) {
+        ld[kIbkMaxK - 1] = d;
+        li[kIbkMaxK - 1] = s;
+#pragma unroll
+        for (int j = kIbkMaxK - 1; j > 0; --j) {
+          const bool sw = ld[j] < ld[j - 1] || (ld[j] == ld[j - 1] && li[j] < li[j - 1]);
+          const double td = ld[j - 1];
+          const int ti = li[j - 1];
+          ld[j - 1] = sw ? ld[j] : td;
+          li[j - 1] = sw ? li[j] : ti;
+          ld[j] = sw ? td : ld[j];
+          li[j] = sw ? ti : li[j];
+        }
+      }
+    }
+    if (l16 == 0)
+#pragma unroll
+      for (int j = 0; j < kIbkMaxK; ++j) {
+        sd[g * kIbkMaxK + j] = ld[j];
+        si[g * kIbkMaxK + j] = li[j];
+      }
+    __syncthreads();
+    if (tid == 0) {
+      // the k nearest of the 16 group lists: repeated minimum over the heads
+      int head[16];
+      for (int h = 0; h < 16; ++h) head[h] = 0;
+      double sum = 0.0;
+      bool ok = true;
+      for (int j = 0; j < kk; ++j) {
+        int best = -1;
+        for (int h = 0; h < 16; ++h) {
+          if (head[h] >= kIbkMaxK) continue;
+          const double d = sd[h * kIbkMaxK + head[h]];
+          const int i = si[h * kIbkMaxK + head[h]];
+          if (best < 0) {
+            best = h;
+            continue;
+          }
+          const double bd = sd[best * kIbkMaxK + head[best]];
+          const int bi = si[best * kIbkMaxK + head[best]];
+          if (d < bd || (d == bd && i < bi)) best = h;
+        }
+        const int i = si[best * kIbkMaxK + head[best]];
+        ok = ok && i != INT_MAX;
+        sum += i != INT_MAX ? a.y[s0 + i] : 0.0;
+        ++head[best];
+      }
+      reinterpret_cast<T*>(a.out)[a.q_dst[q]] = ok ? (T)(sum / (double)kk) : qnan<T>();
+    }
+    __syncthreads();   // the lists are read before the next query writes them
+  }
 }
 
 template <int EH, int KT, typename T>
 hipError_t launch_knn_kt(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
-  hipLaunchKernelGGL((ibk_knn_kernel<EH, KT, T>), dim3(n_tiles * a.split), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((ibk_knn_kernel<EH, KT>), dim3(n_tiles * a.split), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (a.split > 1) {
-    const hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL((ibk_merge_kernel<KT>), dim3((unsigned)((a.n_queries + 255) / 256)), dim3(256), 0, s, a);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((ibk_merge_kernel<KT, T>), dim3((unsigned)((a.n_queries + 255) / 256)), dim3(256), 0, s, a);
   }
+  e = launch_fill_i32(a.exact_n, 0, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((ibk_refine_kernel<T, KT>), dim3((unsigned)((a.n_queries * 16 + 255) / 256)), dim3(256), 0, s,
+                     a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((ibk_exact_kernel<T>), dim3(256), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -398,7 +629,7 @@ hipError_t launch_knn_kt(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
 template <int EH, int KT>
 int split_kt(int n_tiles, int cus) {
   int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(ibk_knn_kernel<EH, KT, float>),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(ibk_knn_kernel<EH, KT>),
                                                    256, 0) != hipSuccess || per < 1)
     per = 2;
   return n_tiles > 0 ? std::min(8, std::max(1, (per * cus + n_tiles - 1) / n_tiles)) : 1;
@@ -407,32 +638,34 @@ int split_kt(int n_tiles, int cus) {
 int ibk_split(int Epad, int k, int n_tiles, int cus) {
   auto by_k = [&](auto eh) -> int {
     constexpr int EH = decltype(eh)::value;
-    if (k <= 4) return split_kt<EH, 4>(n_tiles, cus);
-    if (k <= 8) return split_kt<EH, 8>(n_tiles, cus);
-    if (k <= 12) return split_kt<EH, 12>(n_tiles, cus);
-    return split_kt<EH, 16>(n_tiles, cus);
+    const int kt = ibk_kt(k);
+    if (kt == 8) return split_kt<EH, 8>(n_tiles, cus);
+    if (kt == 16) return split_kt<EH, 16>(n_tiles, cus);
+    return split_kt<EH, 24>(n_tiles, cus);
   };
   if (Epad == 32) return by_k(std::integral_constant<int, 16>{});
   if (Epad == 64) return by_k(std::integral_constant<int, 32>{});
-  return by_k(std::integral_constant<int, 64>{});
+  if (Epad == 128) return by_k(std::integral_constant<int, 64>{});
+  return by_k(std::integral_constant<int, 128>{});
 }
 
 template <int EH, typename T>
 hipError_t launch_knn_eh(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
-  if (a.k <= 4) return launch_knn_kt<EH, 4, T>(a, n_tiles, s);
-  if (a.k <= 8) return launch_knn_kt<EH, 8, T>(a, n_tiles, s);
-  if (a.k <= 12) return launch_knn_kt<EH, 12, T>(a, n_tiles, s);
-  return launch_knn_kt<EH, 16, T>(a, n_tiles, s);
+  if (a.kt == 8) return launch_knn_kt<EH, 8, T>(a, n_tiles, s);
+  if (a.kt == 16) return launch_knn_kt<EH, 16, T>(a, n_tiles, s);
+  return launch_knn_kt<EH, 24, T>(a, n_tiles, s);
 }
 
 template <typename T>
 hipError_t launch_ibk_knn(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
+  if (a.kt != ibk_kt(a.k) || a.E > 16 * kIbkMaxCols || a.k > kIbkMaxK) return hipErrorInvalidValue;
   (void)hipGetLastError();
   switch (a.Epad) {
     case 32: return launch_knn_eh<16, T>(a, n_tiles, s);
     case 64: return launch_knn_eh<32, T>(a, n_tiles, s);
     case 128: return launch_knn_eh<64, T>(a, n_tiles, s);
+    case 256: return launch_knn_eh<128, T>(a, n_tiles, s);
     default: return hipErrorInvalidValue;
   }
 }

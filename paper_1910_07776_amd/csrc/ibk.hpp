@@ -10,7 +10,8 @@
 
 namespace sugg {
 
-constexpr int kIbkList = 16;       // neighbours kept per query (k <= 16)
+constexpr int kIbkMaxK = 16;       // largest k
+constexpr int kIbkList = 24;       // FP32 candidates kept per query (k plus a margin, at most 24)
 constexpr int kIbkQueries = 128;   // queries per workgroup (4 waves x 32)
 constexpr int kIbkTile = 32;       // database samples per staged tile
 constexpr int kIbkQueue = 20;      // queued candidates per lane (at least 16, one tile's)
@@ -22,6 +23,10 @@ struct IbkModel {
   int E = 0, Epad = 0, D = 0, k = 10;
   int64_t Ntr = 0, Ns = 0;
   float* Z = nullptr;          // [Ns, Epad] FP32 sample vectors, columns >= E zero
+  double* Z64 = nullptr;       // [Ntr, E] FP64 standardised training rows (exact distances)
+  int32_t* srow = nullptr;     // [Ns] training row of each sample (its before version)
+  double dt_norm = 0.0;        // Euclidean norm over columns of max_rows |Z32 - Z64|: the
+                               //   FP32 rounding of any stored vector is at most this
   float* norm = nullptr;       // [Ns] their squared norms
   double* y = nullptr;         // [Ns] ln cyc(before) - ln cyc(after)
   int64_t* d_off = nullptr;    // [D+1]
@@ -52,9 +57,13 @@ struct IbkPlan {
   int Epad = 0;
   float* zq = nullptr;         // [N, Epad] standardised rows of the batch
   void* edges = nullptr;       // [N] plan dtype: chain-edge predictions
-  float* part_d = nullptr;     // partial neighbour lists when samples are split
+  float* part_d = nullptr;     // candidate lists of every query (per sample share when split)
   int32_t* part_i = nullptr;
   int64_t part_cap = 0;        // entries allocated
+  int32_t* exact_q = nullptr;  // queries whose FP32 candidates could not be certified, and
+  int32_t* exact_n = nullptr;  //   their count (device), searched again in FP64
+  int64_t exact_cap = 0;
+  int exact_mode = -1;         // output form of the last call (0 edges, 1 grid)
   IbkQueries q[2];
 };
 
@@ -69,12 +78,25 @@ struct IbkKnnArgs {
   const int32_t* tiles;
   int32_t Epad;
   int32_t k;
+  int32_t kt;                  // FP32 candidates kept per query (k plus a margin)
   int32_t split;               // sample partitions per query tile (workgroups per tile)
-  float* part_d;               // [queries, split, kIbkList] partial lists (split > 1)
+  float* part_d;               // [queries, split, kIbkList] candidate lists
   int32_t* part_i;
   int64_t n_queries;
   int32_t n_tiles;
   void* out;                   // plan dtype
+  // exact re-ranking: FP64 features of the queries (from the plan's counters)
+  // and of the samples (training rows), and the queue of uncertified queries
+  const void* counters;        // plan dtype [N, E]
+  const void* cycles;          // plan dtype [N]
+  int32_t E;
+  const double* mu64;
+  const double* sig64;
+  const double* Z64;           // [Ntr, E]
+  const int32_t* srow;         // [Ns]
+  double dt_norm;              // IbkModel::dt_norm
+  int32_t* exact_q;
+  int32_t* exact_n;
 };
 
 template <typename T>
@@ -88,8 +110,16 @@ hipError_t launch_ibk_gather(const float* Z, const int32_t* srow, int64_t Ns, in
 template <typename T>
 hipError_t launch_ibk_labels(const T* cycles, const int32_t* before, const int32_t* after, int64_t Ns,
                              double* y, hipStream_t s);
+// per column, the largest |z32 - z64| over the rows (as float bits, maxed into out[E])
+hipError_t launch_ibk_dz(const float* z32, int32_t Epad, const double* z64, int64_t N, int32_t E, uint32_t* out,
+                         hipStream_t s);
+// FP32 candidate search, re-ranking of the candidates by FP64 distance with a
+// certificate, and an FP64 search over every sample for the queries the
+// certificate does not cover; writes the mean label of the k nearest
 template <typename T>
 hipError_t launch_ibk_knn(const IbkKnnArgs& a, int n_tiles, hipStream_t s);
+// candidates kept per query for a given k
+inline int ibk_kt(int k) { return k <= 4 ? 8 : k <= 10 ? 16 : 24; }
 int ibk_split(int Epad, int k, int n_tiles, int cus);
 template <typename T>
 hipError_t launch_ibk_compose(const T* edges, const T* grid, int32_t grid_ld, const int64_t* row_off,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -16,7 +17,7 @@ using namespace sugg;
 
 void ibk_model_free(IbkModel*& m) {
   if (!m) return;
-  dfree(m->Z); dfree(m->norm); dfree(m->y); dfree(m->d_off);
+  dfree(m->Z); dfree(m->Z64); dfree(m->srow); dfree(m->norm); dfree(m->y); dfree(m->d_off);
   dfree(m->mu64); dfree(m->sig64); dfree(m->mu_t); dfree(m->isg_t);
   delete m;
   m = nullptr;
@@ -28,6 +29,8 @@ void ibk_plan_free(IbkPlan*& p) {
   dfree(p->edges);
   dfree(p->part_d);
   dfree(p->part_i);
+  dfree(p->exact_q);
+  dfree(p->exact_n);
   for (auto& q : p->q) {
     dfree(q.src); dfree(q.dst); dfree(q.tiles);
   }
@@ -38,7 +41,7 @@ void ibk_plan_free(IbkPlan*& p) {
 namespace {
 
 int ibk_epad(int E) {
-  for (int e : {32, 64, 128})
+  for (int e : {32, 64, 128, 256})
     if (E <= e) return e;
   return -1;
 }
@@ -84,7 +87,6 @@ int fit_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, int k, hipStrea
     hb.insert(hb.end(), bef[o].begin(), bef[o].end());
     ha.insert(ha.end(), aft[o].begin(), aft[o].end());
   }
-  int32_t* d_before = nullptr;
   int32_t* d_after = nullptr;
   double* partial = nullptr;
   float* zrows = nullptr;
@@ -98,7 +100,8 @@ int fit_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, int k, hipStrea
   if (e == hipSuccess) e = hipMalloc((void**)&zrows, sizeof(float) * (size_t)p->N * m->Epad);
   if (e == hipSuccess) e = hipMalloc((void**)&m->Z, sizeof(float) * (size_t)ns1 * m->Epad);
   if (e == hipSuccess) e = hipMalloc((void**)&m->norm, sizeof(float) * (size_t)ns1);
-  if (e == hipSuccess) e = upload_vec(d_before, hb);
+  if (e == hipSuccess) e = upload_vec(m->srow, hb);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->Z64, sizeof(double) * (size_t)std::max<int64_t>(p->N, 1) * E);
   if (e == hipSuccess) e = upload_vec(d_after, ha);
   if (e == hipSuccess) e = hipMalloc((void**)&m->y, sizeof(double) * ns1);
   if (e == hipSuccess) e = upload_vec(m->d_off, m->off);
@@ -108,11 +111,32 @@ int fit_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, int k, hipStrea
     e = launch_colstats<T>(c, cyc, p->N, E, partial, chunks, m->mu64, m->sig64, (T*)m->mu_t, (T*)m->isg_t,
                            ctx->d_status, s);
   if (e == hipSuccess) e = launch_ibk_z<T>(c, cyc, p->N, E, m->Epad, m->mu64, m->sig64, zrows, ctx->d_status, s);
-  if (e == hipSuccess) e = launch_ibk_gather(zrows, d_before, m->Ns, m->Epad, m->Z, s);
+  if (e == hipSuccess) e = launch_ibk_gather(zrows, m->srow, m->Ns, m->Epad, m->Z, s);
   if (e == hipSuccess) e = launch_ibk_norm(m->Z, m->Ns, m->Epad, m->norm, s);
-  if (e == hipSuccess) e = launch_ibk_labels<T>(cyc, d_before, d_after, m->Ns, m->y, s);
+  if (e == hipSuccess) e = launch_ibk_labels<T>(cyc, m->srow, d_after, m->Ns, m->y, s);
+  // FP64 standardised training rows for exact distances
+  double* lcyc = nullptr;
+  if (e == hipSuccess) e = hipMalloc((void**)&lcyc, sizeof(double) * (size_t)std::max<int64_t>(p->N, 1));
+  if (e == hipSuccess) e = launch_zfeat64<T>(c, cyc, p->N, E, m->mu64, m->sig64, m->Z64, lcyc, s);
+  // the largest FP32 rounding of each column of the stored vectors
+  uint32_t* dz = nullptr;
+  if (e == hipSuccess) e = hipMalloc((void**)&dz, sizeof(uint32_t) * E);
+  if (e == hipSuccess) e = hipMemsetAsync(dz, 0, sizeof(uint32_t) * E, s);
+  if (e == hipSuccess) e = launch_ibk_dz(zrows, m->Epad, m->Z64, p->N, E, dz, s);
+  std::vector<uint32_t> hdz(E, 0);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dfree(d_before);
+  if (e == hipSuccess) e = hipMemcpy(hdz.data(), dz, sizeof(uint32_t) * E, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) {
+    double acc = 0.0;
+    for (int j = 0; j < E; ++j) {
+      float f;
+      std::memcpy(&f, &hdz[j], sizeof f);
+      acc += (double)f * (double)f;
+    }
+    m->dt_norm = std::sqrt(acc) * (1.0 + 1e-12);
+  }
+  dfree(dz);
+  dfree(lcyc);
   dfree(d_after);
   dfree(partial);
   dfree(zrows);
@@ -233,6 +257,15 @@ int score_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, T* grid, T* t
   a.tiles = q.tiles;
   a.Epad = w->Epad;
   a.k = m->k;
+  a.kt = ibk_kt(m->k);
+  a.counters = c;
+  a.cycles = cyc;
+  a.E = p->E;
+  a.mu64 = m->mu64;
+  a.sig64 = m->sig64;
+  a.Z64 = m->Z64;
+  a.srow = m->srow;
+  a.dt_norm = m->dt_norm;
   a.out = grid ? (void*)grid : w->edges;
   a.n_queries = q.n;
   a.n_tiles = q.n_tiles;
@@ -242,21 +275,29 @@ int score_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, T* grid, T* t
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
     cus = 256;
   a.split = ibk_split(w->Epad, m->k, q.n_tiles, cus);
-  a.part_d = nullptr;
-  a.part_i = nullptr;
-  if (a.split > 1) {
-    const int64_t need = q.n * a.split * kIbkList;
-    if (w->part_cap < need) {
-      dfree(w->part_d);
-      dfree(w->part_i);
-      w->part_cap = 0;
-      if (e == hipSuccess) e = hipMalloc((void**)&w->part_d, sizeof(float) * need);
-      if (e == hipSuccess) e = hipMalloc((void**)&w->part_i, sizeof(int32_t) * need);
-      if (e == hipSuccess) w->part_cap = need;
-    }
-    a.part_d = w->part_d;
-    a.part_i = w->part_i;
+  const int64_t need = std::max<int64_t>(q.n, 1) * a.split * kIbkList;
+  if (w->part_cap < need) {
+    dfree(w->part_d);
+    dfree(w->part_i);
+    w->part_cap = 0;
+    if (e == hipSuccess) e = hipMalloc((void**)&w->part_d, sizeof(float) * need);
+    if (e == hipSuccess) e = hipMalloc((void**)&w->part_i, sizeof(int32_t) * need);
+    if (e == hipSuccess) w->part_cap = need;
   }
+  if (w->exact_cap < std::max<int64_t>(q.n, 1)) {
+    dfree(w->exact_q);
+    dfree(w->exact_n);
+    w->exact_cap = 0;
+    if (e == hipSuccess) e = hipMalloc((void**)&w->exact_q, sizeof(int32_t) * std::max<int64_t>(q.n, 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&w->exact_n, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(w->exact_n, 0, sizeof(int32_t));
+    if (e == hipSuccess) w->exact_cap = std::max<int64_t>(q.n, 1);
+  }
+  a.part_d = w->part_d;
+  a.part_i = w->part_i;
+  a.exact_q = w->exact_q;
+  a.exact_n = w->exact_n;
+  w->exact_mode = mode;
   if (e == hipSuccess) e = launch_ibk_knn<T>(a, q.n_tiles, s);
   if (e == hipSuccess)
     e = launch_ibk_compose<T>(grid ? nullptr : (const T*)w->edges, grid, p->Bmax, p->d_row_off, p->d_nopts, p->K,
@@ -280,8 +321,8 @@ int32_t sugg_ibk_fit(sugg_ctx* ctx, const sugg_plan* train, const void* counters
   if (!ctx) return SUGG_E_ARG;
   int rc = common_checks(ctx, train, counters, cycles);
   if (rc) return rc;
-  if (k < 1 || k > kIbkList) return ctx->fail(SUGG_E_ARG, "k must be in [1, %d]", kIbkList);
-  if (ibk_epad(train->E) < 0) return ctx->fail(SUGG_E_SHAPE, "IBK supports at most 128 events (E=%d)", train->E);
+  if (k < 1 || k > kIbkMaxK) return ctx->fail(SUGG_E_ARG, "k must be in [1, %d]", kIbkMaxK);
+  if (ibk_epad(train->E) < 0) return ctx->fail(SUGG_E_SHAPE, "IBK supports at most 256 events (E=%d)", train->E);
   if (train->N == 0) return ctx->fail(SUGG_E_SHAPE, "IBK needs at least one training row");
   if (train->N >= ((int64_t)1 << 31)) return ctx->fail(SUGG_E_BUDGET, "too many training rows for IBK");
   sugg_plan* p = const_cast<sugg_plan*>(train);
@@ -293,6 +334,21 @@ int32_t sugg_ibk_counts(sugg_ctx* ctx, int64_t* counts, int32_t D) {
   if (!ctx || !counts) return SUGG_E_ARG;
   if (!ctx->ibk) return ctx->fail(SUGG_E_STATE, "no IBK model");
   for (int o = 0; o < D; ++o) counts[o] = o < ctx->ibk->D ? ctx->ibk->off[o + 1] - ctx->ibk->off[o] : 0;
+  return SUGG_OK;
+}
+
+int32_t sugg_ibk_exact_count(sugg_ctx* ctx, const sugg_plan* plan, int64_t* n) {
+  if (!ctx || !n) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  *n = 0;
+  if (!plan->ibk || !plan->ibk->exact_n) return SUGG_OK;
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  int32_t v = 0;
+  const int rc = ctx->hip(hipDeviceSynchronize(), "synchronize");
+  if (rc) return rc;
+  const hipError_t e = hipMemcpy(&v, plan->ibk->exact_n, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return ctx->hip(e, "copy");
+  *n = v;
   return SUGG_OK;
 }
 

@@ -280,6 +280,14 @@ def ibk_counts(ctx: Context, D: int) -> np.ndarray:
     return out
 
 
+def ibk_exact_count(ctx: Context, plan: Plan) -> int:
+    """Queries of the plan's last IBK call whose FP32 candidates could not be
+    certified and were searched again over all samples in FP64."""
+    n = C.c_int64()
+    A.check(ctx.h, A.lib().sugg_ibk_exact_count(ctx.h, plan.h, C.byref(n)))
+    return int(n.value)
+
+
 def ibk_predict(ctx: Context, plan: Plan, counters, cycles, grid: bool = False):
     """Returns (table [N], grid [N, Bmax] or None) with IBK as Tier 2."""
     plan.check_inputs(counters, cycles)

@@ -1,8 +1,9 @@
 """GPU instance-based Tier 2 model (IBK, k nearest neighbours) against the
-FP64 oracle.  The GPU measures distances in FP32, so a query whose k-th and
-(k+1)-th nearest samples are closer than the FP32 rounding of a distance may
-legitimately pick either: those queries are counted and skipped; every other
-prediction must match to 1e-5 on the speedup scale."""
+FP64 oracle.  The GPU's neighbours are exact: its FP32 candidates are
+re-ranked by FP64 distance and certified (or searched again in FP64), so
+every neighbour set equals the oracle's and every prediction matches it to
+1e-5 on the speedup scale (FP32 outputs) or 1e-9 (FP64 outputs); no query is
+skipped.  The number of queries the library searched again is reported."""
 import numpy as np
 import pytest
 import torch
@@ -13,15 +14,6 @@ from oracle.checks import check_list
 from synthgen import make_batch
 
 pytestmark = pytest.mark.gpu
-
-RTOL = 1e-5
-
-
-def decided(d_k, d_k1):
-    """The k nearest are one set for any rounding of FP32 distances: the
-    (k+1)-th squared distance exceeds the k-th by more than the FP32 error of
-    |q|^2 + |t|^2 - 2 q.t over 128 standardised features (a few 1e-4)."""
-    return d_k1 - d_k > 5e-3 + 2e-5 * d_k
 
 
 @pytest.fixture(scope="module")
@@ -41,34 +33,16 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def oracle_grid_unique(db, batch, k, Bmax):
-    """Oracle grid plus a mask of entries whose neighbour set is unique."""
-    z = P.standardize(P.features(batch.counters, batch.cycles), db["mu"], db["sigma"])
-    grid = np.full((len(z), Bmax), np.nan)
-    uniq = np.zeros((len(z), Bmax), dtype=bool)
-    for kk in range(len(batch.nopts)):
-        B, r0 = int(batch.nopts[kk]), int(batch.row_off[kk])
-        ids = batch.opt_ids[int(batch.opt_off[kk]):int(batch.opt_off[kk + 1])]
-        for S in range(1 << B):
-            for b in range(B):
-                if (S >> b) & 1:
-                    continue
-                Z, y = db["Z"][int(ids[b])], db["y"][int(ids[b])]
-                idx, d2 = N.neighbours(Z, z[r0 + S], k + 1)
-                kk_ = min(k, len(Z))
-                grid[r0 + S, b] = float(np.mean(y[idx[:kk_]]))
-                uniq[r0 + S, b] = len(Z) <= k or decided(d2[k - 1], d2[k])
-    return grid, uniq
-
-
-def close(got, want):
-    return np.abs(np.exp(got) - np.exp(want)) <= RTOL * np.exp(want)
+def close(got, want, rtol):
+    return np.abs(np.exp(got) - np.exp(want)) <= rtol * np.exp(want)
 
 
 @pytest.mark.parametrize("dtype,E,k", [(torch.float32, 128, 10), (torch.float64, 128, 10),
-                                       (torch.float64, 40, 10), (torch.float32, 37, 3), (torch.float32, 96, 16)])
+                                       (torch.float64, 40, 10), (torch.float32, 37, 3), (torch.float32, 96, 16),
+                                       (torch.float32, 256, 10), (torch.float32, 200, 1)])
 def test_ibk_matches_oracle(G, ctx, dtype, E, k):
     npdt = np.float32 if dtype == torch.float32 else np.float64
+    rtol = 1e-5 if dtype == torch.float32 else 1e-9
     tr = make_batch(31, range(4000, 4048), E, 6, brange=(2, 6), dtype=npdt)
     te = make_batch(31, range(40), E, 6, brange=(0, 6), dtype=npdt)
     ptr = G.Plan(ctx, tr.nopts, tr.opt_ids, E, 6, dtype=dtype)
@@ -78,33 +52,29 @@ def test_ibk_matches_oracle(G, ctx, dtype, E, k):
     p = G.Plan(ctx, te.nopts, te.opt_ids, E, 6, dtype=dtype)
     c, cy = dev(te.counters), dev(te.cycles)
     table_g, grid = G.ibk_predict(ctx, p, c, cy, grid=True)
+    n_grid = G.ibk_exact_count(ctx, p)
     table_e, _ = G.ibk_predict(ctx, p, c, cy)
     idx, score, count, table_s = G.ibk_suggest(ctx, p, c, cy)
+    n_edges = G.ibk_exact_count(ctx, p)
     G.sync(ctx)
+    print(f"E={E} k={k} {dtype}: queries searched again in FP64: grid {n_grid}, edges {n_edges}")
     # the chain-edge form and the grid form run the same searches
     assert torch.equal(table_g, table_e) and torch.equal(table_s, table_e)
-    go, uniq = oracle_grid_unique(db, te, k, p.Bmax)
+    go = N.predict_grid(db, te, k, Bmax=p.Bmax)
     g = grid.cpu().numpy().astype(np.float64)
     pred = ~np.isnan(go)
     assert np.array_equal(~np.isnan(g), pred)
-    assert uniq[pred].mean() > 0.95, uniq[pred].mean()
-    ok = close(g[pred & uniq], go[pred & uniq])
-    assert ok.all(), np.flatnonzero(~ok)[:10]
-    # composed tables and suggestions where every chain edge is decided
+    ok = close(g[pred], go[pred], rtol)
+    assert ok.all(), (np.flatnonzero(~ok)[:10], g[pred][~ok][:5], go[pred][~ok][:5])
+    # every composed table and suggestion list
     to = P.compose(go, te)
     t = table_e.cpu().numpy().astype(np.float64)
+    assert close(t, to, rtol).all()
     idx, score, count = idx.cpu().numpy(), score.cpu().numpy(), count.cpu().numpy()
-    checked = 0
     for kk in range(te.K):
-        B, r0 = int(te.nopts[kk]), int(te.row_off[kk])
-        if not all(uniq[r0 + S, b] for S in range(1 << B) for b in range(B) if not (S >> b) & 1):
-            continue
-        checked += 1
-        assert close(t[r0:r0 + (1 << B)], to[r0:r0 + (1 << B)]).all(), kk
-        errs = check_list(idx[kk, :count[kk]], score[kk, :count[kk]], to[r0:r0 + (1 << B)], P.TAU, 3, 1e-5,
-                          first=1)
+        r0, r1 = int(te.row_off[kk]), int(te.row_off[kk + 1])
+        errs = check_list(idx[kk, :count[kk]], score[kk, :count[kk]], to[r0:r1], P.TAU, 3, rtol, first=1)
         assert not errs, (kk, errs)
-    assert checked >= te.K // 4   # kernels with every prediction decided (small B mostly)
 
 
 def test_one_neighbour_returns_the_training_labels(G, ctx):
@@ -120,35 +90,31 @@ def test_one_neighbour_returns_the_training_labels(G, ctx):
     np.testing.assert_allclose(g[before, b], y.astype(np.float32), rtol=1e-6, atol=1e-7)
 
 
-def test_ibk_full_size_sampled(G, ctx):
+def test_ibk_full_size(G, ctx):
     """512 training and 512 test kernels of 64 versions x 128 events (16,384
-    samples per optimisation): sampled chain edges against the oracle."""
+    samples per optimisation, 32,256 chain-edge searches) in the launch the
+    benchmark times: 1,000 sampled chain edges against the oracle's search,
+    every one compared."""
     tr = make_batch(1910, range(10 ** 6, 10 ** 6 + 512), 128, 6)
     te = make_batch(1910, range(512), 128, 6)
     ptr = G.Plan(ctx, tr.nopts, tr.opt_ids, 128, 6)
     G.ibk_fit(ctx, ptr, dev(tr.counters), dev(tr.cycles), k=10)
     p = G.Plan(ctx, te.nopts, te.opt_ids, 128, 6)
-    _, grid = G.ibk_predict(ctx, p, dev(te.counters), dev(te.cycles), grid=True)
+    idx, score, count, table = G.ibk_suggest(ctx, p, dev(te.counters), dev(te.cycles))
+    n_exact = G.ibk_exact_count(ctx, p)
     G.sync(ctx)
-    g = grid.cpu().numpy().astype(np.float64)
+    print(f"queries searched again in FP64: {n_exact} of {te.N - te.K}")
+    assert n_exact < 0.05 * (te.N - te.K)
+    t = table.cpu().numpy().astype(np.float64)
     db = N.database(tr, 6)
     z = P.standardize(P.features(te.counters, te.cycles), db["mu"], db["sigma"])
     rng = np.random.default_rng(5)
-    done = skipped = 0
-    while done < 120:
-        r = int(rng.integers(0, te.row_off[-1]))
-        b = int(rng.integers(0, 6))
-        S = r - int(te.row_off[r // 64])
-        if (S >> b) & 1:
-            continue
-        idx, d2 = N.neighbours(db["Z"][b], z[r], 11)
-        if not decided(d2[9], d2[10]):
-            skipped += 1
-            continue
-        want = float(np.mean(db["y"][b][idx[:10]]))
-        assert close(g[r, b], want), (r, b, g[r, b], want)
-        done += 1
-    assert skipped < 12
+    for r in rng.choice(np.flatnonzero(np.arange(te.N) % 64 != 0), size=1000, replace=False):
+        S = int(r % 64)
+        b = S.bit_length() - 1                      # the last step of S's chain
+        want = N.predict_one(db, z[r - (1 << b)], b, 10)
+        got = t[r] - t[r - (1 << b)]                 # the edge, from the composed table
+        assert abs(got - want) <= 2e-5 * (1 + abs(want)) + 4e-6 * abs(t[r]), (r, got, want)
 
 
 def test_ibk_errors(G, ctx):
@@ -161,11 +127,6 @@ def test_ibk_errors(G, ctx):
         with pytest.raises(SuggError) as e:
             G.ibk_fit(ctx, p, c, cy, k=k)
         assert e.value.name == "SUGG_E_ARG"
-    wide = make_batch(33, range(2), 160, 6, brange=(2, 2))
-    pw = G.Plan(ctx, wide.nopts, wide.opt_ids, 160, 6)
-    with pytest.raises(SuggError) as e:
-        G.ibk_fit(ctx, pw, dev(wide.counters), dev(wide.cycles))
-    assert e.value.name == "SUGG_E_SHAPE"
     G.ibk_fit(ctx, p, c, cy)
     assert np.array_equal(G.ibk_counts(ctx, 6), [32, 32, 32, 0, 0, 0])
     one = make_batch(33, range(100, 101), 128, 6, brange=(1, 1))
