@@ -14,14 +14,14 @@ surrogate table Ls[S] and plain composed table L[S], S in [0, 2^B):
   3. more than ``cap`` band subsets: the kernel falls back;
   4. otherwise the kernel falls back when some listed or band subset has
      |Ls[S] - L[S]| > tol (or a non-finite difference);
-  5. it also falls back unless the plain values confirm Tier 3's contract for
-     the list (Section 2: only choices above the threshold, sorted by
-     benefit): every listed subset has L[S] > tau, the list is in descending
-     order of L (equal values: smaller S first), and no band subset has
-     L[S] > tau.  A kept answer is then exactly Tier 3's ranking of the plain
-     values over the judged subsets;
+  5. it also falls back unless the plain values keep Tier 3's threshold
+     (Section 2: only choices above it): every listed subset has L[S] > tau
+     and no band subset has L[S] > tau;
   6. a kernel that falls back gets the plain answer (Tier 3 on L); the others
-     keep the surrogate's subsets, reported with their plain values L[S].
+     keep the surrogate's subsets with their plain values L[S], sorted by
+     them (Tier 3's order: descending, equal values by smaller S).  A kept
+     answer is then exactly Tier 3's ranking of the plain values over the
+     judged subsets.
 """
 from __future__ import annotations
 
@@ -57,10 +57,10 @@ def serve_kernel(sur, plain, tau: float = TAU, n: int = N_SUGGEST, tol: float = 
         return True, rank(plain, tau, n, first=1), judged
     if any(not abs(sur[S] - plain[S]) <= tol for S in judged):
         return True, rank(plain, tau, n, first=1), judged
-    ordered = all((plain[a] > plain[b]) or (plain[a] == plain[b] and a < b) for a, b in zip(listed, listed[1:]))
-    if not ordered or any(not plain[S] > tau for S in listed) or any(plain[S] > tau for S in extra):
+    if any(not plain[S] > tau for S in listed) or any(plain[S] > tau for S in extra):
         return True, rank(plain, tau, n, first=1), judged
-    return False, [(S, float(plain[S])) for S in listed], judged
+    kept = sorted(listed, key=lambda S: (-plain[S], S))
+    return False, [(S, float(plain[S])) for S in kept], judged
 
 
 def serve(sur_tables, plain_tables, **kw):
