@@ -256,15 +256,15 @@ SUGG_API int32_t sugg_greedy(sugg_ctx* ctx, const sugg_plan* plan, const void* c
  *      with SUGG_BASELINE), 2. the surrogate's table, 3. its top n_suggest
  *      above tau, 4. the threshold band of short lists (sugg_band_select, at
  *      most cap subsets), 5. the judge of the listed and band subsets
- *      against the plain composed values, 6. Tier 3's contract checked on
- *      the plain values (every listed subset above tau, the list in
- *      descending plain order with equal values by smaller subset, no band
- *      subset above tau), 7. the plain fused path for the kernels flagged
- *      (difference above tol, band overflow, or a broken contract).
+ *      against the plain composed values, 6. Tier 3's threshold checked on
+ *      the plain values (every listed subset above tau, no band subset
+ *      above tau), 7. the plain fused path for the kernels flagged
+ *      (difference above tol, band overflow, or a threshold breach).
  * idx_out [K x n] / score_out [K x n] / count_out [K]: the answer (subsets of
- * the surrogate's list with their plain values, which is then Tier 3's
- * ranking of the plain values over the judged subsets, or the plain answer
- * where flagged); flag_out [K]: 1 where the plain path answered.  A learned
+ * the surrogate's list with their plain values, sorted by them: descending,
+ * equal values by smaller subset - Tier 3's ranking of the plain values over
+ * the judged subsets - or the plain answer where flagged); flag_out [K]: 1
+ * where the plain path answered.  A learned
  * surrogate is an extension of the paper's Tier 2, which stays the judge.
  * The plan keeps a workspace for its queries (allocated on its first call,
  * not inside a graph capture). */

@@ -845,9 +845,9 @@ int32_t sugg_serve_query(sugg_ctx* ctx, const sugg_plan* plan, sugg_mlp* mlp, co
   if (!rc) rc = run_judge<float>(ctx, p, c, cy, idx_out, n, (float*)score_out, w.sc, tol, flag_out, 1, stream);
   if (!rc) rc = run_judge<float>(ctx, p, c, cy, w.bc, cap, w.bout, w.br, tol, flag_out, 1, stream);
   // 6. Tier 3's contract by the plain values: listed subsets above the
-  // threshold and in plain order, no band subset above it
+  // threshold, no band subset above it; kept lists sorted by plain value
   if (!rc)
-    rc = ctx->hip(launch_confirm(K, n, idx_out, (const float*)score_out, count_out, w.bc, w.bout, cap,
+    rc = ctx->hip(launch_confirm(K, n, idx_out, (float*)score_out, count_out, w.bc, w.bout, cap,
                                  (float)ctx->params.tau, flag_out, stream), "serve: confirm");
   // 7. the plain path for the flagged kernels
   if (!rc)

@@ -673,60 +673,72 @@ hipError_t launch_ibk_knn(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
 // ---- composition along the ascending chain, then the top-n ------------------
 // L(S) = L(S without its highest bit b) + step(S), step(S) = the prediction of
 // adding b to S without it (the same sum, in the same order, as adding the
-// steps of the chain from the baseline one by one).  One wave per kernel.
-template <typename T, int KT>
-__global__ void __launch_bounds__(64) ibk_compose_kernel(const T* __restrict__ edges, const T* __restrict__ grid,
+// steps of the chain from the baseline one by one), in TE; outputs in TO.
+// One wave per kernel.
+template <typename TE, typename TO, int KT>
+__global__ void __launch_bounds__(64) ibk_compose_kernel(const TE* __restrict__ edges, const TO* __restrict__ grid,
                                                          int grid_ld, const int64_t* __restrict__ row_off,
-                                                         const int32_t* __restrict__ nopts, int K, T* table,
-                                                         int32_t* idx_out, T* score_out, int32_t* count_out, int n,
-                                                         T tau) {
+                                                         const int32_t* __restrict__ nopts, int K, TO* table,
+                                                         int32_t* idx_out, TO* score_out, int32_t* count_out, int n,
+                                                         TE tau) {
   extern __shared__ __align__(16) unsigned char smem[];
-  T* L = reinterpret_cast<T*>(smem);
+  TE* L = reinterpret_cast<TE*>(smem);
   const int k = blockIdx.x, lane = threadIdx.x;
   if (k >= K) return;
   const int B = nopts[k];
   const int64_t r0 = row_off[k];
-  if (lane == 0) L[0] = T(0);
+  if (lane == 0) L[0] = TE(0);
   __syncthreads();
   for (int b = 0; b < B; ++b) {
     const int lo = 1 << b;
     for (int S = lo + lane; S < 2 * lo; S += kWave) {
-      const T e = edges ? edges[r0 + S] : grid[(r0 + S - lo) * grid_ld + b];
+      const TE e = edges ? edges[r0 + S] : (TE)grid[(r0 + S - lo) * grid_ld + b];
       L[S] = L[S - lo] + e;
     }
     __syncthreads();
   }
-  Entry<T> lst[KT];
+  Entry<TE> lst[KT];
 #pragma unroll
-  for (int i = 0; i < KT; ++i) lst[i] = empty_entry<T>();
+  for (int i = 0; i < KT; ++i) lst[i] = empty_entry<TE>();
   for (int S = lane; S < (1 << B); S += kWave) {
-    const T v = L[S];
-    if (table) table[r0 + S] = v;
+    const TE v = L[S];
+    if (table) table[r0 + S] = (TO)v;
     if (S != 0 && v > tau) {
-      Entry<T> e;
+      Entry<TE> e;
       e.v = v;
       e.s = S;
-      list_insert<T, KT>(lst, e);
+      list_insert<TE, KT>(lst, e);
     }
   }
   if (idx_out) {
-    group_merge<T, KT>(lst, kWave);
-    if (lane == 0) write_list<T, KT>(lst, k, n, idx_out, score_out, count_out);
+    group_merge<TE, KT>(lst, kWave);
+    if (lane == 0) {
+      int cnt = 0;
+#pragma unroll
+      for (int i = 0; i < KT; ++i)
+        if (i < n) {
+          const bool ok = lst[i].s >= 0;
+          idx_out[(int64_t)k * n + i] = ok ? lst[i].s : -1;
+          score_out[(int64_t)k * n + i] = ok ? (TO)lst[i].v : qnan<TO>();
+          cnt += ok ? 1 : 0;
+        }
+      count_out[k] = cnt;
+    }
   }
 }
 
-template <typename T>
-hipError_t launch_ibk_compose(const T* edges, const T* grid, int32_t grid_ld, const int64_t* row_off,
-                              const int32_t* nopts, int32_t K, int32_t Bmax, T* table, int32_t* idx_out,
-                              T* score_out, int32_t* count_out, int32_t n, T tau, hipStream_t s) {
+template <typename TE, typename TO>
+hipError_t launch_ibk_compose(const TE* edges, const TO* grid, int32_t grid_ld, const int64_t* row_off,
+                              const int32_t* nopts, int32_t K, int32_t Bmax, TO* table, int32_t* idx_out,
+                              TO* score_out, int32_t* count_out, int32_t n, TE tau, hipStream_t s) {
   if (K <= 0) return hipSuccess;
-  const size_t smem = sizeof(T) * ((size_t)1 << Bmax);
+  const size_t smem = sizeof(TE) * ((size_t)1 << Bmax);
   (void)hipGetLastError();
   if (n <= 4)
-    hipLaunchKernelGGL((ibk_compose_kernel<T, 4>), dim3(K), dim3(64), smem, s, edges, grid, grid_ld, row_off,
+    hipLaunchKernelGGL((ibk_compose_kernel<TE, TO, 4>), dim3(K), dim3(64), smem, s, edges, grid, grid_ld, row_off,
                        nopts, K, table, idx_out, score_out, count_out, n, tau);
   else
-    hipLaunchKernelGGL((ibk_compose_kernel<T, 8>), dim3(K), dim3(64), smem, s, edges, grid, grid_ld, row_off,
+    hipLaunchKernelGGL((ibk_compose_kernel<TE, TO, 8>), dim3(K), dim3(64), smem, s, edges, grid, grid_ld, row_off,
                        nopts, K, table, idx_out, score_out, count_out, n, tau);
   return hipGetLastError();
 }
@@ -754,12 +766,15 @@ hipError_t launch_ibk_nan(T* p, int64_t n, hipStream_t s) {
   template hipError_t launch_ibk_labels<T>(const T*, const int32_t*, const int32_t*, int64_t, double*,       \
                                            hipStream_t);                                                     \
   template hipError_t launch_ibk_knn<T>(const IbkKnnArgs&, int, hipStream_t);                                \
-  template hipError_t launch_ibk_compose<T>(const T*, const T*, int32_t, const int64_t*, const int32_t*,     \
-                                            int32_t, int32_t, T*, int32_t*, T*, int32_t*, int32_t, T,        \
-                                            hipStream_t);                                                    \
+  template hipError_t launch_ibk_compose<T, T>(const T*, const T*, int32_t, const int64_t*, const int32_t*,  \
+                                               int32_t, int32_t, T*, int32_t*, T*, int32_t*, int32_t, T,     \
+                                               hipStream_t);                                                 \
   template hipError_t launch_ibk_nan<T>(T*, int64_t, hipStream_t);
 SUGG_INST(float)
 SUGG_INST(double)
 #undef SUGG_INST
+template hipError_t launch_ibk_compose<double, float>(const double*, const float*, int32_t, const int64_t*,
+                                                      const int32_t*, int32_t, int32_t, float*, int32_t*, float*,
+                                                      int32_t*, int32_t, double, hipStream_t);
 
 }  // namespace sugg

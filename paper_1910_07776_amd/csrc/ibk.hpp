@@ -121,10 +121,12 @@ hipError_t launch_ibk_knn(const IbkKnnArgs& a, int n_tiles, hipStream_t s);
 // candidates kept per query for a given k
 inline int ibk_kt(int k) { return k <= 4 ? 8 : k <= 10 ? 16 : 24; }
 int ibk_split(int Epad, int k, int n_tiles, int cus);
-template <typename T>
-hipError_t launch_ibk_compose(const T* edges, const T* grid, int32_t grid_ld, const int64_t* row_off,
-                              const int32_t* nopts, int32_t K, int32_t Bmax, T* table, int32_t* idx_out,
-                              T* score_out, int32_t* count_out, int32_t n, T tau, hipStream_t s);
+// Composition and top-n from chain edges (dtype TE, the composition's
+// arithmetic) or from a grid (dtype TO); outputs of dtype TO.
+template <typename TE, typename TO>
+hipError_t launch_ibk_compose(const TE* edges, const TO* grid, int32_t grid_ld, const int64_t* row_off,
+                              const int32_t* nopts, int32_t K, int32_t Bmax, TO* table, int32_t* idx_out,
+                              TO* score_out, int32_t* count_out, int32_t n, TE tau, hipStream_t s);
 
 }  // namespace sugg
 

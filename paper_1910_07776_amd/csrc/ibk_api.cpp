@@ -300,7 +300,7 @@ int score_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, T* grid, T* t
   w->exact_mode = mode;
   if (e == hipSuccess) e = launch_ibk_knn<T>(a, q.n_tiles, s);
   if (e == hipSuccess)
-    e = launch_ibk_compose<T>(grid ? nullptr : (const T*)w->edges, grid, p->Bmax, p->d_row_off, p->d_nopts, p->K,
+    e = launch_ibk_compose<T, T>(grid ? nullptr : (const T*)w->edges, grid, p->Bmax, p->d_row_off, p->d_nopts, p->K,
                               p->Bmax, table, idx, score, count, ctx->params.n_suggest, (T)ctx->params.tau, s);
   return ctx->hip(e, "IBK scoring");
 }

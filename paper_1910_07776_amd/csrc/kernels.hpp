@@ -115,8 +115,9 @@ template <typename T>
 hipError_t launch_band(const T* scores, const int64_t* seg_off, int32_t nseg, int32_t skip_head,
                        const int32_t* top_idx, const int32_t* top_count, int32_t n, double lo, int32_t C,
                        int32_t* cand_out, T* ref_out, int32_t* flag_out, hipStream_t s);
-// serving: flag kernels whose kept answer breaks Tier 3's contract by the plain values
-hipError_t launch_confirm(int32_t K, int32_t n, const int32_t* idx, const float* plain, const int32_t* count,
+// serving: flag kernels whose kept answer breaks Tier 3's threshold by the
+// plain values, sort the others' lists by them
+hipError_t launch_confirm(int32_t K, int32_t n, int32_t* idx, float* plain, const int32_t* count,
                           const int32_t* band_idx, const float* band_plain, int32_t C, float tau, int32_t* flag,
                           hipStream_t s);
 

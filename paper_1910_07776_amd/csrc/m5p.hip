@@ -10,7 +10,10 @@
 // evaluated sixteen lanes per prediction with a DPP reduction.  Edge mode
 // forms the predictions of the ascending chain only (row S predicts adding
 // each b above its top bit: the one edge into every version S | 2^b); grid
-// mode every b not in S.
+// mode every b not in S.  Counters are read in the plan's dtype TI and every
+// step computes in FP64 (features, tests, leaf models), so each walk takes
+// the branch of the FP64 reference and FP32 plans differ from it only by the
+// rounding of their outputs.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -21,18 +24,20 @@ namespace sugg {
 
 constexpr int kM5pThreads = kM5pRows * kRowLanes;
 
-template <typename T, int NCH, int VW>
-__device__ __forceinline__ void m5p_load_row(const T* rp, int E, int l16, T (&c)[NCH][VW]) {
+// Lane l16's chunks of a row, columns (l16 + 16 ch) * VW + [0, VW), read in
+// the plan dtype and widened to FP64 (1 past E).
+template <typename TI, int NCH, int VW>
+__device__ __forceinline__ void m5p_load_row(const TI* rp, int E, int l16, double (&c)[NCH][VW]) {
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
     const int c0 = (l16 + kRowLanes * ch) * VW;
     if (c0 + VW <= E) {
-      const VecN<T, VW> q = *reinterpret_cast<const VecN<T, VW>*>(rp + c0);
+      const VecN<TI, VW> q = *reinterpret_cast<const VecN<TI, VW>*>(rp + c0);
 #pragma unroll
-      for (int v = 0; v < VW; ++v) c[ch][v] = q.v[v];
+      for (int v = 0; v < VW; ++v) c[ch][v] = (double)q.v[v];
     } else {
 #pragma unroll
-      for (int v = 0; v < VW; ++v) c[ch][v] = c0 + v < E ? rp[c0 + v] : T(1);
+      for (int v = 0; v < VW; ++v) c[ch][v] = c0 + v < E ? (double)rp[c0 + v] : 1.0;
     }
   }
 }
@@ -85,13 +90,14 @@ __device__ __forceinline__ int m5p_row_edges(int S, int B, bool grid) {
   return grid ? B - __popc((unsigned)S) : B - 1 - (S ? 31 - __clz(S) : -1);
 }
 
-template <typename T, int VPL, int VW>
-__global__ void __launch_bounds__(kM5pThreads) m5p_kernel(const M5pArgs<T> a) {
+template <typename TI, int VPL, int VW>
+__global__ void __launch_bounds__(kM5pThreads) m5p_kernel(const M5pArgs<TI> a) {
+  using T = double;
   constexpr int NCH = VPL / VW;
   constexpr int EP = kRowLanes * VPL;
   constexpr int kMaxEdges = kM5pRows * SUGG_MAX_OPTS;
   static_assert(kMaxEdges <= kM5pThreads, "one walk per thread");
-  __shared__ __align__(16) T zl[kM5pRows][EP];
+  __shared__ __align__(32) T zl[kM5pRows][EP];
   __shared__ int32_t e_leaf[kMaxEdges];
   __shared__ int32_t e_gb[kMaxEdges];
   const int tid = threadIdx.x, g = tid / kRowLanes, l16 = tid % kRowLanes;
@@ -109,9 +115,9 @@ __global__ void __launch_bounds__(kM5pThreads) m5p_kernel(const M5pArgs<T> a) {
     T s_r[NCH][VW], m_r[NCH][VW];
     column_constants<T, NCH, VW, false>(a.mu, a.isg, a.E, l16, s_r, m_r);
     T c[NCH][VW];
-    m5p_load_row<T, NCH, VW>(a.counters + (r0 + Sr) * a.E, a.E, l16, c);
+    m5p_load_row<TI, NCH, VW>(a.counters + (r0 + Sr) * a.E, a.E, l16, c);
     T z[NCH][VW];
-    const T chk = row_features<T, NCH, VW>(c, a.cycles[r0 + Sr], s_r, m_r, z);
+    const T chk = row_features<T, NCH, VW>(c, (T)a.cycles[r0 + Sr], s_r, m_r, z);
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       VecN<T, VW> q;
@@ -163,8 +169,9 @@ __global__ void __launch_bounds__(kM5pThreads) m5p_kernel(const M5pArgs<T> a) {
     const T p = row_sum16(part) + a.lb[leaf];
     if (l16 == 0) {
       const int S = S0 + r;
-      if (grid) a.grid[(r0 + S) * a.Bmax + b] = p;
-      else a.edges[r0 + (S | (1 << b))] = p;
+      if (grid) a.grid[(r0 + S) * a.Bmax + b] = (TI)p;
+      // the chain edges in FP64 in both modes: the composition reads them
+      if (!grid || b > (S ? 31 - __clz(S) : -1)) a.edges[r0 + (S | (1 << b))] = p;
     }
   }
 }
@@ -177,13 +184,14 @@ __global__ void __launch_bounds__(kM5pThreads) m5p_kernel(const M5pArgs<T> a) {
 // the top-n of wave 0.  The arithmetic of an edge and of the composition is
 // that of the tiled kernel and the separate composition, so both give the
 // same bits.
-template <typename T, int VPL, int VW, int KT>
-__global__ void __launch_bounds__(kM5pThreads) m5p_small_kernel(const M5pArgs<T> a, T* table, int32_t* idx_out,
-                                                                T* score_out, int32_t* count_out, int n, T tau) {
+template <typename TI, int VPL, int VW, int KT>
+__global__ void __launch_bounds__(kM5pThreads) m5p_small_kernel(const M5pArgs<TI> a, TI* table, int32_t* idx_out,
+                                                                TI* score_out, int32_t* count_out, int n, double tau) {
+  using T = double;
   constexpr int NCH = VPL / VW;
   constexpr int EP = kRowLanes * VPL;
   constexpr int kRows = 64, kPer = kRows / kM5pRows;
-  __shared__ __align__(16) T zl[kRows][EP];
+  __shared__ __align__(32) T zl[kRows][EP];
   __shared__ T ev[kRows];
   __shared__ T L[kRows];
   __shared__ int32_t e_leaf[kRows];
@@ -200,14 +208,14 @@ __global__ void __launch_bounds__(kM5pThreads) m5p_small_kernel(const M5pArgs<T>
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int S = g + kM5pRows * i;
-      m5p_load_row<T, NCH, VW>(a.counters + (r0 + (S < V ? S : 0)) * a.E, a.E, l16, c[i]);
+      m5p_load_row<TI, NCH, VW>(a.counters + (r0 + (S < V ? S : 0)) * a.E, a.E, l16, c[i]);
     }
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int S = g + kM5pRows * i;
       T z[NCH][VW];
-      const T chk = row_features<T, NCH, VW>(c[i], a.cycles[r0 + (S < V ? S : 0)], s_r, m_r, z);
+      const T chk = row_features<T, NCH, VW>(c[i], (T)a.cycles[r0 + (S < V ? S : 0)], s_r, m_r, z);
       bad |= S < V && l16 == 0 && !__builtin_isfinite(chk);
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) {
@@ -269,7 +277,7 @@ __global__ void __launch_bounds__(kM5pThreads) m5p_small_kernel(const M5pArgs<T>
     for (int i = 0; i < KT; ++i) lst[i] = empty_entry<T>();
     if (tid < V) {
       const T v = L[tid];
-      if (table) table[r0 + tid] = v;
+      if (table) table[r0 + tid] = (TI)v;
       if (tid != 0 && v > tau) {
         Entry<T> e;
         e.v = v;
@@ -279,59 +287,70 @@ __global__ void __launch_bounds__(kM5pThreads) m5p_small_kernel(const M5pArgs<T>
     }
     if (idx_out) {
       group_merge<T, KT>(lst, kWave);
-      if (tid == 0) write_list<T, KT>(lst, k, n, idx_out, score_out, count_out);
+      if (tid == 0) {
+        int cnt = 0;
+#pragma unroll
+        for (int i = 0; i < KT; ++i)
+          if (i < n) {
+            const bool ok = lst[i].s >= 0;
+            idx_out[(int64_t)k * n + i] = ok ? lst[i].s : -1;
+            score_out[(int64_t)k * n + i] = ok ? (TI)lst[i].v : qnan<TI>();
+            cnt += ok ? 1 : 0;
+          }
+        count_out[k] = cnt;
+      }
     }
   }
 }
 
-template <typename T, int VPL>
-hipError_t launch_m5p_vpl(const M5pArgs<T>& a, int n_tiles, hipStream_t s) {
-  constexpr int VEC = 16 / sizeof(T);
+template <typename TI, int VPL>
+hipError_t launch_m5p_vpl(const M5pArgs<TI>& a, int n_tiles, hipStream_t s) {
+  constexpr int VEC = 16 / sizeof(TI);
   const bool vec = (a.E % VEC) == 0 && (reinterpret_cast<uintptr_t>(a.counters) % 16) == 0;
   (void)hipGetLastError();
-  if (vec) hipLaunchKernelGGL((m5p_kernel<T, VPL, VEC>), dim3(n_tiles), dim3(kM5pThreads), 0, s, a);
-  else hipLaunchKernelGGL((m5p_kernel<T, VPL, 1>), dim3(n_tiles), dim3(kM5pThreads), 0, s, a);
+  if (vec) hipLaunchKernelGGL((m5p_kernel<TI, VPL, VEC>), dim3(n_tiles), dim3(kM5pThreads), 0, s, a);
+  else hipLaunchKernelGGL((m5p_kernel<TI, VPL, 1>), dim3(n_tiles), dim3(kM5pThreads), 0, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int VPL>
-hipError_t launch_m5p_small_vpl(const M5pArgs<T>& a, int K, T* table, int32_t* idx, T* score, int32_t* count, int n,
-                                T tau, hipStream_t s) {
-  constexpr int VEC = 16 / sizeof(T);
+template <typename TI, int VPL>
+hipError_t launch_m5p_small_vpl(const M5pArgs<TI>& a, int K, TI* table, int32_t* idx, TI* score, int32_t* count,
+                                int n, double tau, hipStream_t s) {
+  constexpr int VEC = 16 / sizeof(TI);
   const bool vec = (a.E % VEC) == 0 && (reinterpret_cast<uintptr_t>(a.counters) % 16) == 0;
   (void)hipGetLastError();
   const dim3 grid(K), block(kM5pThreads);
   if (n <= 4) {
-    if (vec) hipLaunchKernelGGL((m5p_small_kernel<T, VPL, VEC, 4>), grid, block, 0, s, a, table, idx, score, count, n, tau);
-    else hipLaunchKernelGGL((m5p_small_kernel<T, VPL, 1, 4>), grid, block, 0, s, a, table, idx, score, count, n, tau);
+    if (vec) hipLaunchKernelGGL((m5p_small_kernel<TI, VPL, VEC, 4>), grid, block, 0, s, a, table, idx, score, count, n, tau);
+    else hipLaunchKernelGGL((m5p_small_kernel<TI, VPL, 1, 4>), grid, block, 0, s, a, table, idx, score, count, n, tau);
   } else {
-    if (vec) hipLaunchKernelGGL((m5p_small_kernel<T, VPL, VEC, 8>), grid, block, 0, s, a, table, idx, score, count, n, tau);
-    else hipLaunchKernelGGL((m5p_small_kernel<T, VPL, 1, 8>), grid, block, 0, s, a, table, idx, score, count, n, tau);
+    if (vec) hipLaunchKernelGGL((m5p_small_kernel<TI, VPL, VEC, 8>), grid, block, 0, s, a, table, idx, score, count, n, tau);
+    else hipLaunchKernelGGL((m5p_small_kernel<TI, VPL, 1, 8>), grid, block, 0, s, a, table, idx, score, count, n, tau);
   }
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_m5p_small(const M5pArgs<T>& a, int K, T* table, int32_t* idx, T* score, int32_t* count, int n, T tau,
-                            hipStream_t s) {
+template <typename TI>
+hipError_t launch_m5p_small(const M5pArgs<TI>& a, int K, TI* table, int32_t* idx, TI* score, int32_t* count, int n,
+                            double tau, hipStream_t s) {
   if (K <= 0) return hipSuccess;
-  if (a.E <= 16 * 4) return launch_m5p_small_vpl<T, 4>(a, K, table, idx, score, count, n, tau, s);
-  if (a.E <= 16 * 8) return launch_m5p_small_vpl<T, 8>(a, K, table, idx, score, count, n, tau, s);
-  return launch_m5p_small_vpl<T, 16>(a, K, table, idx, score, count, n, tau, s);
+  if (a.E <= 16 * 4) return launch_m5p_small_vpl<TI, 4>(a, K, table, idx, score, count, n, tau, s);
+  if (a.E <= 16 * 8) return launch_m5p_small_vpl<TI, 8>(a, K, table, idx, score, count, n, tau, s);
+  return launch_m5p_small_vpl<TI, 16>(a, K, table, idx, score, count, n, tau, s);
 }
 
-template <typename T>
-hipError_t launch_m5p(const M5pArgs<T>& a, int n_tiles, hipStream_t s) {
+template <typename TI>
+hipError_t launch_m5p(const M5pArgs<TI>& a, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  if (a.E <= 16 * 4) return launch_m5p_vpl<T, 4>(a, n_tiles, s);
-  if (a.E <= 16 * 8) return launch_m5p_vpl<T, 8>(a, n_tiles, s);
-  return launch_m5p_vpl<T, 16>(a, n_tiles, s);
+  if (a.E <= 16 * 4) return launch_m5p_vpl<TI, 4>(a, n_tiles, s);
+  if (a.E <= 16 * 8) return launch_m5p_vpl<TI, 8>(a, n_tiles, s);
+  return launch_m5p_vpl<TI, 16>(a, n_tiles, s);
 }
 
 template hipError_t launch_m5p<float>(const M5pArgs<float>&, int, hipStream_t);
 template hipError_t launch_m5p<double>(const M5pArgs<double>&, int, hipStream_t);
-template hipError_t launch_m5p_small<float>(const M5pArgs<float>&, int, float*, int32_t*, float*, int32_t*, int, float,
-                                            hipStream_t);
+template hipError_t launch_m5p_small<float>(const M5pArgs<float>&, int, float*, int32_t*, float*, int32_t*, int,
+                                            double, hipStream_t);
 template hipError_t launch_m5p_small<double>(const M5pArgs<double>&, int, double*, int32_t*, double*, int32_t*, int,
                                              double, hipStream_t);
 

@@ -55,21 +55,20 @@ struct alignas(128) M5pBlock {
 };
 
 // Device form of a fitted model: every optimisation's tree concatenated.
+// Predictions are formed in FP64 whatever the plan's dtype (features from the
+// counters, the walk's tests, the leaf models), so a walk takes the branch
+// the FP64 reference takes.
 struct M5pModel {
   int E = 0, D = 0, ldl = 0;
   M5pParams prm;
   std::vector<M5pHostTree> trees;     // per global id (empty when untrained)
   std::vector<int32_t> root;          // per global id: first block, -1 when untrained
   int32_t* d_root = nullptr;
-  M5pBlock<float>* blk32 = nullptr;
   M5pBlock<double>* blk64 = nullptr;
   int max_blocks = 0;                 // longest chain of blocks of a walk
-  float* lw32 = nullptr;              // [leaves, ldl], columns >= E zero
-  double* lw64 = nullptr;
-  float* lb32 = nullptr;              // [leaves] intercepts
-  double* lb64 = nullptr;
-  float *mu32 = nullptr, *isg32 = nullptr;    // column constants for the features
-  double *mu64 = nullptr, *isg64 = nullptr;
+  double* lw64 = nullptr;             // [leaves, ldl], columns >= E zero
+  double* lb64 = nullptr;             // [leaves] intercepts
+  double *mu64 = nullptr, *isg64 = nullptr;   // column constants for the features
 };
 
 struct M5pPlan {
@@ -78,40 +77,41 @@ struct M5pPlan {
   void* edges = nullptr;              // [N] plan dtype
 };
 
-template <typename T>
+// TI: the plan's dtype (counters, cycles, outputs); arithmetic in FP64.
+template <typename TI>
 struct M5pArgs {
-  const T* counters;
-  const T* cycles;
+  const TI* counters;
+  const TI* cycles;
   const int64_t* row_off;
   const int32_t* nopts;
   const int64_t* opt_off;
   const int32_t* opt_ids;
   const int32_t* tiles;
-  const T* mu;
-  const T* isg;
+  const double* mu;
+  const double* isg;
   const int32_t* root;
-  const M5pBlock<T>* blocks;
-  const T* lw;
-  const T* lb;
+  const M5pBlock<double>* blocks;
+  const double* lw;
+  const double* lb;
   int32_t ldl;
   int32_t max_blocks;
   int32_t E;
   int32_t Bmax;
-  T* grid;      // grid mode when non-null: every b not in S
-  T* edges;     // else chain edges: e[row(k, S | 2^b)] for b above the top bit of S
+  TI* grid;       // grid mode when non-null: every b not in S
+  double* edges;  // else chain edges: e[row(k, S | 2^b)] for b above the top bit of S
   int32_t* status;
 };
 
 constexpr int kM5pRows = 16;          // versions per workgroup (16 lanes each)
 
-template <typename T>
-hipError_t launch_m5p(const M5pArgs<T>& a, int n_tiles, hipStream_t s);
+template <typename TI>
+hipError_t launch_m5p(const M5pArgs<TI>& a, int n_tiles, hipStream_t s);
 // Kernels of at most 64 versions, chain edges only: the whole pass (edges,
 // composition, top-n) in one launch, one workgroup per kernel.
 constexpr int kM5pSmallB = 6;
-template <typename T>
-hipError_t launch_m5p_small(const M5pArgs<T>& a, int K, T* table, int32_t* idx, T* score, int32_t* count, int n,
-                            T tau, hipStream_t s);
+template <typename TI>
+hipError_t launch_m5p_small(const M5pArgs<TI>& a, int K, TI* table, int32_t* idx, TI* score, int32_t* count, int n,
+                            double tau, hipStream_t s);
 
 }  // namespace sugg
 

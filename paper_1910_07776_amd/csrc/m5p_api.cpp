@@ -21,8 +21,7 @@ using namespace sugg;
 
 void m5p_model_free(M5pModel*& m) {
   if (!m) return;
-  dfree(m->d_root); dfree(m->blk32); dfree(m->blk64); dfree(m->lw32); dfree(m->lw64);
-  dfree(m->lb32); dfree(m->lb64); dfree(m->mu32); dfree(m->isg32); dfree(m->mu64); dfree(m->isg64);
+  dfree(m->d_root); dfree(m->blk64); dfree(m->lw64); dfree(m->lb64); dfree(m->mu64); dfree(m->isg64);
   delete m;
   m = nullptr;
 }
@@ -107,7 +106,6 @@ int induce_all(sugg_ctx* ctx, const sugg_plan* p, const std::vector<double>& z, 
 }
 
 // Leaf ordinal stored in a threshold slot's bits (read back the same way).
-void put_leaf(float& slot, int32_t id) { std::memcpy(&slot, &id, sizeof id); }
 void put_leaf(double& slot, int32_t id) {
   const int64_t v = id;
   std::memcpy(&slot, &v, sizeof v);
@@ -117,23 +115,19 @@ void put_leaf(double& slot, int32_t id) {
 // the root; leaf ordinals offset by leaf_base, block indices by the blocks
 // already present.  Returns the root block; *chain receives the longest run
 // of blocks a walk loads.
-int pack_tree(const M5pHostTree& t, int leaf_base, std::vector<M5pBlock<float>>& b32,
-              std::vector<M5pBlock<double>>& b64, int* chain) {
+int pack_tree(const M5pHostTree& t, int leaf_base, std::vector<M5pBlock<double>>& b64, int* chain) {
   struct Todo {
     int node, block, level;
   };
   auto fresh = [&]() {
-    M5pBlock<float> f{};
     M5pBlock<double> d{};
     for (int p = 0; p < 8; ++p) {
-      f.feat[p] = d.feat[p] = -1;
-      f.exit[p] = d.exit[p] = -1;
-      put_leaf(f.thr[p], leaf_base);   // unreachable slots name a valid leaf
-      put_leaf(d.thr[p], leaf_base);
+      d.feat[p] = -1;
+      d.exit[p] = -1;
+      put_leaf(d.thr[p], leaf_base);   // unreachable slots name a valid leaf
     }
-    b32.push_back(f);
     b64.push_back(d);
-    return (int)b32.size() - 1;
+    return (int)b64.size() - 1;
   };
   std::vector<Todo> todo{{0, fresh(), 1}};
   *chain = 1;
@@ -146,15 +140,12 @@ int pack_tree(const M5pHostTree& t, int leaf_base, std::vector<M5pBlock<float>>&
     for (int p = 0; p < 7; ++p) {
       const int m = pos[p];
       if (m < 0) continue;
-      M5pBlock<float>& f = b32[td.block];
       M5pBlock<double>& d = b64[td.block];
       if (t.feat[m] < 0) {
-        put_leaf(f.thr[p], leaf_base + t.leaf[m]);
         put_leaf(d.thr[p], leaf_base + t.leaf[m]);
         continue;
       }
-      f.feat[p] = d.feat[p] = (int16_t)t.feat[m];
-      f.thr[p] = (float)t.thr[m];
+      d.feat[p] = (int16_t)t.feat[m];
       d.thr[p] = t.thr[m];
       if (p < 3) {
         pos[2 * p + 1] = t.left[m];
@@ -171,7 +162,6 @@ int pack_tree(const M5pHostTree& t, int leaf_base, std::vector<M5pBlock<float>>&
           ref = fresh();
           todo.push_back({c, ref, td.level + 1});
         }
-        b32[td.block].exit[2 * (p - 3) + side] = ref;
         b64[td.block].exit[2 * (p - 3) + side] = ref;
       }
     }
@@ -182,9 +172,7 @@ int pack_tree(const M5pHostTree& t, int leaf_base, std::vector<M5pBlock<float>>&
 // Concatenate the trees into the device arrays.
 int upload_model(sugg_ctx* ctx, M5pModel* m) {
   const int E = m->E, ldl = m->ldl;
-  std::vector<M5pBlock<float>> b32;
   std::vector<M5pBlock<double>> b64;
-  std::vector<float> lw32, lb32;
   std::vector<double> lw64, lb64;
   m->root.assign(m->D, -1);
   m->max_blocks = 1;
@@ -193,26 +181,21 @@ int upload_model(sugg_ctx* ctx, M5pModel* m) {
     const M5pHostTree& t = m->trees[o];
     if (t.feat.empty()) continue;
     int chain = 1;
-    m->root[o] = pack_tree(t, leaf_base, b32, b64, &chain);
+    m->root[o] = pack_tree(t, leaf_base, b64, &chain);
     m->max_blocks = std::max(m->max_blocks, chain);
     for (int l = 0; l < t.leaves; ++l) {
       const double* w = t.lw.data() + (size_t)l * (E + 1);
       for (int j = 0; j < ldl; ++j) {
         const double v = j < E ? w[j] : 0.0;
         lw64.push_back(v);
-        lw32.push_back((float)v);
       }
       lb64.push_back(w[E]);
-      lb32.push_back((float)w[E]);
     }
     leaf_base += t.leaves;
   }
   hipError_t e = put(m->d_root, m->root);
-  if (e == hipSuccess) e = put(m->blk32, b32);
   if (e == hipSuccess) e = put(m->blk64, b64);
-  if (e == hipSuccess) e = put(m->lw32, lw32);
   if (e == hipSuccess) e = put(m->lw64, lw64);
-  if (e == hipSuccess) e = put(m->lb32, lb32);
   if (e == hipSuccess) e = put(m->lb64, lb64);
   return ctx->hip(e, "M5P model upload");
 }
@@ -262,17 +245,10 @@ int fit_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, const M5pParams
   int rc = induce_all(ctx, p, hz, hl, m);
   if (!rc) rc = upload_model(ctx, m);
   if (!rc) {
-    std::vector<float> mu32(E), isg32(E);
     std::vector<double> isg64(E);
-    for (int j = 0; j < E; ++j) {
-      isg64[j] = 1.0 / hsig[j];
-      mu32[j] = (float)hmu[j];
-      isg32[j] = (float)isg64[j];
-    }
+    for (int j = 0; j < E; ++j) isg64[j] = 1.0 / hsig[j];
     e = put(m->mu64, hmu);
     if (e == hipSuccess) e = put(m->isg64, isg64);
-    if (e == hipSuccess) e = put(m->mu32, mu32);
-    if (e == hipSuccess) e = put(m->isg32, isg32);
     rc = ctx->hip(e, "M5P statistics upload");
   }
   if (rc) {
@@ -321,7 +297,6 @@ int score_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, T* grid, T* t
     }
     p->m5p = w;
   }
-  const bool f32 = sizeof(T) == 4;
   M5pArgs<T> a;
   a.counters = c;
   a.cycles = cyc;
@@ -330,29 +305,29 @@ int score_t(sugg_ctx* ctx, sugg_plan* p, const T* c, const T* cyc, T* grid, T* t
   a.opt_off = p->d_opt_off;
   a.opt_ids = p->d_opt_ids;
   a.tiles = p->m5p->tiles;
-  a.mu = (const T*)(f32 ? (const void*)m->mu32 : (const void*)m->mu64);
-  a.isg = (const T*)(f32 ? (const void*)m->isg32 : (const void*)m->isg64);
+  a.mu = m->mu64;
+  a.isg = m->isg64;
   a.root = m->d_root;
-  a.blocks = (const M5pBlock<T>*)(f32 ? (const void*)m->blk32 : (const void*)m->blk64);
-  a.lw = (const T*)(f32 ? (const void*)m->lw32 : (const void*)m->lw64);
-  a.lb = (const T*)(f32 ? (const void*)m->lb32 : (const void*)m->lb64);
+  a.blocks = m->blk64;
+  a.lw = m->lw64;
+  a.lb = m->lb64;
   a.ldl = m->ldl;
   a.max_blocks = m->max_blocks;
   a.E = p->E;
   a.Bmax = p->Bmax;
   a.grid = grid;
-  a.edges = (T*)p->m5p->edges;
+  a.edges = (double*)p->m5p->edges;
   a.status = ctx->d_status;
   hipError_t e = hipSuccess;
   if (!grid && p->Bmax <= kM5pSmallB) {
-    e = launch_m5p_small<T>(a, p->K, table, idx, score, count, ctx->params.n_suggest, (T)ctx->params.tau, s);
+    e = launch_m5p_small<T>(a, p->K, table, idx, score, count, ctx->params.n_suggest, ctx->params.tau, s);
     return ctx->hip(e, "M5P scoring");
   }
   if (grid) e = launch_ibk_nan<T>(grid, p->N * p->Bmax, s);
   if (e == hipSuccess) e = launch_m5p<T>(a, p->m5p->n_tiles, s);
   if (e == hipSuccess)
-    e = launch_ibk_compose<T>(grid ? nullptr : a.edges, grid, p->Bmax, p->d_row_off, p->d_nopts, p->K, p->Bmax, table,
-                              idx, score, count, ctx->params.n_suggest, (T)ctx->params.tau, s);
+    e = launch_ibk_compose<double, T>(a.edges, grid, p->Bmax, p->d_row_off, p->d_nopts, p->K,
+                                      p->Bmax, table, idx, score, count, ctx->params.n_suggest, ctx->params.tau, s);
   return ctx->hip(e, "M5P scoring");
 }
 

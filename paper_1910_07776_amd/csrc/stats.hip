@@ -335,31 +335,42 @@ hipError_t launch_band(const T* scores, const int64_t* seg_off, int32_t nseg, in
 
 // Tier 3's contract on a served kernel's kept answer (Section 2: only choices
 // above the threshold, sorted by expected benefit), judged by the plain
-// values: each listed subset's plain value above tau, the list in descending
-// plain order (equal values: smaller subset first), and no band subset's
-// plain value above tau.  A kernel that breaks it is flagged (flags already
-// set stay set).  One thread per kernel.
-__global__ void confirm_kernel(int K, int n, const int32_t* __restrict__ idx, const float* __restrict__ plain,
+// values: a listed subset whose plain value is not above tau, or a band
+// subset whose plain value is above it, flags the kernel (flags already set
+// stay set); an unflagged kernel's list is sorted by its plain values
+// (descending, equal values by the smaller subset).  One thread per kernel.
+__global__ void confirm_kernel(int K, int n, int32_t* __restrict__ idx, float* __restrict__ plain,
                                const int32_t* __restrict__ count, const int32_t* __restrict__ band_idx,
                                const float* __restrict__ band_plain, int C, float tau, int32_t* flag) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K || flag[k]) return;
   const int cnt = count[k] < n ? count[k] : n;
   bool bad = false;
-  for (int i = 0; i < cnt; ++i) {
-    const float v = plain[(int64_t)k * n + i];
-    bad |= !(v > tau);
-    if (i > 0) {
-      const float u = plain[(int64_t)k * n + i - 1];
-      bad |= !(u > v || (u == v && idx[(int64_t)k * n + i - 1] < idx[(int64_t)k * n + i]));
-    }
-  }
+  for (int i = 0; i < cnt; ++i) bad |= !(plain[(int64_t)k * n + i] > tau);
   for (int j = 0; j < C; ++j)
     if (band_idx[(int64_t)k * C + j] >= 0) bad |= band_plain[(int64_t)k * C + j] > tau;
-  if (bad) flag[k] = 1;
+  if (bad) {
+    flag[k] = 1;
+    return;
+  }
+  // insertion sort of at most SUGG_MAX_SUGGEST entries
+  int32_t* ip = idx + (int64_t)k * n;
+  float* vp = plain + (int64_t)k * n;
+  for (int i = 1; i < cnt; ++i) {
+    const float v = vp[i];
+    const int32_t s = ip[i];
+    int j = i;
+    while (j > 0 && (vp[j - 1] < v || (vp[j - 1] == v && ip[j - 1] > s))) {
+      vp[j] = vp[j - 1];
+      ip[j] = ip[j - 1];
+      --j;
+    }
+    vp[j] = v;
+    ip[j] = s;
+  }
 }
 
-hipError_t launch_confirm(int32_t K, int32_t n, const int32_t* idx, const float* plain, const int32_t* count,
+hipError_t launch_confirm(int32_t K, int32_t n, int32_t* idx, float* plain, const int32_t* count,
                           const int32_t* band_idx, const float* band_plain, int32_t C, float tau, int32_t* flag,
                           hipStream_t s) {
   if (K <= 0) return hipSuccess;

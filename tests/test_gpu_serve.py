@@ -180,7 +180,7 @@ def _check_served(ys, table_o, row_off, flag, out, tol, tag):
         listed = judged[:len(P.rank(ys[k], P.TAU, 3, first=1))]
         if any(abs(abs(ys[k, S] - plain_k[S]) - tol) <= 1e-4 for S in judged) or \
                 any(abs(plain_k[S] - P.TAU) <= 2e-5 for S in judged) or \
-                any(abs(plain_k[a] - plain_k[b]) <= 2e-5 for a, b in zip(listed, listed[1:])):
+                any(abs(plain_k[a] - plain_k[b]) <= 2e-5 for i, a in enumerate(listed) for b in listed[i + 1:]):
             exempt += 1
             continue
         assert flag[k] == int(fb), (tag, k)
