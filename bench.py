@@ -49,14 +49,25 @@ def path_bytes(N, E, K, n, table=True, tsize=4):
     return N * (E + 1) * tsize + (N * tsize if table else 0) + K * n * (4 + tsize) + K * 4
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_1910_07776_amd", "csrc", "path_impl.hpp")
+CSRC = os.path.join(ROOT, "paper_1910_07776_amd", "csrc")
+# scoring kernel of each launch form and the source file that defines it
+KERNEL_SRC = {"path_kernel": os.path.join(CSRC, "path_impl.hpp"),
+              "path_split_kernel": os.path.join(CSRC, "path_split.hip"),
+              "path_chunk_kernel": os.path.join(CSRC, "path_stream.hip")}
+
+
+def scoring_kernel(tuned) -> str:
+    """Name of the scoring kernel a launch shape runs (unroll 0: split form,
+    below 0: streaming form, else the fused persistent kernel)."""
+    u = tuned.get("unroll", 1)
+    return "path_split_kernel" if u == 0 else "path_chunk_kernel" if u < 0 else "path_kernel"
 
 
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of the scoring kernel from rocprofv3 FETCH_SIZE and
     WRITE_SIZE (scaled by a 1 GiB copy's readings), recorded in profiles/ with
-    the fused kernel source's hash; None if the kernel changed since or no
-    record exists for this form and workload."""
+    the hash of the source that defines the kernel; None if that source
+    changed since or no record exists for this form and workload."""
     import hashlib
     try:
         path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
@@ -64,7 +75,7 @@ def measured_traffic(kernel: str, workload: str):
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    cur = hashlib.sha256(open(KERNEL_SRC[kernel], "rb").read()).hexdigest()
     if kv.get("source_sha256") != cur:
         return None
     return float(kv["traffic_bytes_per_launch"])
@@ -238,7 +249,7 @@ def plain512_extra(G, dev, train, test, no_cpu=False):
     G.sync(ctx)
     us = e0.elapsed_time(e1) / (reps * N_BATCHES) * 1e3
     by = path_bytes(nb_rows, E, K_BATCH, n)
-    kernel = "path_split_kernel" if tuned.get("unroll") == 0 else "path_kernel"
+    kernel = scoring_kernel(tuned)
     timing = pass_timing(G, ctx, plan, views, outs, g, stream)
     accuracy = plain_accuracy(outs[0]["table"].cpu().numpy().astype(np.float64), test, K_BATCH)
     res = {"workload": "512 kernels x 64 versions x 128 FP32 events, top-3 per kernel",
@@ -634,7 +645,7 @@ def ragged_headline(G, ctx, dev, steps, warm, no_cpu=False):
     entries = int(te.N - te.K)
     by = path_bytes(te.N, E, te.K, n)
     gbs = by / (ms / 1e3) / 1e9
-    kernel = "path_split_kernel" if tuned.get("unroll") == 0 else "path_kernel"
+    kernel = scoring_kernel(tuned)
     log(f"ragged: {ms:.3f} ms/pass, {gbs:.0f} GB/s, wall {wall:.2f} s")
     table = out["table"].cpu().numpy().astype(np.float64)
     bs = np.bincount(te.nopts, minlength=11)

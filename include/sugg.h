@@ -103,21 +103,38 @@ SUGG_API int32_t sugg_plan_max_opts(const sugg_plan* plan); /* max B_k, or -1 */
  * many as fit on the device at once).  unroll = 0 selects the split form for
  * plans whose kernels all have the same B <= 6 and the same ids: 16 versions
  * per workgroup, the last of a kernel's workgroups composing and ranking it
- * (per-plan counters, re-armed by each launch; used by sugg_suggest and
- * sugg_predict without a grid; other calls take the fused form with unroll 1).
- * Results do not depend on it. */
+ * (per-plan counters, re-armed by each launch).  unroll = -1, -2 or -4
+ * selects the streaming form (1, 2 or 4 rows per lane group and stage):
+ * workgroups of 4 waves each take a chunk of consecutive whole kernels in
+ * memory order (about sugg_plan_get_items rows, any mix of B) and stream,
+ * compose and rank it.  The split and streaming forms serve sugg_suggest and
+ * sugg_predict without a grid; other calls take the fused form with unroll
+ * 1.  Results do not depend on the shape. */
 SUGG_API int32_t sugg_plan_set_launch(sugg_plan* plan, int32_t waves, int32_t unroll, int32_t grid);
 SUGG_API int32_t sugg_plan_get_launch(const sugg_plan* plan, int32_t* waves, int32_t* unroll, int32_t* grid);
 
+/* Work-item size of the plan's scoring pass: kernels of equal B are packed
+ * into items of about `rows` versions for the fused form, and consecutive
+ * kernels into chunks of at most `rows` versions for the streaming form (a
+ * kernel with more versions is an item or chunk alone); 16 <= rows <= 4096.  Rebuilds and uploads the work list
+ * (synchronous; not inside a graph capture).  Results do not depend on it.
+ * sugg_plan_get_items returns the current size (-1 for a null plan). */
+SUGG_API int32_t sugg_plan_set_items(sugg_ctx* ctx, sugg_plan* plan, int32_t rows);
+SUGG_API int32_t sugg_plan_get_items(const sugg_plan* plan);
+
 /* Autotuner: times the fused scoring pass (sugg_suggest) of this plan on the
- * given inputs for every candidate launch shape (waves 2, 4, 8 x unroll
- * 1, 2, 4, in that order, then the split form where the plan has one; reps
- * timed passes each after one warm-up) and keeps the fastest in the plan.
- * times_ms (nullable, 10 floats) receives the mean pass time of each
- * candidate (-1 for a split form the plan does not have).  Needs a fitted model; allocates and frees
- * temporary outputs; synchronises the stream. */
+ * given inputs for every candidate: for item sizes 128, 256, 512, 1024 rows,
+ * waves 2, 4, 8 x unroll 1, 2, 4, then the streaming form with unroll -1,
+ * -2, -4 (12 shapes per size, in that order), then the split form where the
+ * plan has one (with the plan's item size); reps timed passes each after
+ * one warm-up; keeps the fastest in the plan.  times_ms (nullable, at least
+ * SUGG_TUNE_CANDIDATES floats, times_cap its length) receives the mean pass
+ * time of each candidate (-1 for one the plan cannot run: an item size whose
+ * workspace exceeds LDS, a split form it does not have).  Needs a fitted
+ * model; allocates and frees temporary outputs; synchronises the stream. */
+#define SUGG_TUNE_CANDIDATES 49
 SUGG_API int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, const void* cycles,
-                               int32_t reps, float* times_ms, hipStream_t stream);
+                               int32_t reps, float* times_ms, int32_t times_cap, hipStream_t stream);
 
 /* Tier 1 (Section 2): features are ln(counter / cycles).
  * mode SUGG_FIT_STATS: set the context's column statistics (mean, population

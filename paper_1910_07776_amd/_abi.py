@@ -21,6 +21,7 @@ SUGG_MAX_OPTS = 12
 SUGG_MAX_EVENTS = 256
 SUGG_MAX_GLOBAL_OPTS = 64
 SUGG_MAX_SUGGEST = 8
+SUGG_TUNE_CANDIDATES = 49
 
 
 class SuggError(RuntimeError):
@@ -55,7 +56,9 @@ SIGNATURES = {
     "sugg_plan_max_opts": (_I32, [_P]),
     "sugg_plan_set_launch": (_I32, [_P, _I32, _I32, _I32]),
     "sugg_plan_get_launch": (_I32, [_P, _PI32, _PI32, _PI32]),
-    "sugg_autotune": (_I32, [_P, _P, _P, _P, _I32, C.POINTER(C.c_float), _P]),
+    "sugg_autotune": (_I32, [_P, _P, _P, _P, _I32, C.POINTER(C.c_float), _I32, _P]),
+    "sugg_plan_set_items": (_I32, [_P, _P, _I32]),
+    "sugg_plan_get_items": (_I32, [_P]),
     "sugg_load_features": (_I32, [_P, _P, _P, _P, _I32, _P, _P]),
     "sugg_load_features_noalloc": (_I32, [_P, _P, _P, _P, _I32, _P, _P]),
     "sugg_fit": (_I32, [_P, _P, _P, _P, _P]),

@@ -81,6 +81,77 @@ void build_items(const std::vector<int32_t>& nopts, const std::vector<int64_t>& 
   }
 }
 
+// The plan's work list for items of about `target` rows (build_items), the
+// arithmetic geometry of batches whose kernels all have one B, and the
+// kernel records; replaces a previous list.  Synchronous.
+hipError_t plan_items(sugg_plan* p, int target) {
+  const int K = p->K;
+  std::vector<Item> items;
+  std::vector<int32_t> ik;
+  build_items(p->nopts, p->row_off, target, items, ik, p->max_item_rows, p->max_item_kernels);
+  p->item_rows = target;
+  // a batch whose kernels all have the same B gets arithmetic item geometry
+  p->uni_B = -1;
+  p->uni_nk = 0;
+  p->uni_ops = 0;
+  p->uni_opt_lo = p->uni_opt_hi = 0;
+  if (K > 0 && std::all_of(p->nopts.begin(), p->nopts.end(), [&](int32_t b) { return b == p->nopts[0]; })) {
+    p->uni_B = p->nopts[0];
+    p->uni_nk = items[0].nk;
+    // and when every kernel also carries the same optimisation ids
+    bool same = true;
+    for (int k = 1; k < K && same; ++k)
+      for (int b = 0; b < p->uni_B; ++b) same &= p->opt_ids[p->opt_off[k] + b] == p->opt_ids[b];
+    if (same) {
+      p->uni_ops = 1;
+      for (int b = 0; b < p->uni_B; ++b) {
+        const uint64_t o = (uint64_t)(uint8_t)p->opt_ids[b];
+        if (b < 8) p->uni_opt_lo |= o << (8 * b);
+        else p->uni_opt_hi |= o << (8 * (b - 8));
+      }
+    }
+  }
+  p->n_items = (int)items.size();
+  std::vector<KRec> recs(ik.size());
+  for (size_t i = 0; i < ik.size(); ++i) {
+    const int k = ik[i];
+    KRec& r = recs[i];
+    std::memset(&r, 0, sizeof r);
+    r.row_off = p->row_off[k];
+    r.kid = k;
+    for (int b = 0; b < p->nopts[k]; ++b) r.opt[b] = (uint8_t)p->opt_ids[p->opt_off[k] + b];
+  }
+  // streaming form: consecutive whole kernels in memory order, a chunk closed
+  // before it would pass `target` rows (a larger kernel is a chunk alone)
+  std::vector<Chunk> chunks;
+  p->chunk_max_rows = 1;
+  p->chunk_max_nk = 1;
+  for (int k = 0; k < K;) {
+    Chunk c;
+    std::memset(&c, 0, sizeof c);
+    c.row0 = p->row_off[k];
+    c.k0 = k;
+    int64_t rows = 0;
+    while (k < K && (c.nk == 0 || rows + ((int64_t)1 << p->nopts[k]) <= target)) {
+      rows += (int64_t)1 << p->nopts[k];
+      ++c.nk;
+      ++k;
+    }
+    c.R = (int32_t)rows;
+    p->chunk_max_rows = std::max(p->chunk_max_rows, c.R);
+    p->chunk_max_nk = std::max(p->chunk_max_nk, c.nk);
+    chunks.push_back(c);
+  }
+  p->n_chunks = (int)chunks.size();
+  dfree(p->d_items);
+  dfree(p->d_recs);
+  dfree(p->d_chunks);
+  hipError_t e = upload(p->d_items, items.data(), sizeof(Item) * items.size());
+  if (e == hipSuccess) e = upload(p->d_recs, recs.data(), sizeof(KRec) * recs.size());
+  if (e == hipSuccess) e = upload(p->d_chunks, chunks.data(), sizeof(Chunk) * chunks.size());
+  return e;
+}
+
 template <typename T>
 const T* model_mu(sugg_ctx* c);
 template <>
@@ -241,13 +312,15 @@ int check_model_for(sugg_ctx* ctx, const sugg_plan* p) {
 // metadata, cross-wave lists) for the widest configuration.
 size_t path_lds_bound(size_t tsize, int D, int E, int max_rows, int max_nk, int max_B) {
   const int vpl = E <= 64 ? 4 : (E <= 128 ? 8 : 16);
-  return tsize * ((size_t)D * 16 * vpl + D + 2 * (size_t)max_rows) + 16 * (size_t)max_nk * (1 + max_B) +
+  return tsize * ((size_t)D * 16 * vpl + D + 2 * 16 * vpl + 2 * (size_t)max_rows) + 16 * (size_t)max_nk * (1 + max_B) +
          (tsize + 8) * 8 * 8 + 256;
 }
 
 constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+constexpr int kTuneItems[] = {128, 256, 512, 1024};
 constexpr int kTuneWaves[] = {2, 4, 8};
 constexpr int kTuneUnroll[] = {1, 2, 4};
+static_assert(4 * (3 * 3 + 3) + 1 == SUGG_TUNE_CANDIDATES, "autotuner candidate count");
 
 template <typename T>
 int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* grid, T* table,
@@ -287,8 +360,36 @@ int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* gri
   a.status = ctx->d_status;
   if (p->cfg.unroll == 0 && p->split_ok() && !grid && !kmask)
     return ctx->hip(launch_path_split<T>(a, p->d_arrivals, (T*)p->d_split_edges, s), "scoring kernel");
+  if (p->cfg.unroll < 0 && !grid && !kmask &&
+      path_chunk_lds(sizeof(T), ctx->D, p->E, p->chunk_max_rows, p->chunk_max_nk) <= kLdsPerWorkgroup) {
+    ChunkArgs<T> ch;
+    ch.counters = c;
+    ch.cycles = cyc;
+    ch.E = p->E;
+    ch.D = ctx->D;
+    ch.W = a.W;
+    ch.ldw = a.ldw;
+    ch.mu = a.mu;
+    ch.isg = a.isg;
+    ch.row_off = p->d_row_off;
+    ch.nopts = p->d_nopts;
+    ch.opt_off = p->d_opt_off;
+    ch.opt_ids = p->d_opt_ids;
+    ch.chunks = p->d_chunks;
+    ch.n_chunks = p->n_chunks;
+    ch.max_rows = p->chunk_max_rows;
+    ch.max_nk = p->chunk_max_nk;
+    ch.table = table;
+    ch.idx_out = idx;
+    ch.score_out = score;
+    ch.count_out = count;
+    ch.n = n;
+    ch.tau = (T)ctx->params.tau;
+    ch.status = ctx->d_status;
+    return ctx->hip(launch_path_chunks<T>(ch, -p->cfg.unroll, s), "scoring kernel (streaming form)");
+  }
   PathLaunch cfg = p->cfg;
-  if (cfg.unroll == 0) cfg.unroll = 1;   // the split form does not apply: fused, one row per stage
+  if (cfg.unroll <= 0) cfg.unroll = 1;   // the split or streaming form does not apply: fused, one row per stage
   return ctx->hip(launch_path<T>(a, p->max_item_rows, p->max_item_kernels, std::max(1, p->Bmax), cfg, s),
                   "scoring kernel");
 }
@@ -477,46 +578,12 @@ int32_t sugg_plan_create(sugg_ctx* ctx, int32_t K, int32_t E, int32_t D, int32_t
   const int cus = cu_count(ctx->device);
   int target = 256;
   while (target > 64 && p->N / target < 2 * cus) target >>= 1;
-  std::vector<Item> items;
-  std::vector<int32_t> ik;
-  build_items(p->nopts, p->row_off, target, items, ik, p->max_item_rows, p->max_item_kernels);
-  // a batch whose kernels all have the same B gets arithmetic item geometry
-  p->uni_B = -1;
-  p->uni_nk = 0;
-  if (K > 0 && std::all_of(p->nopts.begin(), p->nopts.end(), [&](int32_t b) { return b == p->nopts[0]; })) {
-    p->uni_B = p->nopts[0];
-    p->uni_nk = items[0].nk;
-    // and when every kernel also carries the same optimisation ids
-    bool same = true;
-    for (int k = 1; k < K && same; ++k)
-      for (int b = 0; b < p->uni_B; ++b) same &= p->opt_ids[p->opt_off[k] + b] == p->opt_ids[b];
-    if (same) {
-      p->uni_ops = 1;
-      for (int b = 0; b < p->uni_B; ++b) {
-        const uint64_t o = (uint64_t)(uint8_t)p->opt_ids[b];
-        if (b < 8) p->uni_opt_lo |= o << (8 * b);
-        else p->uni_opt_hi |= o << (8 * (b - 8));
-      }
-    }
-  }
-  p->n_items = (int)items.size();
   p->stat_chunks = colstats_chunks(std::max<int64_t>(p->N, 1));
-  hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = upload(p->d_items, items.data(), sizeof(Item) * items.size());
+  hipError_t e = plan_items(p, target);
   if (e == hipSuccess) e = upload(p->d_row_off, p->row_off.data(), sizeof(int64_t) * (K + 1));
   if (e == hipSuccess) e = upload(p->d_opt_off, p->opt_off.data(), sizeof(int64_t) * (K + 1));
   if (e == hipSuccess) e = upload(p->d_opt_ids, p->opt_ids.data(), sizeof(int32_t) * nid);
   if (e == hipSuccess) e = upload(p->d_nopts, p->nopts.data(), sizeof(int32_t) * K);
-  std::vector<KRec> recs(ik.size());
-  for (size_t i = 0; i < ik.size(); ++i) {
-    const int k = ik[i];
-    KRec& r = recs[i];
-    std::memset(&r, 0, sizeof r);
-    r.row_off = p->row_off[k];
-    r.kid = k;
-    for (int b = 0; b < p->nopts[k]; ++b) r.opt[b] = (uint8_t)p->opt_ids[p->opt_off[k] + b];
-  }
-  if (e == hipSuccess) e = upload(p->d_recs, recs.data(), sizeof(KRec) * recs.size());
   if (e == hipSuccess) e = upload(p->d_queue, nullptr, 64);
   if (e == hipSuccess) e = hipMemset(p->d_queue, 0, 64);
   if (e == hipSuccess && p->uni_B >= 0 && p->uni_B <= 6 && p->uni_ops) {
@@ -874,13 +941,25 @@ int32_t sugg_sync(sugg_ctx* ctx, hipStream_t stream) {
 
 int32_t sugg_plan_set_launch(sugg_plan* plan, int32_t waves, int32_t unroll, int32_t grid) {
   if (!plan) return SUGG_E_ARG;
-  if (waves < 1 || waves > 8 || (unroll != 0 && unroll != 1 && unroll != 2 && unroll != 4) || grid < 0)
+  if (waves < 1 || waves > 8 || grid < 0) return SUGG_E_ARG;
+  if (unroll != 0 && unroll != 1 && unroll != 2 && unroll != 4 && unroll != -1 && unroll != -2 && unroll != -4)
     return SUGG_E_ARG;
   plan->cfg.waves = waves;
   plan->cfg.unroll = unroll;
   plan->cfg.grid = grid;
   return SUGG_OK;
 }
+
+int32_t sugg_plan_set_items(sugg_ctx* ctx, sugg_plan* plan, int32_t rows) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (rows < 16 || rows > 4096) return ctx->fail(SUGG_E_ARG, "item rows %d outside [16, 4096]", rows);
+  if (rows == plan->item_rows) return SUGG_OK;
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  return ctx->hip(plan_items(plan, rows), "plan items");
+}
+
+int32_t sugg_plan_get_items(const sugg_plan* plan) { return plan ? plan->item_rows : -1; }
 
 int32_t sugg_plan_get_launch(const sugg_plan* plan, int32_t* waves, int32_t* unroll, int32_t* grid) {
   if (!plan || !waves || !unroll || !grid) return SUGG_E_ARG;
@@ -891,11 +970,13 @@ int32_t sugg_plan_get_launch(const sugg_plan* plan, int32_t* waves, int32_t* unr
 }
 
 int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, const void* cycles, int32_t reps,
-                      float* times_ms, hipStream_t stream) {
+                      float* times_ms, int32_t times_cap, hipStream_t stream) {
   if (!ctx) return SUGG_E_ARG;
   if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
   if (plan->K == 0) return SUGG_OK;
   if (!counters || !cycles || reps < 1) return ctx->fail(SUGG_E_ARG, "null input or reps < 1");
+  if (times_ms && times_cap < SUGG_TUNE_CANDIDATES)
+    return ctx->fail(SUGG_E_ARG, "times_ms holds %d entries, %d needed", times_cap, SUGG_TUNE_CANDIDATES);
   int rc = check_model_for(ctx, plan);
   if (rc) return rc;
   if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
@@ -910,13 +991,30 @@ int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, cons
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   const PathLaunch keep = plan->cfg;
+  const int keep_items = plan->item_rows;
   PathLaunch best = keep;
+  int best_items = keep_items;
   float best_ms = 1e30f;
   int ci = 0;
-  for (int w : kTuneWaves) {
-    for (int u : kTuneUnroll) {
+  std::vector<std::pair<int, int>> shapes;   // (waves, unroll): fused shapes, then the streaming form
+  for (int w : kTuneWaves)
+    for (int u : kTuneUnroll) shapes.push_back({w, u});
+  for (int u : {-1, -2, -4}) shapes.push_back({4, u});
+  for (int ir : kTuneItems)
+    for (const auto& wu : shapes) {
       if (e != hipSuccess) break;
-      plan->cfg = PathLaunch{w, u, 0};
+      if (plan->item_rows != ir) e = plan_items(plan, ir);
+      if (e != hipSuccess) break;
+      const int u = wu.second;
+      plan->cfg = PathLaunch{wu.first, u, 0};
+      const size_t lds = u > 0 ? path_lds_bound(ts, ctx->D, plan->E, plan->max_item_rows, plan->max_item_kernels,
+                                                plan->Bmax)
+                               : path_chunk_lds(ts, ctx->D, plan->E, plan->chunk_max_rows, plan->chunk_max_nk);
+      if (lds > kLdsPerWorkgroup) {   // this item size does not fit
+        if (times_ms) times_ms[ci] = -1.f;
+        ++ci;
+        continue;
+      }
       float ms = 0.f;
       for (int rep = -1; rep < reps && e == hipSuccess; ++rep) {   // rep -1 warms up
         if (rep == 0) e = hipEventRecord(e0, stream);
@@ -936,12 +1034,13 @@ int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, cons
       if (e == hipSuccess && ms < best_ms) {
         best_ms = ms;
         best = plan->cfg;
+        best_items = plan->item_rows;
       }
       ++ci;
     }
-  }
   // the split form (equal kernels of at most 64 versions): one more candidate
   if (times_ms) times_ms[ci] = -1.f;
+  if (e == hipSuccess && plan->item_rows != keep_items) e = plan_items(plan, keep_items);
   if (e == hipSuccess && plan->split_ok()) {
     plan->cfg = PathLaunch{4, 0, 0};
     float ms = 0.f;
@@ -963,9 +1062,15 @@ int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, cons
     if (e == hipSuccess && ms < best_ms) {
       best_ms = ms;
       best = plan->cfg;
+      best_items = plan->item_rows;
     }
   }
   plan->cfg = e == hipSuccess ? best : keep;
+  const int want_items = e == hipSuccess ? best_items : keep_items;
+  if (plan->item_rows != want_items) {
+    const hipError_t e2 = plan_items(plan, want_items);
+    if (e == hipSuccess) e = e2;
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(table);

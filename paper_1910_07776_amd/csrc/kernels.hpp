@@ -99,6 +99,46 @@ hipError_t launch_path_vpl(const PathArgs<T>& a, int max_item_rows, int max_item
 template <typename T>
 hipError_t launch_path_split(const PathArgs<T>& a, int32_t* arrivals, T* edges, hipStream_t s);
 
+// The streaming form of the scoring pass: workgroups take chunks of
+// consecutive whole kernels in memory order (mixed B), one chunk each.
+struct alignas(16) Chunk {
+  int64_t row0;   // first row
+  int32_t k0;     // first kernel
+  int32_t nk;     // kernels
+  int32_t R;      // rows
+  int32_t pad[3];
+};
+template <typename T>
+struct ChunkArgs {
+  const T* counters;
+  const T* cycles;
+  int32_t E;
+  int32_t D;
+  const T* W;
+  int32_t ldw;
+  const T* mu;
+  const T* isg;
+  const int64_t* row_off;    // [K+1]
+  const int32_t* nopts;      // [K]
+  const int64_t* opt_off;    // [K+1]
+  const int32_t* opt_ids;
+  const Chunk* chunks;
+  int32_t n_chunks;
+  int32_t max_rows;          // largest chunk
+  int32_t max_nk;            // most kernels in a chunk
+  T* table;                  // nullable
+  int32_t* idx_out;          // nullable (then no ranking)
+  T* score_out;
+  int32_t* count_out;
+  int32_t n;
+  T tau;
+  int32_t* status;
+};
+template <typename T>
+hipError_t launch_path_chunks(const ChunkArgs<T>& a, int unroll, hipStream_t s);
+// dynamic LDS of the streaming form
+size_t path_chunk_lds(size_t tsize, int D, int E, int max_rows, int max_nk);
+
 template <typename T>
 hipError_t launch_path(const PathArgs<T>& a, int max_item_rows, int max_item_kernels,
                        int max_B, const PathLaunch& cfg, hipStream_t s);

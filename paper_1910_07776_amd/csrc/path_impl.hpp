@@ -138,7 +138,7 @@ __device__ __forceinline__ void column_constants(const T* mu, const T* isg, int 
 // Dynamic LDS layout of the fused kernel (host and device agree on it).
 struct PathSmem {
   int ep;        // padded weight row length
-  size_t W, Wb, e, L, kro, kid, kop, xw, total;
+  size_t W, Wb, sm, e, L, kro, kid, kop, xw, total;
 };
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -151,6 +151,7 @@ __host__ __device__ inline PathSmem path_smem(int D, int max_rows, int max_nk, i
   s.W = o;   o += sizeof(T) * (size_t)D * s.ep;
   s.Wb = o;  o += sizeof(T) * (size_t)D;
   o = align_up(o, 16);
+  s.sm = o;  o += sizeof(T) * 2 * (size_t)s.ep;
   s.e = o;   o += sizeof(T) * (size_t)max_rows;
   s.L = o;   o += sizeof(T) * (size_t)max_rows;
   o = align_up(o, 16);
@@ -212,7 +213,7 @@ __device__ __forceinline__ void write_list(const Entry<T> (&L)[KT], int k, int n
 // FULL: E == 16 * VPL (every lane column is a real column, no bounds checks).
 // GRID: the per-optimisation grid is written (every b not in S predicted).
 template <typename T, int VPL, int VW, int U, int KT, bool FULL, bool GRID>
-__global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const int max_rows,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((U == 1 && !GRID && KT <= 4) ? 5 : 1, 8))) path_kernel(const PathArgs<T> a, const int max_rows,
                                                    const int max_nk, const int max_B) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NCH = VPL / VW;
@@ -235,33 +236,78 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
   const int EP = ly.ep;
   // this lane's columns: chunk ch covers columns (l16 + 16 ch) * VW + [0, VW);
   // z = fma(log(c) - log(cyc), s, m) with s = unit / sigma, m = -mu / sigma
-  T s_r[NCH][VW], m_r[NCH][VW];
+  T* sml = reinterpret_cast<T*>(smem + ly.sm);
   // weights, intercepts and column constants are staged after the first
   // item's row loads are in flight (so the two memory latencies overlap)
   auto stage_model = [&]() {
     stage_weights<T, FULL>(a.W, a.ldw, D, E, EP, Wl, Wb, tid, nthr);
-    column_constants<T, NCH, VW, FULL>(a.mu, a.isg, E, l16, s_r, m_r);
+    if (tid < kRowLanes) {
+      T s0[NCH][VW], m0[NCH][VW];
+      column_constants<T, NCH, VW, FULL>(a.mu, a.isg, E, l16, s0, m0);
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+          sml[(l16 + kRowLanes * ch) * VW + v] = s0[ch][v];
+          sml[EP + (l16 + kRowLanes * ch) * VW + v] = m0[ch][v];
+        }
+    }
   };
   bool staged = false;
   T ca[U][NCH][VW], cb[U][NCH][VW];
   T cya[U], cyb[U];
   bool bad = false;
 
-  int it = blockIdx.x;
-  while (it < a.n_items) {
-    if (dynamic && tid == 0) s_next = (int)gridDim.x + atomicAdd(a.queue, 1);
-    Item item;
+  auto get_item = [&](int i) -> Item {
+    Item t;
     if (a.uni_B >= 0) {
       // every kernel has uni_B optimisations and items take uni_nk adjacent
       // kernels in batch order: the item needs no lookup
-      item.first = it * a.uni_nk;
-      item.nk = min(a.uni_nk, a.K - item.first);
-      item.B = a.uni_B;
-      item.R = item.nk << a.uni_B;
-      item.row0 = (int64_t)item.first << a.uni_B;
+      t.first = i * a.uni_nk;
+      t.nk = min(a.uni_nk, a.K - t.first);
+      t.B = a.uni_B;
+      t.R = t.nk << a.uni_B;
+      t.row0 = (int64_t)t.first << a.uni_B;
     } else {
-      item = a.items[it];
+      t = a.items[i];
     }
+    return t;
+  };
+  const int step = nwaves * 4 * U;
+  const int b0 = wave * 4 * U;
+  // Loads of an item's rows straight from the work list (kernel records in
+  // global memory): used for the rows requested before the item's metadata
+  // is in LDS, i.e. the first two row groups of the next item, issued while
+  // the current one is composed and ranked.
+  auto load_ahead = [&](const Item& t, int base, T (&c)[U][NCH][VW], T (&cy)[U]) {
+    const uint32_t m = (1u << t.B) - 1u;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int rr = base + u * 4 + grp;
+      rr = rr < t.R ? rr : t.R - 1;
+      const int64_t grow = t.row0 >= 0 ? t.row0 + rr : a.recs[t.first + (rr >> t.B)].row_off + (rr & m);
+      const T* rp = a.counters + grow * E;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const int c0 = (l16 + kRowLanes * ch) * VW;
+        if (FULL || c0 < E) {
+          const VecN<T, VW> q = *reinterpret_cast<const VecN<T, VW>*>(rp + c0);
+#pragma unroll
+          for (int v = 0; v < VW; ++v) c[u][ch][v] = q.v[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < VW; ++v) c[u][ch][v] = T(1);
+        }
+      }
+      cy[u] = a.cycles[grow];
+    }
+  };
+  bool ahead = false;   // the current item's first two row groups are already in flight
+
+  int it = blockIdx.x;
+  while (it < a.n_items) {
+    if (dynamic && tid == 0) s_next = (int)gridDim.x + atomicAdd(a.queue, 1);
+    const Item item = get_item(it);
     const int B = item.B, nk = item.nk, R = item.R;
     const uint32_t mask = (1u << B) - 1u;
     const bool contig = item.row0 >= 0;
@@ -295,13 +341,13 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
         cy[u] = contig ? icyc[rr] : a.cycles[grow];
       }
     };
-    const int step = nwaves * 4 * U;
-    const int b0 = wave * 4 * U;
     // adjacent kernels need no metadata for their first rows: issue them now
-    const bool early = contig && b0 < R && !a.kmask;
+    // (unless the previous item already did)
+    const bool early = (ahead || contig) && b0 < R && !a.kmask;
     const bool early2 = early && b0 + step < R;
-    if (early) load(b0, ca, cya);
-    if (early2) load(b0 + step, cb, cyb);
+    if (early && !ahead) load(b0, ca, cya);
+    if (early2 && !ahead) load(b0 + step, cb, cyb);
+    ahead = false;
     if (!staged) {
       stage_model();
       staged = true;
@@ -343,6 +389,17 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
         const int r = r0 + grp;
         const bool live = r < R;
         T z[NCH][VW];
+        T s_r[NCH][VW], m_r[NCH][VW];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          const VecN<T, VW> qs = *reinterpret_cast<const VecN<T, VW>*>(sml + (l16 + kRowLanes * ch) * VW);
+          const VecN<T, VW> qm = *reinterpret_cast<const VecN<T, VW>*>(sml + EP + (l16 + kRowLanes * ch) * VW);
+#pragma unroll
+          for (int v = 0; v < VW; ++v) {
+            s_r[ch][v] = qs.v[v];
+            m_r[ch][v] = qm.v[v];
+          }
+        }
         const T chk = row_features<T, NCH, VW>(c[u], cy[u], s_r, m_r, z);
         // a non-positive, non-normal or non-finite counter or cycle count
         // makes the checksum NaN or infinite
@@ -372,11 +429,7 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
           }
         };
         int h0 = hlo;
-        for (; h0 + 4 <= B; h0 += 4) dots(std::integral_constant<int, 4>{}, h0);
-        if (h0 + 2 <= B) {
-          dots(std::integral_constant<int, 2>{}, h0);
-          h0 += 2;
-        }
+        for (; h0 + 2 <= B; h0 += 2) dots(std::integral_constant<int, 2>{}, h0);
         if (h0 < B) dots(std::integral_constant<int, 1>{}, h0);
         if (GRID && l16 == 0 && live) {
           const int64_t grow = row_addr(r);
@@ -401,6 +454,18 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
       compute(base + step, cb, cyb);
     }
     __syncthreads();
+    // persistent mode: the next item's first two row groups go out now, so
+    // their latency overlaps this item's composition and ranking
+    int nit = a.n_items;
+    if (dynamic) {
+      nit = s_next;
+      if (nit < a.n_items && !a.kmask) {
+        const Item nx = get_item(nit);
+        if (b0 < nx.R) load_ahead(nx, b0, ca, cya);
+        if (b0 + step < nx.R) load_ahead(nx, b0 + step, cb, cyb);
+        ahead = true;
+      }
+    }
 
     // ---- compose the subset table -----------------------------------------
     // L(S) = sum over the bits b of S, ascending, of the edge into
@@ -497,9 +562,8 @@ __global__ void __launch_bounds__(512) path_kernel(const PathArgs<T> a, const in
       }
     }
     if (!dynamic) break;   // one item per workgroup
-    __syncthreads();       // this item's LDS is no longer read
-    it = s_next;
-    __syncthreads();
+    __syncthreads();       // this item's LDS is no longer read (nor s_next)
+    it = nit;
   }
   if (__ballot(bad) != 0 && lane == 0) atomicOr(a.status, (int)kStatusBadCounter);
   // In persistent mode the last workgroup to finish re-arms the work counter

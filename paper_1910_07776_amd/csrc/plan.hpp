@@ -60,12 +60,16 @@ struct sugg_plan {
   // counters (zero between launches) and the chain-edge buffer [N]
   int32_t* d_arrivals = nullptr;
   void* d_split_edges = nullptr;
+  // streaming form: chunks of consecutive whole kernels (about item_rows rows)
+  sugg::Chunk* d_chunks = nullptr;
+  int n_chunks = 0, chunk_max_rows = 1, chunk_max_nk = 1;
   bool split_ok() const { return uni_B >= 0 && uni_B <= 6 && uni_ops && d_arrivals; }
   int n_items = 0, max_item_rows = 1, max_item_kernels = 1;
   int uni_B = -1, uni_nk = 0;
   int uni_ops = 0;
   uint64_t uni_opt_lo = 0, uni_opt_hi = 0;
   sugg::PathLaunch cfg{4, 2, 0};   // launch shape of the scoring kernel (autotuned)
+  int item_rows = 256;             // target rows of a work item (autotuned)
   // statistics workspace
   double* d_stat_partial = nullptr;
   int stat_chunks = 1;
@@ -92,7 +96,7 @@ struct sugg_plan {
     ibk_plan_free(ibk);
     m5p_plan_free(m5p);
     dfree(d_items); dfree(d_recs); dfree(d_row_off); dfree(d_opt_off); dfree(d_opt_ids); dfree(d_nopts);
-    dfree(d_queue); dfree(d_arrivals); dfree(d_split_edges); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
+    dfree(d_queue); dfree(d_arrivals); dfree(d_split_edges); dfree(d_chunks); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
     dfree(d_solveA); dfree(d_reduced); dfree(d_gwork); dfree(d_pair_base); dfree(d_pair_row0); dfree(d_pair_bit);
     dfree(d_opt_work_begin);
   }

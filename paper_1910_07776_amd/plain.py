@@ -121,6 +121,13 @@ class Plan:
     def set_launch(self, waves: int, unroll: int, grid: int = 0):
         A.check(self.ctx.h, A.lib().sugg_plan_set_launch(self.h, waves, unroll, grid))
 
+    def set_items(self, rows: int):
+        """Target rows of a work item of the scoring pass (rebuilds the work list)."""
+        A.check(self.ctx.h, A.lib().sugg_plan_set_items(self.ctx.h, self.h, int(rows)))
+
+    def get_items(self) -> int:
+        return int(A.lib().sugg_plan_get_items(self.h))
+
     def get_launch(self):
         w, u, g = C.c_int32(), C.c_int32(), C.c_int32()
         A.check(self.ctx.h, A.lib().sugg_plan_get_launch(self.h, C.byref(w), C.byref(u), C.byref(g)))
@@ -406,29 +413,35 @@ def band_select(ctx: Context, scores, seg_off, top_idx, top_count, tau: float = 
     return cand, ref, flag
 
 
+TUNE_ITEMS = (128, 256, 512, 1024)
 TUNE_WAVES = (2, 4, 8)
 TUNE_UNROLL = (1, 2, 4)
 
 
 def autotune(ctx: Context, plan: Plan, counters, cycles, reps: int = 5, cache=None):
     """Time every launch shape of the plan's scoring kernel on these inputs
-    and keep the fastest.  ``cache`` (a tuning.TuneCache) is consulted first
-    and updated afterwards.  Returns the chosen shape and the timings."""
+    (item size x waves x unroll, and the split form where there is one) and
+    keep the fastest.  ``cache`` (a tuning.TuneCache) is consulted first and
+    updated afterwards.  Returns the chosen shape and the timings."""
     from . import tuning
     key = tuning.plan_key(plan, ctx.params["n_suggest"])
     if cache is not None and key in cache:
         cfg = cache[key]
+        if "items" in cfg:
+            plan.set_items(cfg["items"])
         plan.set_launch(cfg["waves"], cfg["unroll"], 0)
         return cfg
     plan.check_inputs(counters, cycles)
-    times = (C.c_float * (len(TUNE_WAVES) * len(TUNE_UNROLL) + 1))()
+    times = (C.c_float * A.SUGG_TUNE_CANDIDATES)()
     A.check(ctx.h, A.lib().sugg_autotune(ctx.h, plan.h, _ptr(counters), _ptr(cycles), int(reps), times,
-                                         _stream()))
+                                         A.SUGG_TUNE_CANDIDATES, _stream()))
     cfg = plan.get_launch()
-    cfg["times_ms"] = {f"w{w}u{u}": float(times[i * len(TUNE_UNROLL) + j])
-                       for i, w in enumerate(TUNE_WAVES) for j, u in enumerate(TUNE_UNROLL)}
-    if times[len(TUNE_WAVES) * len(TUNE_UNROLL)] >= 0:
-        cfg["times_ms"]["split"] = float(times[len(TUNE_WAVES) * len(TUNE_UNROLL)])
+    cfg["items"] = plan.get_items()
+    shapes = [f"w{w}u{u}" for w in TUNE_WAVES for u in TUNE_UNROLL] + [f"stream{u}" for u in (1, 2, 4)]
+    names = [f"i{ir}{sh}" for ir in TUNE_ITEMS for sh in shapes]
+    cfg["times_ms"] = {n: float(times[i]) for i, n in enumerate(names) if times[i] >= 0}
+    if times[len(names)] >= 0:
+        cfg["times_ms"]["split"] = float(times[len(names)])
     if cache is not None:
         cache[key] = cfg
     return cfg

@@ -112,6 +112,8 @@ def test_512_kernels_fit_predict_suggest(G, ctx):
     db = tuning.TuneCache(os.path.join(os.path.dirname(HERE), "paper_1910_07776_amd", "tuning_db.json"))
     key = tuning.plan_key(pte, 3)
     assert key in db, key
+    if "items" in db[key]:
+        pte.set_items(db[key]["items"])
     pte.set_launch(db[key]["waves"], db[key]["unroll"], 0)
     again = G.suggest(ctx, pte, c, cy)
     G.sync(ctx)
@@ -345,6 +347,8 @@ def test_ragged_16384_kernels_full_size(G):
     db = tuning.TuneCache(os.path.join(os.path.dirname(HERE), "paper_1910_07776_amd", "tuning_db.json"))
     key = tuning.plan_key(pte, 3)
     assert key in db, key
+    if "items" in db[key]:
+        pte.set_items(db[key]["items"])
     pte.set_launch(db[key]["waves"], db[key]["unroll"], 0)
     idx, score, count, table = G.suggest(ctx, pte, *gpu_inputs(te))
     G.sync(ctx)
@@ -371,7 +375,8 @@ def test_launch_shapes_and_persistent_queue_bit_identical(G, ctx, ragged):
     pte = plan_of(G, ctx, te, 12)
     c, cy = gpu_inputs(te)
     ref = [t.clone() for t in G.suggest(ctx, pte, c, cy)]
-    shapes = [(w, u, 0) for w in (1, 2, 4, 8) for u in (1, 2, 4)] + [(4, 2, 3), (2, 4, 7), (8, 1, 1)]
+    shapes = [(w, u, 0) for w in (1, 2, 4, 8) for u in (1, 2, 4)] + [(4, 2, 3), (2, 4, 7), (8, 1, 1)] + \
+        [(4, -1, 0), (4, -2, 0), (4, -4, 0)]   # the streaming form
     for w, u, g in shapes:
         pte.set_launch(w, u, g)
         for _ in range(2):
@@ -381,8 +386,22 @@ def test_launch_shapes_and_persistent_queue_bit_identical(G, ctx, ragged):
                                    torch.nan_to_num(y.double(), nan=-7.0)), (w, u, g)
     G.sync(ctx)
     cfg = G.autotune(ctx, pte, c, cy, reps=2)
-    assert cfg["waves"] in (2, 4, 8) and cfg["unroll"] in (1, 2, 4)
-    assert len(cfg["times_ms"]) == 9 and all(v > 0 for v in cfg["times_ms"].values())
+    assert cfg["waves"] in (2, 4, 8) and cfg["unroll"] in (1, 2, 4, -1, -2, -4)
+    assert cfg["items"] in (128, 256, 512, 1024)
+    assert len(cfg["times_ms"]) == 48 and all(v > 0 for v in cfg["times_ms"].values())
+    assert pte.get_items() == cfg["items"]
+    # every item size gives the same bits as the default one
+    for rows in (16, 128, 1024, 4096):
+        pte.set_items(rows)
+        pte.set_launch(4, 1, 0)
+        out = G.suggest(ctx, pte, c, cy)
+        for x, y in zip(ref, out):
+            assert torch.equal(torch.nan_to_num(x.double(), nan=-7.0), torch.nan_to_num(y.double(), nan=-7.0)), rows
+        pte.set_launch(4, 2, 3)   # persistent: items taken from the queue, the next one's rows prefetched
+        out = G.suggest(ctx, pte, c, cy)
+        for x, y in zip(ref, out):
+            assert torch.equal(torch.nan_to_num(x.double(), nan=-7.0), torch.nan_to_num(y.double(), nan=-7.0)), rows
+    G.sync(ctx)
 
 
 def test_graph_replays_match_eager(G, ctx, ragged):
@@ -491,8 +510,8 @@ def test_split_form_512_kernels_against_oracle(G):
         assert_scores(table.cpu().numpy(), otab, RTOL32, "table")
         check_suggestions(idx, score, count, otab, te.row_off, P.TAU, 3, RTOL32)
         cfg = G.autotune(c_, pte, c, cy, reps=2)
-        assert len(cfg["times_ms"]) == 10 and cfg["times_ms"]["split"] > 0
-        assert cfg["unroll"] in (0, 1, 2, 4)
+        assert len(cfg["times_ms"]) == 49 and cfg["times_ms"]["split"] > 0
+        assert cfg["unroll"] in (0, 1, 2, 4, -1, -2, -4)
     finally:
         c_.close()
 
