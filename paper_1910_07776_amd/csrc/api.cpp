@@ -124,6 +124,7 @@ hipError_t plan_items(sugg_plan* p, int target) {
   // streaming form: consecutive whole kernels in memory order, a chunk closed
   // before it would pass `target` rows (a larger kernel is a chunk alone)
   std::vector<Chunk> chunks;
+  std::vector<CRec> crec(K);
   p->chunk_max_rows = 1;
   p->chunk_max_nk = 1;
   for (int k = 0; k < K;) {
@@ -133,6 +134,11 @@ hipError_t plan_items(sugg_plan* p, int target) {
     c.k0 = k;
     int64_t rows = 0;
     while (k < K && (c.nk == 0 || rows + ((int64_t)1 << p->nopts[k]) <= target)) {
+      CRec& r = crec[k];
+      std::memset(&r, 0, sizeof r);
+      r.rel = (int16_t)rows;   // < max(target, 2^SUGG_MAX_OPTS) <= 4096
+      r.B = (int8_t)p->nopts[k];
+      for (int b = 0; b < p->nopts[k]; ++b) r.op[b] = (uint8_t)p->opt_ids[p->opt_off[k] + b];
       rows += (int64_t)1 << p->nopts[k];
       ++c.nk;
       ++k;
@@ -146,9 +152,11 @@ hipError_t plan_items(sugg_plan* p, int target) {
   dfree(p->d_items);
   dfree(p->d_recs);
   dfree(p->d_chunks);
+  dfree(p->d_crec);
   hipError_t e = upload(p->d_items, items.data(), sizeof(Item) * items.size());
   if (e == hipSuccess) e = upload(p->d_recs, recs.data(), sizeof(KRec) * recs.size());
   if (e == hipSuccess) e = upload(p->d_chunks, chunks.data(), sizeof(Chunk) * chunks.size());
+  if (e == hipSuccess) e = upload(p->d_crec, crec.data(), sizeof(CRec) * crec.size());
   return e;
 }
 
@@ -371,10 +379,7 @@ int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* gri
     ch.ldw = a.ldw;
     ch.mu = a.mu;
     ch.isg = a.isg;
-    ch.row_off = p->d_row_off;
-    ch.nopts = p->d_nopts;
-    ch.opt_off = p->d_opt_off;
-    ch.opt_ids = p->d_opt_ids;
+    ch.recs = p->d_crec;
     ch.chunks = p->d_chunks;
     ch.n_chunks = p->n_chunks;
     ch.max_rows = p->chunk_max_rows;

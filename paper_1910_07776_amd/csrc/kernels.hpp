@@ -108,6 +108,15 @@ struct alignas(16) Chunk {
   int32_t R;      // rows
   int32_t pad[3];
 };
+// One kernel of a chunk (kernel order, one record per kernel of the batch):
+// its first row relative to its chunk's, its B and global ids (bit b <-> op[b]).
+struct alignas(16) CRec {
+  int16_t rel;
+  int8_t B;
+  int8_t pad;
+  uint8_t op[12];
+};
+static_assert(sizeof(CRec) == 16 && SUGG_MAX_OPTS <= 12, "chunk kernel record");
 template <typename T>
 struct ChunkArgs {
   const T* counters;
@@ -118,10 +127,7 @@ struct ChunkArgs {
   int32_t ldw;
   const T* mu;
   const T* isg;
-  const int64_t* row_off;    // [K+1]
-  const int32_t* nopts;      // [K]
-  const int64_t* opt_off;    // [K+1]
-  const int32_t* opt_ids;
+  const CRec* recs;          // [K]
   const Chunk* chunks;
   int32_t n_chunks;
   int32_t max_rows;          // largest chunk
@@ -134,6 +140,7 @@ struct ChunkArgs {
   T tau;
   int32_t* status;
 };
+// unroll: rows per lane group per stage (1, 2, 4); one workgroup per chunk
 template <typename T>
 hipError_t launch_path_chunks(const ChunkArgs<T>& a, int unroll, hipStream_t s);
 // dynamic LDS of the streaming form

@@ -62,6 +62,7 @@ struct sugg_plan {
   void* d_split_edges = nullptr;
   // streaming form: chunks of consecutive whole kernels (about item_rows rows)
   sugg::Chunk* d_chunks = nullptr;
+  sugg::CRec* d_crec = nullptr;   // [K] each kernel's record within its chunk
   int n_chunks = 0, chunk_max_rows = 1, chunk_max_nk = 1;
   bool split_ok() const { return uni_B >= 0 && uni_B <= 6 && uni_ops && d_arrivals; }
   int n_items = 0, max_item_rows = 1, max_item_kernels = 1;
@@ -96,7 +97,7 @@ struct sugg_plan {
     ibk_plan_free(ibk);
     m5p_plan_free(m5p);
     dfree(d_items); dfree(d_recs); dfree(d_row_off); dfree(d_opt_off); dfree(d_opt_ids); dfree(d_nopts);
-    dfree(d_queue); dfree(d_arrivals); dfree(d_split_edges); dfree(d_chunks); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
+    dfree(d_queue); dfree(d_arrivals); dfree(d_split_edges); dfree(d_chunks); dfree(d_crec); dfree(d_stat_partial); dfree(d_z64); dfree(d_lcyc64); dfree(d_gram_partial);
     dfree(d_solveA); dfree(d_reduced); dfree(d_gwork); dfree(d_pair_base); dfree(d_pair_row0); dfree(d_pair_bit);
     dfree(d_opt_work_begin);
   }
