@@ -358,10 +358,16 @@ def graph_check(G, ctx, plan, views, outs, tuned, reps: int = 20):
     last-level cache; here the tuned shape and a few others are timed as the
     measurement runs them (one graph of 32 passes over distinct batches) and
     the fastest is kept.  Returns us per pass of each shape."""
+    import re
     import torch
-    shapes = {"tuned": (plan.get_items(), tuned["waves"], tuned["unroll"]), "i256w4u1": (256, 4, 1),
-              "i256w8u1": (256, 8, 1), "i128w8u1": (128, 8, 1), "split": (plan.get_items(), 4, 0),
-              "i256stream2": (256, 4, -2)}
+    shapes = {"tuned": (plan.get_items(), tuned["waves"], tuned["unroll"]), "split": (plan.get_items(), 4, 0)}
+    # the next four by the autotuner's own times
+    for name in sorted(tuned.get("times_ms", {}), key=tuned["times_ms"].get):
+        m = re.fullmatch(r"i(\d+)(?:w(\d+)u(\d+)|stream(\d+))", name)
+        if m and len(shapes) < 6:
+            shape = (int(m[1]), int(m[2]), int(m[3])) if m[2] else (int(m[1]), 4, -int(m[4]))
+            if shape not in shapes.values():
+                shapes[name] = shape
     res = {}
     stream = torch.cuda.current_stream()
     for name, (items, w, u) in shapes.items():

@@ -123,16 +123,16 @@ SUGG_API int32_t sugg_plan_set_items(sugg_ctx* ctx, sugg_plan* plan, int32_t row
 SUGG_API int32_t sugg_plan_get_items(const sugg_plan* plan);
 
 /* Autotuner: times the fused scoring pass (sugg_suggest) of this plan on the
- * given inputs for every candidate: for item sizes 128, 256, 512, 1024 rows,
- * waves 2, 4, 8 x unroll 1, 2, 4, then the streaming form with unroll -1,
- * -2, -4 (12 shapes per size, in that order), then the split form where the
- * plan has one (with the plan's item size); reps timed passes each after
- * one warm-up; keeps the fastest in the plan.  times_ms (nullable, at least
+ * given inputs for every candidate: for item sizes 64, 128, 256, 512 and
+ * 1024 rows, waves 2, 4, 8 x unroll 1, 2, 4, then the streaming form with
+ * unroll -1, -2, -4 (12 shapes per size, in that order), then the split form
+ * where the plan has one (with the plan's item size); reps timed passes each
+ * after one warm-up; keeps the fastest in the plan.  times_ms (nullable, at least
  * SUGG_TUNE_CANDIDATES floats, times_cap its length) receives the mean pass
  * time of each candidate (-1 for one the plan cannot run: an item size whose
  * workspace exceeds LDS, a split form it does not have).  Needs a fitted
  * model; allocates and frees temporary outputs; synchronises the stream. */
-#define SUGG_TUNE_CANDIDATES 49
+#define SUGG_TUNE_CANDIDATES 61
 SUGG_API int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, const void* cycles,
                                int32_t reps, float* times_ms, int32_t times_cap, hipStream_t stream);
 

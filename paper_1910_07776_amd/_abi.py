@@ -21,7 +21,7 @@ SUGG_MAX_OPTS = 12
 SUGG_MAX_EVENTS = 256
 SUGG_MAX_GLOBAL_OPTS = 64
 SUGG_MAX_SUGGEST = 8
-SUGG_TUNE_CANDIDATES = 49
+SUGG_TUNE_CANDIDATES = 61
 
 
 class SuggError(RuntimeError):

@@ -325,10 +325,10 @@ size_t path_lds_bound(size_t tsize, int D, int E, int max_rows, int max_nk, int 
 }
 
 constexpr size_t kLdsPerWorkgroup = 160 * 1024;
-constexpr int kTuneItems[] = {128, 256, 512, 1024};
+constexpr int kTuneItems[] = {64, 128, 256, 512, 1024};
 constexpr int kTuneWaves[] = {2, 4, 8};
 constexpr int kTuneUnroll[] = {1, 2, 4};
-static_assert(4 * (3 * 3 + 3) + 1 == SUGG_TUNE_CANDIDATES, "autotuner candidate count");
+static_assert(5 * (3 * 3 + 3) + 1 == SUGG_TUNE_CANDIDATES, "autotuner candidate count");
 
 template <typename T>
 int run_path(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, T* grid, T* table,

@@ -275,35 +275,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((U == 
   };
   const int step = nwaves * 4 * U;
   const int b0 = wave * 4 * U;
-  // Loads of an item's rows straight from the work list (kernel records in
-  // global memory): used for the rows requested before the item's metadata
-  // is in LDS, i.e. the first two row groups of the next item, issued while
-  // the current one is composed and ranked.
-  auto load_ahead = [&](const Item& t, int base, T (&c)[U][NCH][VW], T (&cy)[U]) {
-    const uint32_t m = (1u << t.B) - 1u;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      int rr = base + u * 4 + grp;
-      rr = rr < t.R ? rr : t.R - 1;
-      const int64_t grow = t.row0 >= 0 ? t.row0 + rr : a.recs[t.first + (rr >> t.B)].row_off + (rr & m);
-      const T* rp = a.counters + grow * E;
-#pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) {
-        const int c0 = (l16 + kRowLanes * ch) * VW;
-        if (FULL || c0 < E) {
-          const VecN<T, VW> q = *reinterpret_cast<const VecN<T, VW>*>(rp + c0);
-#pragma unroll
-          for (int v = 0; v < VW; ++v) c[u][ch][v] = q.v[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < VW; ++v) c[u][ch][v] = T(1);
-        }
-      }
-      cy[u] = a.cycles[grow];
-    }
-  };
-  bool ahead = false;   // the current item's first two row groups are already in flight
-
   int it = blockIdx.x;
   while (it < a.n_items) {
     if (dynamic && tid == 0) s_next = (int)gridDim.x + atomicAdd(a.queue, 1);
@@ -341,17 +312,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((U == 
         cy[u] = contig ? icyc[rr] : a.cycles[grow];
       }
     };
-    // adjacent kernels need no metadata for their first rows: issue them now
-    // (unless the previous item already did)
-    const bool early = (ahead || contig) && b0 < R && !a.kmask;
-    const bool early2 = early && b0 + step < R;
-    if (early && !ahead) load(b0, ca, cya);
-    if (early2 && !ahead) load(b0 + step, cb, cyb);
-    ahead = false;
-    if (!staged) {
-      stage_model();
-      staged = true;
-    }
     if (a.kmask) {   // masked runs: the selection flag starts clear
       if (tid == 0) s_any = 0;
       __syncthreads();
@@ -438,34 +398,32 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((U == 
       }
     };
 
-    // two register buffers: the next rows load while the current ones compute
-    __syncthreads();   // weights, item metadata and the selection flag are visible
+    __syncthreads();   // item metadata and the selection flag are visible
     if (a.kmask && !s_any) {   // masked run: no selected kernel in this item
       it = dynamic ? s_next : a.n_items;
       __syncthreads();
       continue;
     }
-    if (!early && b0 < R) load(b0, ca, cya);
-    for (int base = b0; base < R; base += 2 * step) {
-      if (base + step < R && !(early2 && base == b0)) load(base + step, cb, cyb);
+    // Two register buffers: the next rows load while the current ones
+    // compute.  Every load is issued unconditionally (rows past the item
+    // re-read its last row) and the loop has one exit, so the loads in flight
+    // are the same on every path and a step waits only for its own rows.
+    load(b0, ca, cya);
+    load(b0 + step, cb, cyb);
+    if (!staged) {   // the model's loads overlap the first rows'
+      stage_model();
+      staged = true;
+    }
+    __syncthreads();   // weights visible
+    const int pairs = b0 < R ? (R - b0 + 2 * step - 1) / (2 * step) : 0;
+    for (int i = 0, base = b0; i < pairs; ++i, base += 2 * step) {
       compute(base, ca, cya);
-      if (base + step >= R) break;
-      if (base + 2 * step < R) load(base + 2 * step, ca, cya);
+      load(base + 2 * step, ca, cya);
       compute(base + step, cb, cyb);
+      load(base + 3 * step, cb, cyb);
     }
     __syncthreads();
-    // persistent mode: the next item's first two row groups go out now, so
-    // their latency overlaps this item's composition and ranking
-    int nit = a.n_items;
-    if (dynamic) {
-      nit = s_next;
-      if (nit < a.n_items && !a.kmask) {
-        const Item nx = get_item(nit);
-        if (b0 < nx.R) load_ahead(nx, b0, ca, cya);
-        if (b0 + step < nx.R) load_ahead(nx, b0 + step, cb, cyb);
-        ahead = true;
-      }
-    }
+    const int nit = dynamic ? s_next : a.n_items;
 
     // ---- compose the subset table -----------------------------------------
     // L(S) = sum over the bits b of S, ascending, of the edge into

@@ -413,7 +413,7 @@ def band_select(ctx: Context, scores, seg_off, top_idx, top_count, tau: float = 
     return cand, ref, flag
 
 
-TUNE_ITEMS = (128, 256, 512, 1024)
+TUNE_ITEMS = (64, 128, 256, 512, 1024)
 TUNE_WAVES = (2, 4, 8)
 TUNE_UNROLL = (1, 2, 4)
 

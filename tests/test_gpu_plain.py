@@ -387,8 +387,8 @@ def test_launch_shapes_and_persistent_queue_bit_identical(G, ctx, ragged):
     G.sync(ctx)
     cfg = G.autotune(ctx, pte, c, cy, reps=2)
     assert cfg["waves"] in (2, 4, 8) and cfg["unroll"] in (1, 2, 4, -1, -2, -4)
-    assert cfg["items"] in (128, 256, 512, 1024)
-    assert len(cfg["times_ms"]) == 48 and all(v > 0 for v in cfg["times_ms"].values())
+    assert cfg["items"] in (64, 128, 256, 512, 1024)
+    assert len(cfg["times_ms"]) == 60 and all(v > 0 for v in cfg["times_ms"].values())
     assert pte.get_items() == cfg["items"]
     # every item size gives the same bits as the default one
     for rows in (16, 128, 1024, 4096):
@@ -510,7 +510,7 @@ def test_split_form_512_kernels_against_oracle(G):
         assert_scores(table.cpu().numpy(), otab, RTOL32, "table")
         check_suggestions(idx, score, count, otab, te.row_off, P.TAU, 3, RTOL32)
         cfg = G.autotune(c_, pte, c, cy, reps=2)
-        assert len(cfg["times_ms"]) == 49 and cfg["times_ms"]["split"] > 0
+        assert len(cfg["times_ms"]) == 61 and cfg["times_ms"]["split"] > 0
         assert cfg["unroll"] in (0, 1, 2, 4, -1, -2, -4)
     finally:
         c_.close()
