@@ -929,7 +929,7 @@ def serving_extra(G, dev, n_queries: int = 10000):
         c, cy, _ = tw.chunk(7000, 4096)
         pools[Bq] = (c, cy)
     min_rows = 1 << 21
-    srv = serve.Server(ctx, nets, n=3, tol=0.1, budget_bytes=8 << 30, min_rows=min_rows)
+    srv = serve.Server(ctx, nets, n=3, tol=0.1, budget_bytes=8 << 30, min_rows=min_rows, streams=4)
     rng = np.random.default_rng(11)
     qs = []
     for _ in range(n_queries):
@@ -967,13 +967,10 @@ def serving_extra(G, dev, n_queries: int = 10000):
     srv.min_rows = min_rows
     log("service ms (surrogate / plain): " + ", ".join(f"{k} {v['surrogate']:.3f}/{v['plain']:.3f}"
                                                        for k, v in svc.items()))
-    # closed loop, one query at a time with its answer on the host (as in the
-    # real-time loop): service capacity
-    for q in qs[:50]:
-        srv.answer(*q[:4])
+    # closed loop, one query at a time with its answer on the host: service
+    # capacity of one stream
+    srv.prepare(qs)
     torch.cuda.synchronize()
-    srv.fallbacks.zero_()
-    srv.kernels_total = srv.kernels_plain = 0
     t0 = time.perf_counter()
     for q in qs:
         srv.answer(*q[:4])
@@ -983,18 +980,24 @@ def serving_extra(G, dev, n_queries: int = 10000):
     sur_kernels = srv.kernels_total - srv.kernels_plain
     res = {"queries": len(qs), "capacity_qps": cap, "min_rows_for_surrogate": min_rows,
            "kernels_total": srv.kernels_total, "kernels_plain_by_policy": srv.kernels_plain,
-           "surrogate_fallback_rate": float(srv.fallbacks.item()) / max(1, sur_kernels),
+           "surrogate_fallback_rate": float(srv.fallbacks) / max(1, sur_kernels),
            "kernels_per_s_closed_loop": srv.kernels_total / busy, "service_ms": svc, "nets": train_info}
     log(f"serving capacity {cap:.0f} queries/s, surrogate fallback rate {res['surrogate_fallback_rate']:.3f}")
+    # open loop at 50 % and 80 % of the one-stream capacity, up to four
+    # queries in flight within the 8 GiB budget
     for frac in (0.5, 0.8):
         arr = serve.poisson_arrivals(len(qs), frac * cap, seed=int(frac * 100))
         st = serve.run_loop(srv, qs, arr)
         res[f"served_at_{int(frac * 100)}pct"] = st
-        log(f"serving {int(frac * 100)}%: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms")
+        log(f"serving {int(frac * 100)}%: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms "
+            f"(max in flight {st['max_in_flight']})")
         if frac == 0.8:
+            res["agreement_with_plain_top3"] = serve.plain_agreement(srv, qs)
+            log(f"served answers equal to the plain top-3: {res['agreement_with_plain_top3']}")
             stp = serve.run_loop(srv, qs, arr, plain_only=True)
             res["plain_only_same_trace"] = stp
             log(f"plain only, same trace: p50 {stp['p50_ms']:.3f} ms p99 {stp['p99_ms']:.3f} ms")
+    srv.close()
     for m in nets.values():
         m.close()
     ctx.close()

@@ -395,6 +395,32 @@ SUGG_API int32_t sugg_m5p_suggest(sugg_ctx* ctx, const sugg_plan* plan, const vo
                                   void* table_out, int32_t* idx_out, void* score_out, int32_t* count_out,
                                   hipStream_t stream);
 
+/* M5P model checkpoint (host arrays, synchronous).
+ * sugg_m5p_shape: E and D of the context's M5P model (SUGG_E_STATE if none).
+ * sugg_m5p_export: node_off and leaf_off [D+1] always (id o's nodes are
+ *   [node_off[o], node_off[o+1]) of the concatenated arrays, its leaf models
+ *   [leaf_off[o], leaf_off[o+1]); no nodes = untrained); with
+ *   nodes_cap = leaves_cap = 0 nothing else (sizing), otherwise, for caps of
+ *   at least node_off[D] and leaf_off[D]: each id's preorder tree as in
+ *   sugg_m5p_tree (child indices within the id's tree) plus leaf (the node's
+ *   leaf model ordinal within the id, -1 inside), lw [leaves x (E+1)] (the
+ *   smoothed leaf models, intercept last), and mu, isg [E] (the FP64 mean and
+ *   reciprocal standard deviation of ln(c / cyc) that standardise features).
+ * sugg_m5p_import: replaces the context's M5P model with such arrays, which
+ *   predict exactly as the exported model did.  Checked: every tree rooted at
+ *   node 0 with each other node the child of exactly one earlier node, splits
+ *   on features < E at finite thresholds, each leaf model used by exactly one
+ *   leaf, finite leaf models and statistics (SUGG_E_ARG otherwise; the
+ *   previous model is kept). */
+SUGG_API int32_t sugg_m5p_shape(const sugg_ctx* ctx, int32_t* E, int32_t* D);
+SUGG_API int32_t sugg_m5p_export(sugg_ctx* ctx, int64_t nodes_cap, int64_t leaves_cap, int64_t* node_off,
+                                 int64_t* leaf_off, int32_t* feat, double* thr, int32_t* left, int32_t* right,
+                                 int32_t* leaf, int64_t* count, double* lw, double* mu, double* isg);
+SUGG_API int32_t sugg_m5p_import(sugg_ctx* ctx, int32_t E, int32_t D, const int64_t* node_off,
+                                 const int64_t* leaf_off, const int32_t* feat, const double* thr,
+                                 const int32_t* left, const int32_t* right, const int32_t* leaf,
+                                 const int64_t* count, const double* lw, const double* mu, const double* isg);
+
 /* ---- Learned surrogate ------------------------------------------------------
  * An extension of the paper's Tier 2 (which predicts one optimisation at a
  * time): an MLP in -> hidden -> hidden -> out with exact-erf GELU after both

@@ -84,6 +84,9 @@ SIGNATURES = {
     "sugg_m5p_tree": (_I32, [_P, _I32, _I32, _P, _P, _P, _P, _P, _PI32]),
     "sugg_m5p_predict": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
     "sugg_m5p_suggest": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "sugg_m5p_shape": (_I32, [_P, _PI32, _PI32]),
+    "sugg_m5p_export": (_I32, [_P, _I64, _I64, _PI64, _PI64, _PI32, _PD, _PI32, _PI32, _PI32, _PI64, _PD, _PD, _PD]),
+    "sugg_m5p_import": (_I32, [_P, _I32, _I32, _PI64, _PI64, _PI32, _PD, _PI32, _PI32, _PI32, _PI64, _PD, _PD, _PD]),
     "sugg_capture_begin": (_I32, [_P, _P]),
     "sugg_capture_end": (_I32, [_P, _P, C.POINTER(_P)]),
     "sugg_graph_launch": (_I32, [_P, _P, _P]),

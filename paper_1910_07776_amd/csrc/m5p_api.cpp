@@ -416,4 +416,130 @@ int32_t sugg_m5p_suggest(sugg_ctx* ctx, const sugg_plan* plan, const void* count
                          idx_out, (double*)score_out, count_out, stream);
 }
 
+int32_t sugg_m5p_shape(const sugg_ctx* ctx, int32_t* E, int32_t* D) {
+  if (!ctx || !E || !D) return SUGG_E_ARG;
+  if (!ctx->m5p) return const_cast<sugg_ctx*>(ctx)->fail(SUGG_E_STATE, "no M5P model");
+  *E = ctx->m5p->E;
+  *D = ctx->m5p->D;
+  return SUGG_OK;
+}
+
+int32_t sugg_m5p_export(sugg_ctx* ctx, int64_t nodes_cap, int64_t leaves_cap, int64_t* node_off, int64_t* leaf_off,
+                        int32_t* feat, double* thr, int32_t* left, int32_t* right, int32_t* leaf, int64_t* count,
+                        double* lw, double* mu, double* isg) {
+  if (!ctx || !node_off || !leaf_off || nodes_cap < 0 || leaves_cap < 0) return SUGG_E_ARG;
+  const M5pModel* m = ctx->m5p;
+  if (!m) return ctx->fail(SUGG_E_STATE, "no M5P model");
+  const int E = m->E, D = m->D;
+  node_off[0] = leaf_off[0] = 0;
+  for (int o = 0; o < D; ++o) {
+    node_off[o + 1] = node_off[o] + (int64_t)m->trees[o].feat.size();
+    leaf_off[o + 1] = leaf_off[o] + (m->trees[o].feat.empty() ? 0 : m->trees[o].leaves);
+  }
+  if (nodes_cap == 0 && leaves_cap == 0) return SUGG_OK;   // sizes only
+  if (nodes_cap < node_off[D] || leaves_cap < leaf_off[D])
+    return ctx->fail(SUGG_E_ARG, "export needs %lld nodes and %lld leaves", (long long)node_off[D],
+                     (long long)leaf_off[D]);
+  if (!feat || !thr || !left || !right || !leaf || !count || !lw || !mu || !isg)
+    return ctx->fail(SUGG_E_ARG, "null output array");
+  for (int o = 0; o < D; ++o) {
+    const M5pHostTree& t = m->trees[o];
+    if (t.feat.empty()) continue;
+    for (size_t i = 0; i < t.feat.size(); ++i) {
+      const int64_t j = node_off[o] + (int64_t)i;
+      feat[j] = t.feat[i];
+      thr[j] = t.feat[i] >= 0 ? t.thr[i] : std::nan("");
+      left[j] = t.left[i];
+      right[j] = t.right[i];
+      leaf[j] = t.leaf[i];
+      count[j] = t.count[i];
+    }
+    std::copy(t.lw.begin(), t.lw.begin() + (size_t)t.leaves * (E + 1), lw + leaf_off[o] * (E + 1));
+  }
+  hipError_t e = hipMemcpy(mu, m->mu64, sizeof(double) * E, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(isg, m->isg64, sizeof(double) * E, hipMemcpyDeviceToHost);
+  return ctx->hip(e, "M5P export");
+}
+
+int32_t sugg_m5p_import(sugg_ctx* ctx, int32_t E, int32_t D, const int64_t* node_off, const int64_t* leaf_off,
+                        const int32_t* feat, const double* thr, const int32_t* left, const int32_t* right,
+                        const int32_t* leaf, const int64_t* count, const double* lw, const double* mu,
+                        const double* isg) {
+  if (!ctx) return SUGG_E_ARG;
+  if (E < 1 || E > 256 || D < 1 || D > SUGG_MAX_GLOBAL_OPTS) return ctx->fail(SUGG_E_SHAPE, "bad E or D");
+  if (!node_off || !leaf_off || !mu || !isg) return ctx->fail(SUGG_E_ARG, "null argument");
+  if (node_off[0] != 0 || leaf_off[0] != 0) return ctx->fail(SUGG_E_ARG, "offsets must start at 0");
+  if (node_off[D] > 0 && (!feat || !thr || !left || !right || !leaf || !count || !lw))
+    return ctx->fail(SUGG_E_ARG, "null tree array");
+  for (int j = 0; j < E; ++j)
+    if (!std::isfinite(mu[j]) || !std::isfinite(isg[j]) || !(isg[j] > 0.0))
+      return ctx->fail(SUGG_E_ARG, "column statistic %d not finite (or 1/sd not positive)", j);
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  M5pModel* m = new (std::nothrow) M5pModel();
+  if (!m) return ctx->fail(SUGG_E_BUDGET, "out of host memory");
+  m->E = E;
+  m->D = D;
+  m->ldl = m5p_ldl(E);
+  m->trees.resize(D);
+  int rc = SUGG_OK;
+  for (int o = 0; o < D && !rc; ++o) {
+    const int64_t n = node_off[o + 1] - node_off[o], nl = leaf_off[o + 1] - leaf_off[o];
+    if (n < 0 || nl < 0 || (n == 0) != (nl == 0) || n > (1 << 24)) {
+      rc = ctx->fail(SUGG_E_ARG, "id %d: bad node or leaf offsets", o);
+      break;
+    }
+    if (n == 0) continue;
+    M5pHostTree& t = m->trees[o];
+    t.leaves = (int)nl;
+    t.feat.assign(feat + node_off[o], feat + node_off[o + 1]);
+    t.thr.assign(thr + node_off[o], thr + node_off[o + 1]);
+    t.left.assign(left + node_off[o], left + node_off[o + 1]);
+    t.right.assign(right + node_off[o], right + node_off[o + 1]);
+    t.leaf.assign(leaf + node_off[o], leaf + node_off[o + 1]);
+    t.count.assign(count + node_off[o], count + node_off[o + 1]);
+    t.lw.assign(lw + leaf_off[o] * (E + 1), lw + leaf_off[o + 1] * (E + 1));
+    // a tree rooted at node 0: every other node the child of exactly one
+    // earlier node, internal nodes test a real feature at a finite
+    // threshold, leaves name each leaf model exactly once
+    std::vector<int> parents(n, 0), depth(n, 0), seen(nl, 0);
+    for (int64_t i = 0; i < n && !rc; ++i) {
+      if (t.feat[i] >= 0) {
+        if (t.feat[i] >= E || !std::isfinite(t.thr[i]) || t.leaf[i] != -1 || t.left[i] <= i || t.right[i] <= i ||
+            t.left[i] >= n || t.right[i] >= n || t.left[i] == t.right[i]) {
+          rc = ctx->fail(SUGG_E_ARG, "id %d node %lld: bad split", o, (long long)i);
+          break;
+        }
+        ++parents[t.left[i]];
+        ++parents[t.right[i]];
+        depth[t.left[i]] = depth[t.right[i]] = depth[i] + 1;
+      } else {
+        if (t.feat[i] != -1 || t.left[i] != -1 || t.right[i] != -1 || t.leaf[i] < 0 || t.leaf[i] >= nl ||
+            seen[t.leaf[i]]++) {
+          rc = ctx->fail(SUGG_E_ARG, "id %d node %lld: bad leaf", o, (long long)i);
+          break;
+        }
+        t.depth = std::max(t.depth, depth[i]);
+      }
+    }
+    for (int64_t i = 0; i < n && !rc; ++i)
+      if (parents[i] != (i == 0 ? 0 : 1)) rc = ctx->fail(SUGG_E_ARG, "id %d: node %lld is not a tree node", o, (long long)i);
+    if (!rc && std::count(seen.begin(), seen.end(), 1) != nl) rc = ctx->fail(SUGG_E_ARG, "id %d: unused leaf model", o);
+    for (double v : t.lw)
+      if (!rc && !std::isfinite(v)) rc = ctx->fail(SUGG_E_ARG, "id %d: leaf model not finite", o);
+  }
+  if (!rc) rc = upload_model(ctx, m);
+  if (!rc) {
+    hipError_t e = put(m->mu64, std::vector<double>(mu, mu + E));
+    if (e == hipSuccess) e = put(m->isg64, std::vector<double>(isg, isg + E));
+    rc = ctx->hip(e, "M5P statistics upload");
+  }
+  if (rc) {
+    m5p_model_free(m);
+    return rc;
+  }
+  m5p_model_free(ctx->m5p);
+  ctx->m5p = m;
+  return SUGG_OK;
+}
+
 }  // extern "C"

@@ -344,3 +344,56 @@ def test_server_keeps_only_answers_that_meet_tier3(env, side):
     finally:
         ctx.set_params(tau=tau0)
         net.close()
+
+
+def test_admission_by_hbm_budget_with_queries_in_flight(env):
+    """Up to four queries in flight on four streams: a tiny budget (one
+    512-kernel query) makes queries wait until enough of those before them
+    have finished (never more bytes in flight than the budget) and rejects a
+    query larger than the whole budget;
+    a large budget lets several run at once.  Every answered query equals the
+    plain path's answer (a surrogate that is always overruled), on every
+    slot."""
+    G, ctx, te, p, c, cy = env
+    from paper_1910_07776_amd import serve, surrogate as Sg
+    from synthgen.torch_world import TorchWorld
+    tw = TorchWorld(78, 128, 12, B=6)
+    cnt, cyc, _ = tw.chunk(4, 1024)
+    bad = Sg.MLP(ctx, 128, 512, 64, max_batch=1024, seed=9)
+    bad.params.mul_(40.0)   # broken: every kernel falls back to the plain path
+    sizes = [64, 256, 1024, 128, 512, 64, 32, 1024, 256, 200]
+    for budget, streams in ((serve.Server.footprint(512, 6, 128) + 1, 4), (8 << 30, 4), (8 << 30, 1)):
+        srv = serve.Server(ctx, {6: bad}, n=3, tol=0.1, budget_bytes=budget, streams=streams)
+        qs, refs = [], []
+        for j, K in enumerate(sizes):
+            k0 = (37 * j) % (1024 - K + 1)
+            q = srv.plan(6, K, 128, 12)
+            cq, cyq = cnt[k0 << 6:(k0 + K) << 6], cyc[k0 << 6:(k0 + K) << 6]
+            out = {"idx": torch.full((K, 3), -9, dtype=torch.int32, device="cuda"),
+                   "score": torch.empty((K, 3), device="cuda"),
+                   "count": torch.full((K,), -9, dtype=torch.int32, device="cuda"), "table": None}
+            qs.append((q, cq, cyq, out, serve.Server.footprint(K, 6, 128)))
+            refs.append(G.suggest(ctx, q, cq, cyq))
+        srv.prepare(qs)
+        for _, _, _, out, _ in qs:
+            out["idx"].fill_(-9)
+            out["count"].fill_(-9)
+        st = serve.run_loop(srv, qs, np.zeros(len(qs)))   # all arrive at once
+        torch.cuda.synchronize()
+        big = [j for j, K in enumerate(sizes) if serve.Server.footprint(K, 6, 128) > budget]
+        assert st["rejected"] == len(big) and st["queries"] == len(sizes) - len(big)
+        assert st["max_in_flight_bytes"] <= budget
+        if budget < (1 << 30):   # the two 512-sized queries never overlap, others wait their turn
+            assert big and st["waited_for_admission"] >= 1
+        elif streams == 4:
+            assert st["max_in_flight"] >= 2
+        for j, (_, _, _, out, _) in enumerate(qs):
+            if j in big:
+                assert (out["idx"] == -9).all()   # never answered
+                continue
+            assert torch.equal(out["idx"], refs[j][0]) and torch.equal(out["count"], refs[j][2]), (budget, j)
+            assert torch.equal(torch.nan_to_num(out["score"], nan=-7.0), torch.nan_to_num(refs[j][1], nan=-7.0))
+        agree = serve.plain_agreement(srv, [q for j, q in enumerate(qs) if j not in big])
+        assert agree["same_list"] == 1.0 and agree["same_set"] == 1.0
+        srv.close()
+    bad.close()
