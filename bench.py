@@ -769,6 +769,23 @@ def surrogate_extra(G, dev, no_cpu=False):
     train_ms = e0.elapsed_time(e1)
     steps = mlp.step
     flop_step = 3 * 2 * 4096 * (E * 512 + 512 * 512 + 512 * (1 << B))   # forward + backward
+    # steady-state training: one epoch of 256 steps in one library call on a
+    # copy of the trained network (validation excluded)
+    cp = Sg.MLP(ctx, E, 512, 1 << B, max_batch=4096, params=mlp.params.cpu().numpy())
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    perm = torch.randperm(data["X"].shape[0], generator=g, device=dev)[:256 * 4096].to(torch.int32)
+    cp.train_epoch(data["X"], data["Y"], perm[:8 * 4096], 4096)
+    torch.cuda.synchronize()
+    e0.record()
+    cp.train_epoch(data["X"], data["Y"], perm, 4096)
+    e1.record()
+    torch.cuda.synchronize()
+    epoch_ms = e0.elapsed_time(e1)
+    G.sync(ctx)
+    cp.close()
+    log(f"surrogate training: {epoch_ms / 256 * 1e3:.1f} us per step of 4096, "
+        f"{256 * flop_step / (epoch_ms / 1e3) / 1e12:.1f} TFLOP/s")
     del data
 
     # offline comparison on 65,536 held-out kernels of 6 optimisations
@@ -820,6 +837,10 @@ def surrogate_extra(G, dev, no_cpu=False):
         "train_kernels": 1 << 20, "label_s": label_s, "epochs": len(hist), "steps": steps,
         "train_ms": train_ms, "train_samples_per_s": steps * 4096 / (train_ms / 1e3),
         "train_tflops": steps * flop_step / (train_ms / 1e3) / 1e12,
+        "train_step_us_steady": epoch_ms / 256 * 1e3,
+        "train_tflops_steady": 256 * flop_step / (epoch_ms / 1e3) / 1e12,
+        "train_note": "train_ms/train_tflops: the whole run to matched MAPE, validation included; "
+                      "_steady: 256 steps of batch 4096 in one sugg_mlp_train_epoch call",
         "val_mape_plain": plain_val, "val_mape_surrogate": hist[-1].get("val_mape"),
         "matched_mape": bool(hist[-1].get("val_mape", 1e9) <= 1.02 * plain_val),
         "test_kernels": K, "test_mape_plain": m_plain, "test_mape_surrogate": m_sur,

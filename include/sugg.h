@@ -444,9 +444,10 @@ SUGG_API int64_t sugg_mlp_param_count(const sugg_mlp* mlp);
 /* The matrix-core kernel instances the object's last forward and backward
  * launched, host array info [8 x 4]: rows are the forward's layers 1-3, then
  * the backward's dW3, dA2, dW2, dA1, dW1 products; columns are workgroup tile
- * rows, tile columns, K splits, and 1 where the variant without bounds
- * checks ran (zeros for a product not launched yet).  Lets a caller (a
- * test) see which instances a given batch size exercises. */
+ * rows, tile columns, K splits, and the K stage (32, 64 or 128) of the
+ * variant without bounds checks where that ran, 0 where the variant with
+ * bounds checks ran (all zeros for a product not launched yet).  Lets a
+ * caller (a test) see which instances a given batch size exercises. */
 SUGG_API int32_t sugg_mlp_launch_info(const sugg_mlp* mlp, int32_t* info);
 /* Keeps a copy of params for inference (sugg_serve_query): the BF16 working
  * weights are packed from it once, and again only after another call
@@ -474,6 +475,20 @@ SUGG_API int32_t sugg_mlp_adam(sugg_ctx* ctx, sugg_mlp* mlp, float* params, cons
 SUGG_API int32_t sugg_mlp_train_step(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float* grads, float* m, float* v,
                                      int32_t step, float lr, const float* x, const float* target, int32_t batch,
                                      float* loss, hipStream_t stream);
+
+/* A training epoch in one call: for s in [0, steps), the mini-batch of rows
+ * perm[s*batch .. (s+1)*batch) of X [n_rows x in] with targets the same rows
+ * of Y [n_rows x out] (gathered by the first kernel, no copies), then what
+ * sugg_mlp_train_step does with Adam step step0 + s + 1; loss of step s into
+ * losses[s] (device).  Adam also rewrites the BF16 working weights (one
+ * launch), the bias gradients are summed with the weight gradients' split-K
+ * partials.  Bit-identical to train_step on the gathered batches.  perm is a
+ * device int32 array of steps*batch entries; an entry outside [0, n_rows)
+ * reads row 0 and the next sugg_sync reports SUGG_E_ARG.  Asynchronous. */
+SUGG_API int32_t sugg_mlp_train_epoch(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float* grads, float* m,
+                                      float* v, int32_t step0, float lr, const float* X, const float* Y,
+                                      int64_t n_rows, const int32_t* perm, int32_t batch, int32_t steps,
+                                      float* losses, hipStream_t stream);
 
 /* Model checkpoint (host arrays, synchronous).  W is D x (E+1), row o =
  * feature weights of optimisation o followed by its intercept; counts[o] is

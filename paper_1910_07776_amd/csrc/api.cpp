@@ -941,6 +941,7 @@ int32_t sugg_sync(sugg_ctx* ctx, hipStream_t stream) {
   }
   if (st & kStatusBadCounter) return ctx->fail(SUGG_E_BAD_COUNTER, "a counter or cycle count is <= 0, NaN or Inf");
   if (st & kStatusSingular) return ctx->fail(SUGG_E_SINGULAR, "a regression system is not positive definite");
+  if (st & kStatusBadIndex) return ctx->fail(SUGG_E_ARG, "a training row index is outside the training set");
   return SUGG_OK;
 }
 

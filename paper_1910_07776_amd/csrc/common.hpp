@@ -13,7 +13,7 @@ constexpr int kWave = 64;
 constexpr int kMaxSuggest = 8;   // longest suggestion list
 constexpr int kRowLanes = 16;   // lanes that share one counter row (one DPP row)
 
-enum StatusBits : int { kStatusBadCounter = 1, kStatusSingular = 2 };
+enum StatusBits : int { kStatusBadCounter = 1, kStatusSingular = 2, kStatusBadIndex = 4 };
 
 // One item of the ragged work list: nk kernels of equal B whose records are
 // recs[first .. first+nk); R = nk << B rows.  row0 >= 0 when the kernels are

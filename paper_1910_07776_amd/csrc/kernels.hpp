@@ -290,6 +290,7 @@ struct GemmArgs {
   int ldg;
   const float* target;   // [M x N] targets
   int ldt;
+  const int32_t* trow;   // nullable: output row r's target is row trow[r] of target
   float* loss_part;      // one partial per output tile
   float scale;           // dY = scale * (Y - T)
 };
@@ -299,10 +300,34 @@ struct GemmArgs {
 hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s, int32_t* info = nullptr);
 hipError_t launch_pack(const float* src, int rows, int cols, __bf16* dst, int ldd, __bf16* dst_t, int ldt,
                        hipStream_t s);
-hipError_t launch_splitk_sum(const float* part, int64_t n, int splits, float* out, hipStream_t s);
-hipError_t launch_rowsum(const __bf16* x, int rows, int cols, int ld, float* out, hipStream_t s);
 hipError_t launch_loss_sum(const float* part, int n, float scale, float* loss, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int step, hipStream_t s);
+// Rows idx[0..rows) of the FP32 matrix src [src_rows x cols] to BF16
+// row-major dst and transposed dst_t (as launch_pack); an index outside
+// [0, src_rows) reads row 0 and sets kStatusBadIndex in status.  The rows
+// read are written to rows_out [rows].
+hipError_t launch_gather_pack(const float* src, int64_t src_rows, int cols, const int32_t* idx, int rows, __bf16* dst,
+                              int ldd, __bf16* dst_t, int ldt, int32_t* rows_out, int32_t* status, hipStream_t s);
+// split-K sums of a weight gradient (in split order) and row sums of a
+// transposed BF16 activation gradient (its bias gradient) in one launch
+hipError_t launch_wgrad_finish(const float* part, int64_t n, int splits, float* out, const __bf16* x, int rows,
+                               int cols, int ld, float* bias_out, hipStream_t s);
+// Adam (as launch_adam) over the surrogate's flat parameters, writing the
+// updated weights of its three layers to their BF16 working copies
+// (row-major w[l]; transposed wt[l] where non-null, leading dimension = rows)
+struct AdamPackArgs {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+  float lr, b1, b2, eps, c1, c2;
+  int64_t off[3];     // first parameter of each weight matrix
+  int rows[3], cols[3];
+  __bf16* w[3];
+  __bf16* wt[3];
+};
+hipError_t launch_adam_pack(const AdamPackArgs& a, int step, hipStream_t s);
 
 }  // namespace sugg

@@ -25,9 +25,17 @@ namespace sugg {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kKStep = 32;    // K per LDS stage (two MFMAs of K 16)
-constexpr int kKVec = kKStep / 32;   // 8-element vectors per thread and tile row per stage
-constexpr int kLdsRow = kKStep + 8;   // padded LDS row (bf16 elements)
+// K per LDS stage (KS, a template parameter: 32, 64 or 128, each stage two to
+// eight MFMAs of K 16 per tile); a stage's rows are padded by 8 elements.
+template <int KS>
+__host__ __device__ constexpr int lds_row() { return KS + 8; }
+template <int TM, int TN, int KS>
+__host__ __device__ constexpr size_t gemm_lds_bytes() {
+  // operand stages, or the BF16 output tile of the epilogue if larger
+  return sizeof(__bf16) * (2 * 64 * (TM + TN) * lds_row<KS>() > 64 * TM * (64 * TN + 8)
+                               ? 2 * 64 * (TM + TN) * lds_row<KS>()
+                               : 64 * TM * (64 * TN + 8));
+}
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 
@@ -52,11 +60,14 @@ __device__ __forceinline__ bf16x8 load8(const __bf16* p, int ld, int row, int ro
 // MFMA tiles of 32 x 32, so the workgroup tile is (64 TM) x (64 TN).  EX: the
 // tiles cover M, N and each K range exactly and rows are 16-byte aligned, so
 // operand loads and output stores need no bounds checks.
-template <int EPI, int TM, int TN, bool EX>
-__global__ void __launch_bounds__(256, 3) gemm_nt_kernel(const GemmArgs g) {
+template <int EPI, int TM, int TN, bool EX, int KS>
+__global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
   constexpr int WGM = 64 * TM, WGN = 64 * TN;
-  __shared__ __align__(16) __bf16 As[2][WGM * kLdsRow];
-  __shared__ __align__(16) __bf16 Bs[2][WGN * kLdsRow];
+  constexpr int kKVec = KS / 32;          // 8-element vectors per thread and tile row per stage
+  constexpr int kLdsRow = lds_row<KS>();
+  extern __shared__ __align__(16) unsigned char gsm[];
+  __bf16 (*As)[WGM * kLdsRow] = reinterpret_cast<__bf16 (*)[WGM * kLdsRow]>(gsm);
+  __bf16 (*Bs)[WGN * kLdsRow] = reinterpret_cast<__bf16 (*)[WGN * kLdsRow]>(gsm + sizeof(__bf16) * 2 * WGM * kLdsRow);
   __shared__ float red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -92,7 +103,7 @@ __global__ void __launch_bounds__(256, 3) gemm_nt_kernel(const GemmArgs g) {
   };
   fetch(kb);
   int buf = 0;
-  for (int k0 = kb; k0 < ke; k0 += kKStep) {
+  for (int k0 = kb; k0 < ke; k0 += KS) {
 #pragma unroll
     for (int v = 0; v < kKVec; ++v) {
 #pragma unroll
@@ -103,9 +114,9 @@ __global__ void __launch_bounds__(256, 3) gemm_nt_kernel(const GemmArgs g) {
         *reinterpret_cast<bf16x8*>(&Bs[buf][(lr + 64 * i) * kLdsRow + lk + 32 * v]) = rb[i][v];
     }
     __syncthreads();
-    if (k0 + kKStep < ke) fetch(k0 + kKStep);
+    if (k0 + KS < ke) fetch(k0 + KS);
 #pragma unroll
-    for (int s = 0; s < kKStep; s += 16) {
+    for (int s = 0; s < KS; s += 16) {
       const int kk = s + (lane >> 5) * 8;
       bf16x8 fa[TM], fb[TN];
 #pragma unroll
@@ -123,43 +134,111 @@ __global__ void __launch_bounds__(256, 3) gemm_nt_kernel(const GemmArgs g) {
   }
 
   // epilogue: lane holds C[row(r)][col] of each 32 x 32 tile with
-  // col = lane % 32, row(r) = (r / 4) * 8 + (lane / 32) * 4 + r % 4
+  // col = lane % 32, row(r) = (r / 4) * 8 + (lane / 32) * 4 + r % 4.  FP32
+  // outputs are written from there (each half-wave 128 contiguous bytes);
+  // BF16 outputs go through an LDS copy of the tile, from which the
+  // row-major copy and the transposed copy are written 16 bytes per thread
+  // (so the transposed one is as coalesced as the row-major one).
+  constexpr int TLD = WGN + 8;
+  __bf16* T = reinterpret_cast<__bf16*>(gsm);
+  const bool stage = EPI != kEpiWgrad && (g.Cb || g.Ct);
+  // every input of the epilogue (bias, pre-activation, target) is loaded
+  // before its first store, all loads in flight together (a load after a
+  // store to memory that might alias it would wait for that store)
+  float bcol[TN], pre[TM][TN][16];
+  if (EPI == kEpiFwdHidden || EPI == kEpiFwdOut) {
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int col = n0 + wn * 32 * TN + b * 32 + (lane & 31);
+      bcol[b] = (EX || col < g.N) ? g.bias[col] : 0.0f;
+    }
+  }
+  if (EPI == kEpiBwdHidden || (EPI == kEpiFwdOut && g.target)) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 32 * TM + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const bool rok = EX || row < g.M;
+        int64_t src = row;
+        if (EPI == kEpiFwdOut && g.trow && rok) src = g.trow[row];
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int col = n0 + wn * 32 * TN + b * 32 + (lane & 31);
+          const bool ok = rok && (EX || col < g.N);
+          if (EPI == kEpiBwdHidden) pre[a][b][r] = ok ? g.gact[src * g.ldg + col] : 0.0f;
+          else pre[a][b][r] = ok ? g.target[src * g.ldt + col] : 0.0f;
+        }
+      }
+  }
+  if (stage) __syncthreads();   // every wave is done with the operand tiles
   float sse = 0.0f;
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
-      const int col = n0 + wn * 32 * TN + b * 32 + (lane & 31);
+      const int tc = wn * 32 * TN + b * 32 + (lane & 31);
+      const int col = n0 + tc;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm * 32 * TM + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int tr = wm * 32 * TM + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int row = m0 + tr;
         if (!EX && (row >= g.M || col >= g.N)) continue;
         const float v = acc[a][b][r];
+        float o = 0.0f;   // the BF16 output
         if (EPI == kEpiWgrad) {
           g.Cf[(int64_t)split * g.M * g.N + (int64_t)row * g.N + col] = v;
         } else if (EPI == kEpiFwdHidden) {
-          const float z = v + g.bias[col];
+          const float z = v + bcol[b];
           if (g.Cf) g.Cf[(int64_t)row * g.ldcf + col] = z;
-          const float h = gelu_f(z);
-          if (g.Cb) g.Cb[(int64_t)row * g.ldcb + col] = to_bf16(h);
-          if (g.Ct) g.Ct[(int64_t)col * g.ldct + row] = to_bf16(h);
+          o = gelu_f(z);
         } else if (EPI == kEpiFwdOut) {
-          const float y = v + g.bias[col];
+          const float y = v + bcol[b];
           if (g.Cf) g.Cf[(int64_t)row * g.ldcf + col] = y;
           if (g.target) {
-            const float d = y - g.target[(int64_t)row * g.ldt + col];
+            const float d = y - pre[a][b][r];
             sse = fmaf(d, d, sse);
-            const float dy = g.scale * d;
-            g.Cb[(int64_t)row * g.ldcb + col] = to_bf16(dy);
-            g.Ct[(int64_t)col * g.ldct + row] = to_bf16(dy);
+            o = g.scale * d;
           }
         } else {  // kEpiBwdHidden
-          const float d = v * gelu_grad_f(g.gact[(int64_t)row * g.ldg + col]);
-          if (g.Cb) g.Cb[(int64_t)row * g.ldcb + col] = to_bf16(d);
-          if (g.Ct) g.Ct[(int64_t)col * g.ldct + row] = to_bf16(d);
+          o = v * gelu_grad_f(pre[a][b][r]);
+        }
+        if (stage) T[tr * TLD + tc] = to_bf16(o);
+      }
+    }
+  if (stage) {
+    __syncthreads();
+    const int mr = min(WGM, g.M - m0), nc = min(WGN, g.N - n0);   // the tile's valid extent
+    if (g.Cb) {
+      const bool vec = reinterpret_cast<uintptr_t>(g.Cb) % 16 == 0 && g.ldcb % 8 == 0;
+      for (int v = tid; v < WGM * (WGN / 8); v += 256) {
+        const int r = v / (WGN / 8), c = (v % (WGN / 8)) * 8;
+        if (r >= mr) continue;
+        __bf16* dst = g.Cb + (int64_t)(m0 + r) * g.ldcb + n0 + c;
+        if (vec && c + 8 <= nc) {
+          *reinterpret_cast<bf16x8*>(dst) = *reinterpret_cast<const bf16x8*>(T + r * TLD + c);
+        } else {
+          for (int i = 0; i < 8 && c + i < nc; ++i) dst[i] = T[r * TLD + c + i];
         }
       }
     }
+    if (g.Ct) {
+      const bool vec = reinterpret_cast<uintptr_t>(g.Ct) % 16 == 0 && g.ldct % 8 == 0;
+      for (int v = tid; v < WGN * (WGM / 8); v += 256) {
+        const int c = v / (WGM / 8), r = (v % (WGM / 8)) * 8;
+        if (c >= nc) continue;
+        __bf16* dst = g.Ct + (int64_t)(n0 + c) * g.ldct + m0 + r;
+        if (vec && r + 8 <= mr) {
+          bf16x8 q;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) q[i] = T[(r + i) * TLD + c];
+          *reinterpret_cast<bf16x8*>(dst) = q;
+        } else {
+          for (int i = 0; i < 8 && r + i < mr; ++i) dst[i] = T[(r + i) * TLD + c];
+        }
+      }
+    }
+  }
   if (EPI == kEpiFwdOut && g.target) {
     // fixed-order reduction of the tile's squared errors
 #pragma unroll
@@ -170,45 +249,70 @@ __global__ void __launch_bounds__(256, 3) gemm_nt_kernel(const GemmArgs g) {
   }
 }
 
+template <int EPI, int TM, int TN, bool EX, int KS>
+hipError_t launch_gemm_k(const GemmArgs& g, dim3 grid, hipStream_t s) {
+  constexpr size_t lds = gemm_lds_bytes<TM, TN, KS>();
+  auto kern = gemm_nt_kernel<EPI, TM, TN, EX, KS>;
+  if (lds > 64 * 1024) {
+    static const hipError_t attr =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g);
+  return hipSuccess;
+}
+
+// K stage: 32 for 128 x 128 workgroup tiles (three workgroups fit a compute
+// unit's LDS); for smaller tiles 128 where every split's K range is a
+// multiple of 128, else 64 where a multiple of 64, else 32
 template <int EPI, int TM, int TN>
-void launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
+hipError_t launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
   const dim3 grid((g.N + 64 * TN - 1) / (64 * TN), (g.M + 64 * TM - 1) / (64 * TM), splits);
+  const int ks = TM * TN > 2 ? 32   // 128 x 128 tiles: three workgroups per compute unit
+                 : (g.K % 128 == 0 && g.k_per_split % 128 == 0) ? 128
+                 : (g.K % 64 == 0 && g.k_per_split % 64 == 0) ? 64 : 32;
   // every split's K range non-empty and a whole number of stages
-  const bool ex = g.M % (64 * TM) == 0 && g.N % (64 * TN) == 0 && g.K > 0 && g.K % kKStep == 0 &&
-                  g.k_per_split % kKStep == 0 && (int64_t)g.k_per_split * (splits - 1) < g.K && g.lda % 8 == 0 &&
+  const bool ex = g.M % (64 * TM) == 0 && g.N % (64 * TN) == 0 && g.K > 0 && g.K % ks == 0 &&
+                  g.k_per_split % ks == 0 && (int64_t)g.k_per_split * (splits - 1) < g.K && g.lda % 8 == 0 &&
                   g.ldb % 8 == 0 && reinterpret_cast<uintptr_t>(g.A) % 16 == 0 &&
                   reinterpret_cast<uintptr_t>(g.Bt) % 16 == 0;
-  if (ex) hipLaunchKernelGGL((gemm_nt_kernel<EPI, TM, TN, true>), grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((gemm_nt_kernel<EPI, TM, TN, false>), grid, dim3(256), 0, s, g);
+  hipError_t e;
+  if (ex && ks == 128) e = launch_gemm_k<EPI, TM, TN, true, 128>(g, grid, s);
+  else if (ex && ks == 64) e = launch_gemm_k<EPI, TM, TN, true, 64>(g, grid, s);
+  else if (ex) e = launch_gemm_k<EPI, TM, TN, true, 32>(g, grid, s);
+  else e = launch_gemm_k<EPI, TM, TN, false, 32>(g, grid, s);
   if (info) {
     info[0] = 64 * TM;
     info[1] = 64 * TN;
     info[2] = splits;
-    info[3] = ex ? 1 : 0;
+    info[3] = ex ? ks : 0;
   }
+  return e;
 }
 
 template <int EPI>
-void launch_gemm_e(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
+hipError_t launch_gemm_e(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
   // largest tile that still gives at least 256 workgroups; the loss partials
   // of a training forward are laid out per 64 x 64 tile
   const int64_t t22 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * splits;
   const int64_t t21 = (int64_t)((g.N + 63) / 64) * ((g.M + 127) / 128) * splits;
-  if (EPI == kEpiFwdOut && g.target) launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
-  else if (t22 >= 256) launch_gemm_t<EPI, 2, 2>(g, splits, s, info);
-  else if (t21 >= 256) launch_gemm_t<EPI, 2, 1>(g, splits, s, info);
-  else launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
+  if (EPI == kEpiFwdOut && g.target) return launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
+  if (t22 >= 256) return launch_gemm_t<EPI, 2, 2>(g, splits, s, info);
+  if (t21 >= 256) return launch_gemm_t<EPI, 2, 1>(g, splits, s, info);
+  return launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
 }
 
 hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s, int32_t* info) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   (void)hipGetLastError();  // report only this launch's status
+  hipError_t e;
   switch (epi) {
-    case kEpiWgrad: launch_gemm_e<kEpiWgrad>(g, splits, s, info); break;
-    case kEpiFwdHidden: launch_gemm_e<kEpiFwdHidden>(g, splits, s, info); break;
-    case kEpiFwdOut: launch_gemm_e<kEpiFwdOut>(g, splits, s, info); break;
-    default: launch_gemm_e<kEpiBwdHidden>(g, splits, s, info); break;
+    case kEpiWgrad: e = launch_gemm_e<kEpiWgrad>(g, splits, s, info); break;
+    case kEpiFwdHidden: e = launch_gemm_e<kEpiFwdHidden>(g, splits, s, info); break;
+    case kEpiFwdOut: e = launch_gemm_e<kEpiFwdOut>(g, splits, s, info); break;
+    default: e = launch_gemm_e<kEpiBwdHidden>(g, splits, s, info); break;
   }
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -233,6 +337,50 @@ __global__ void pack_bf16_kernel(const float* __restrict__ src, int rows, int co
     }
 }
 
+// pack_bf16_kernel of the rows idx[0..rows) of src (one read per element)
+__global__ void gather_pack_kernel(const float* __restrict__ src, int64_t src_rows, int cols,
+                                   const int32_t* __restrict__ idx, int rows, __bf16* dst, int ldd, __bf16* dst_t,
+                                   int ldt, int32_t* rows_out, int32_t* status) {
+  __shared__ float tile[32][33];
+  __shared__ int64_t srow[32];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  if (threadIdx.x < 32) {
+    const int r = r0 + threadIdx.x;
+    int64_t q = 0;
+    if (r < rows) {
+      q = idx[r];
+      if (q < 0 || q >= src_rows) {
+        atomicOr(status, (int)kStatusBadIndex);
+        q = 0;
+      }
+      if (blockIdx.x == 0) rows_out[r] = (int32_t)q;
+    }
+    srow[threadIdx.x] = q;
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int r = r0 + i, c = c0 + tx;
+    const float v = (r < rows && c < cols) ? src[srow[i] * cols + c] : 0.0f;
+    tile[i][tx] = v;
+    if (r < rows && c < cols) dst[(int64_t)r * ldd + c] = to_bf16(v);
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int c = c0 + i, r = r0 + tx;
+    if (r < rows && c < cols) dst_t[(int64_t)c * ldt + r] = to_bf16(tile[tx][i]);
+  }
+}
+
+hipError_t launch_gather_pack(const float* src, int64_t src_rows, int cols, const int32_t* idx, int rows, __bf16* dst,
+                              int ldd, __bf16* dst_t, int ldt, int32_t* rows_out, int32_t* status, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  (void)hipGetLastError();  // report only this launch's status
+  hipLaunchKernelGGL(gather_pack_kernel, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, s, src, src_rows,
+                     cols, idx, rows, dst, ldd, dst_t, ldt, rows_out, status);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack(const float* src, int rows, int cols, __bf16* dst, int ldd, __bf16* dst_t, int ldt,
                        hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
@@ -242,26 +390,59 @@ hipError_t launch_pack(const float* src, int rows, int cols, __bf16* dst, int ld
   return hipGetLastError();
 }
 
-// Sum of split-K partials in order: out[i] = sum_s part[s][i].
-__global__ void splitk_sum_kernel(const float* __restrict__ part, int64_t n, int splits, float* __restrict__ out) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float v = 0.0f;
-  for (int s = 0; s < splits; ++s) v += part[(int64_t)s * n + i];
-  out[i] = v;
+// The end of a weight gradient: blocks [0, nsum) sum its split-K partials
+// in split order (256 outputs each), the others take the row sums of the
+// transposed activation gradient (its bias gradient), 4 rows each.
+__global__ void wgrad_finish_kernel(const float* __restrict__ part, int64_t n, int splits, float* __restrict__ out,
+                                    int nsum, const __bf16* __restrict__ x, int rows, int cols, int ld,
+                                    float* __restrict__ bias_out) {
+  if ((int)blockIdx.x < nsum) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = 0.0f;
+    for (int q = 0; q < splits; ++q) v += part[(int64_t)q * n + i];
+    out[i] = v;
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const int row = (blockIdx.x - nsum) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  // lane sums of 8 consecutive elements per 512 (eight loads in flight),
+  // then the lane tree: one fixed order
+  const __bf16* xr = x + (int64_t)row * ld;
+  float sm = 0.0f;
+  const bool vec = (ld % 8) == 0 && (reinterpret_cast<uintptr_t>(x) % 16) == 0;
+  int c0 = 0;
+  if (vec) {
+    for (; c0 + 512 * 8 <= cols; c0 += 512 * 8) {
+      bf16x8 q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = *reinterpret_cast<const bf16x8*>(xr + c0 + 512 * u + lane * 8);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sm += (float)q[u][i];
+    }
+    for (; c0 + 512 <= cols; c0 += 512) {
+      const bf16x8 q = *reinterpret_cast<const bf16x8*>(xr + c0 + lane * 8);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sm += (float)q[i];
+    }
+  }
+  for (int c = c0 + lane; c < cols; c += 64) sm += (float)xr[c];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) sm += __shfl_xor(sm, off, 64);
+  if (lane == 0) bias_out[row] = sm;
 }
 
-// Row sums of a BF16 [rows x cols] matrix (bias gradients from transposed
-// activation gradients): one wave per row, lane-strided sums, fixed tree.
-__global__ void rowsum_kernel(const __bf16* __restrict__ x, int rows, int cols, int ld, float* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= rows) return;
-  float s = 0.0f;
-  for (int c = lane; c < cols; c += 64) s += (float)x[(int64_t)row * ld + c];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) out[row] = s;
+hipError_t launch_wgrad_finish(const float* part, int64_t n, int splits, float* out, const __bf16* x, int rows,
+                               int cols, int ld, float* bias_out, hipStream_t s) {
+  const int nsum = (int)((n + 255) / 256), nrow = (rows + 3) / 4;
+  if (nsum + nrow <= 0) return hipSuccess;
+  (void)hipGetLastError();  // report only this launch's status
+  hipLaunchKernelGGL(wgrad_finish_kernel, dim3(nsum + nrow), dim3(256), 0, s, part, n, splits, out, nsum, x, rows,
+                     cols, ld, bias_out);
+  return hipGetLastError();
 }
 
 // Loss from per-tile partial sums, in order.
@@ -278,31 +459,87 @@ __global__ void loss_sum_kernel(const float* __restrict__ part, int n, float sca
   if (threadIdx.x == 0) *loss = red[0] * scale;
 }
 
-// Adam with bias correction (Kingma and Ba, 2015) on FP32 master weights.
+// Adam with bias correction (Kingma and Ba, 2015) on FP32 master weights:
+// one parameter, returns its new value (the one expression both Adam
+// kernels use).
+__device__ __forceinline__ float adam_update(float* __restrict__ p, const float* __restrict__ gr,
+                                             float* __restrict__ m, float* __restrict__ v, int64_t i, float lr,
+                                             float b1, float b2, float eps, float c1, float c2) {
+  const float g = gr[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * g;
+  const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float pn = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pn;
+  return pn;
+}
+
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
                             float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
                             float c2) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float g = gr[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * g;
-    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    (void)adam_update(p, gr, m, v, i, lr, b1, b2, eps, c1, c2);
+}
+
+// Adam over the flat parameters with the three weight matrices' BF16 working
+// copies written from the updated values: blocks [0, tiles) take 32 x 32
+// tiles of the matrices (layer after layer, row-major tile order), updating
+// them and writing the row-major copy directly and the transposed copy
+// through LDS; the remaining blocks update every other parameter (the
+// biases), 256 per block.
+__global__ void adam_pack_kernel(const AdamPackArgs a, int tiles0, int tiles1, int tiles2) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+  int b = blockIdx.x;
+  const int tl[3] = {tiles0, tiles1, tiles2};
+  int l = 0;
+  while (l < 3 && b >= tl[l]) b -= tl[l++];
+  if (l < 3) {
+    const int R = a.rows[l], Cc = a.cols[l], tcols = (Cc + 31) / 32;
+    const int r0 = (b / tcols) * 32, c0 = (b % tcols) * 32;
+    for (int i = ty; i < 32; i += 8) {
+      const int r = r0 + i, c = c0 + tx;
+      float w = 0.0f;
+      if (r < R && c < Cc) {
+        w = adam_update(a.p, a.g, a.m, a.v, a.off[l] + (int64_t)r * Cc + c, a.lr, a.b1, a.b2, a.eps, a.c1, a.c2);
+        a.w[l][(int64_t)r * Cc + c] = (__bf16)w;
+      }
+      tile[i][tx] = w;
+    }
+    if (a.wt[l]) {
+      __syncthreads();
+      for (int i = ty; i < 32; i += 8) {
+        const int c = c0 + i, r = r0 + tx;
+        if (r < R && c < Cc) a.wt[l][(int64_t)c * R + r] = (__bf16)tile[tx][i];
+      }
+    }
+    return;
   }
+  // the rest: parameters outside the three matrices, in order
+  const int64_t j = (int64_t)b * 256 + threadIdx.x;
+  int64_t i = j;
+  for (int q = 0; q < 3; ++q) {   // skip the matrices that come before
+    const int64_t sz = (int64_t)a.rows[q] * a.cols[q];
+    if (i >= a.off[q]) i += sz;
+  }
+  if (i < a.n) (void)adam_update(a.p, a.g, a.m, a.v, i, a.lr, a.b1, a.b2, a.eps, a.c1, a.c2);
 }
 
-hipError_t launch_splitk_sum(const float* part, int64_t n, int splits, float* out, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
+hipError_t launch_adam_pack(const AdamPackArgs& a0, int step, hipStream_t s) {
+  AdamPackArgs a = a0;
+  a.c1 = 1.0f - powf(a.b1, (float)step);
+  a.c2 = 1.0f - powf(a.b2, (float)step);
+  int t[3];
+  int64_t inside = 0;
+  for (int l = 0; l < 3; ++l) {
+    t[l] = ((a.rows[l] + 31) / 32) * ((a.cols[l] + 31) / 32);
+    inside += (int64_t)a.rows[l] * a.cols[l];
+  }
+  const int64_t rest = a.n - inside;
+  const int blocks = t[0] + t[1] + t[2] + (int)((rest + 255) / 256);
   (void)hipGetLastError();  // report only this launch's status
-  hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, n, splits, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_rowsum(const __bf16* x, int rows, int cols, int ld, float* out, hipStream_t s) {
-  if (rows <= 0) return hipSuccess;
-  (void)hipGetLastError();  // report only this launch's status
-  hipLaunchKernelGGL(rowsum_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, x, rows, cols, ld, out);
+  hipLaunchKernelGGL(adam_pack_kernel, dim3(blocks), dim3(256), 0, s, a, t[0], t[1], t[2]);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <new>
 
 #include "ctx.hpp"
@@ -22,6 +23,7 @@ struct sugg_mlp {
   __bf16 *xb = nullptr, *xt = nullptr, *h1 = nullptr, *h1t = nullptr, *h2 = nullptr, *h2t = nullptr;
   __bf16 *dy = nullptr, *dyt = nullptr, *da2 = nullptr, *da2t = nullptr, *da1t = nullptr;
   float *a1 = nullptr, *a2 = nullptr, *part = nullptr, *loss_part = nullptr, *ybuf = nullptr;
+  int32_t* trow = nullptr;      // training rows of the current mini-batch (sugg_mlp_train_epoch)
   int64_t part_n = 0;
   float* frozen = nullptr;      // inference copy of the parameters (sugg_mlp_freeze)
   bool packed_frozen = false;   // the BF16 working weights hold the frozen parameters
@@ -32,7 +34,7 @@ struct sugg_mlp {
     dfree(w1); dfree(w2); dfree(w2t); dfree(w3); dfree(w3t);
     dfree(xb); dfree(xt); dfree(h1); dfree(h1t); dfree(h2); dfree(h2t);
     dfree(dy); dfree(dyt); dfree(da2); dfree(da2t); dfree(da1t);
-    dfree(a1); dfree(a2); dfree(part); dfree(loss_part); dfree(ybuf); dfree(frozen);
+    dfree(a1); dfree(a2); dfree(part); dfree(loss_part); dfree(ybuf); dfree(frozen); dfree(trow);
   }
 };
 
@@ -58,9 +60,11 @@ GemmArgs gemm(const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, int N,
   return g;
 }
 
-// weight gradient dW[M x N] = A[M x K] . Bt[N x K]^T with K split across workgroups
+// weight gradient dW[M x N] = A[M x K] . Bt[N x K]^T with K split across
+// workgroups, and the bias gradient db[M] = row sums of A (the transposed
+// activation gradient, K = batch), summed in one finishing launch
 hipError_t wgrad(sugg_mlp* m, const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, int N, int K, float* dW,
-                 hipStream_t s, int32_t* info) {
+                 float* db, hipStream_t s, int32_t* info) {
   GemmArgs g = gemm(A, lda, Bt, ldb, M, N, K);
   const int sp = splits_for(M, N, K);
   g.k_per_split = ((K + sp - 1) / sp + 31) / 32 * 32;
@@ -68,7 +72,7 @@ hipError_t wgrad(sugg_mlp* m, const __bf16* A, int lda, const __bf16* Bt, int ld
   g.Cf = m->part;
   hipError_t e = launch_gemm(g, kEpiWgrad, used, s, info);
   if (e != hipSuccess) return e;
-  return launch_splitk_sum(m->part, (int64_t)M * N, used, dW, s);
+  return launch_wgrad_finish(m->part, (int64_t)M * N, used, dW, A, M, K, lda, db, s);
 }
 
 int check_mlp(sugg_ctx* ctx, sugg_mlp* m, int batch) {
@@ -79,17 +83,23 @@ int check_mlp(sugg_ctx* ctx, sugg_mlp* m, int batch) {
 }
 
 // forward pass; target (nullable) adds the squared-error loss and dY
+hipError_t pack_weights(sugg_mlp* m, const float* params, hipStream_t s) {
+  const int in = m->in, hid = m->hid, out = m->out;
+  hipError_t e = launch_pack(params + m->off_w1, hid, in, m->w1, in, nullptr, 0, s);
+  if (e == hipSuccess) e = launch_pack(params + m->off_w2, hid, hid, m->w2, hid, m->w2t, hid, s);
+  if (e == hipSuccess) e = launch_pack(params + m->off_w3, out, hid, m->w3, hid, m->w3t, out, s);
+  m->packed_frozen = params == m->frozen;
+  return e;
+}
+
+// x == nullptr: the batch is already packed in xb and xt; trow (nullable):
+// row r's target is target row trow[r]
 int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int B, float* y, bool keep,
-            const float* target, float* loss, hipStream_t s, bool pack_weights = true) {
+            const float* target, float* loss, hipStream_t s, bool pack_w = true, const int32_t* trow = nullptr) {
   const int in = m->in, hid = m->hid, out = m->out, bm = m->bm;
   hipError_t e = hipSuccess;
-  if (pack_weights) {
-    e = launch_pack(params + m->off_w1, hid, in, m->w1, in, nullptr, 0, s);
-    if (e == hipSuccess) e = launch_pack(params + m->off_w2, hid, hid, m->w2, hid, m->w2t, hid, s);
-    if (e == hipSuccess) e = launch_pack(params + m->off_w3, out, hid, m->w3, hid, m->w3t, out, s);
-    m->packed_frozen = params == m->frozen;
-  }
-  if (e == hipSuccess) e = launch_pack(x, B, in, m->xb, in, keep ? m->xt : nullptr, bm, s);
+  if (pack_w) e = pack_weights(m, params, s);
+  if (e == hipSuccess && x) e = launch_pack(x, B, in, m->xb, in, keep ? m->xt : nullptr, bm, s);
   if (e != hipSuccess) return ctx->hip(e, "mlp pack");
   GemmArgs g = gemm(m->xb, in, m->w1, in, B, hid, in);
   g.bias = params + m->off_b1;
@@ -118,6 +128,7 @@ int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int
   if (target) {
     g.target = target;
     g.ldt = out;
+    g.trow = trow;
     g.Cb = m->dy;
     g.ldcb = out;
     g.Ct = m->dyt;
@@ -140,8 +151,7 @@ int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int
 int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grads, hipStream_t s) {
   (void)params;
   const int in = m->in, hid = m->hid, out = m->out, bm = m->bm;
-  hipError_t e = wgrad(m, m->dyt, bm, m->h2t, bm, out, hid, B, grads + m->off_w3, s, m->info[3]);
-  if (e == hipSuccess) e = launch_rowsum(m->dyt, out, B, bm, grads + m->off_b3, s);
+  hipError_t e = wgrad(m, m->dyt, bm, m->h2t, bm, out, hid, B, grads + m->off_w3, grads + m->off_b3, s, m->info[3]);
   if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 3");
   GemmArgs g = gemm(m->dy, out, m->w3t, out, B, hid, out);
   g.gact = m->a2;
@@ -151,8 +161,8 @@ int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grad
   g.Ct = m->da2t;
   g.ldct = bm;
   e = launch_gemm(g, kEpiBwdHidden, 1, s, m->info[4]);
-  if (e == hipSuccess) e = wgrad(m, m->da2t, bm, m->h1t, bm, hid, hid, B, grads + m->off_w2, s, m->info[5]);
-  if (e == hipSuccess) e = launch_rowsum(m->da2t, hid, B, bm, grads + m->off_b2, s);
+  if (e == hipSuccess)
+    e = wgrad(m, m->da2t, bm, m->h1t, bm, hid, hid, B, grads + m->off_w2, grads + m->off_b2, s, m->info[5]);
   if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 2");
   g = gemm(m->da2, hid, m->w2t, hid, B, hid, hid);
   g.gact = m->a1;
@@ -160,8 +170,8 @@ int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grad
   g.Ct = m->da1t;
   g.ldct = bm;
   e = launch_gemm(g, kEpiBwdHidden, 1, s, m->info[6]);
-  if (e == hipSuccess) e = wgrad(m, m->da1t, bm, m->xt, bm, hid, in, B, grads + m->off_w1, s, m->info[7]);
-  if (e == hipSuccess) e = launch_rowsum(m->da1t, hid, B, bm, grads + m->off_b1, s);
+  if (e == hipSuccess)
+    e = wgrad(m, m->da1t, bm, m->xt, bm, hid, in, B, grads + m->off_w1, grads + m->off_b1, s, m->info[7]);
   if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 1");
   return SUGG_OK;
 }
@@ -237,6 +247,7 @@ int32_t sugg_mlp_create(sugg_ctx* ctx, int32_t in, int32_t hidden, int32_t out, 
   A(m->part, sizeof(float) * part);
   A(m->loss_part, sizeof(float) * ((bm + 63) / 64) * ((out + 63) / 64));
   A(m->ybuf, sizeof(float) * bm * out);
+  A(m->trow, sizeof(int32_t) * bm);
   if (e != hipSuccess) {
     delete m;
     return ctx->hip(e, "mlp workspace");
@@ -328,6 +339,55 @@ int32_t sugg_mlp_train_step(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float* 
   rc = backward(ctx, mlp, params, batch, grads, stream);
   if (rc) return rc;
   return sugg_mlp_adam(ctx, mlp, params, grads, m, v, step, lr, 0.9f, 0.999f, 1e-8f, stream);
+}
+
+int32_t sugg_mlp_train_epoch(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float* grads, float* m, float* v,
+                             int32_t step0, float lr, const float* X, const float* Y, int64_t n_rows,
+                             const int32_t* perm, int32_t batch, int32_t steps, float* losses, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  int rc = check_mlp(ctx, mlp, batch);
+  if (rc) return rc;
+  if (!params || !grads || !m || !v || !X || !Y || !perm || (steps > 0 && !losses))
+    return ctx->fail(SUGG_E_ARG, "null argument");
+  if (steps < 0 || step0 < 0 || n_rows < 1 || n_rows > INT32_MAX || !(lr > 0.f))
+    return ctx->fail(SUGG_E_ARG, "bad steps, step0, n_rows or lr");
+  if (steps == 0) return SUGG_OK;
+  hipError_t e = pack_weights(mlp, params, stream);
+  if (e != hipSuccess) return ctx->hip(e, "mlp pack");
+  AdamPackArgs ap{};
+  ap.p = params;
+  ap.g = grads;
+  ap.m = m;
+  ap.v = v;
+  ap.n = mlp->nparam;
+  ap.lr = lr;
+  ap.b1 = 0.9f;
+  ap.b2 = 0.999f;
+  ap.eps = 1e-8f;
+  const int64_t offs[3] = {mlp->off_w1, mlp->off_w2, mlp->off_w3};
+  const int rows[3] = {mlp->hid, mlp->hid, mlp->out}, cols[3] = {mlp->in, mlp->hid, mlp->hid};
+  __bf16* w[3] = {mlp->w1, mlp->w2, mlp->w3};
+  __bf16* wt[3] = {nullptr, mlp->w2t, mlp->w3t};
+  for (int l = 0; l < 3; ++l) {
+    ap.off[l] = offs[l];
+    ap.rows[l] = rows[l];
+    ap.cols[l] = cols[l];
+    ap.w[l] = w[l];
+    ap.wt[l] = wt[l];
+  }
+  for (int s = 0; s < steps; ++s) {
+    e = launch_gather_pack(X, n_rows, mlp->in, perm + (int64_t)s * batch, batch, mlp->xb, mlp->in, mlp->xt, mlp->bm,
+                           mlp->trow, ctx->d_status, stream);
+    if (e != hipSuccess) return ctx->hip(e, "mlp gather");
+    rc = forward(ctx, mlp, params, nullptr, batch, mlp->ybuf, true, Y, losses + s, stream, false, mlp->trow);
+    if (rc) return rc;
+    rc = backward(ctx, mlp, params, batch, grads, stream);
+    if (rc) return rc;
+    e = launch_adam_pack(ap, step0 + s + 1, stream);
+    if (e != hipSuccess) return ctx->hip(e, "mlp adam");
+  }
+  mlp->packed_frozen = false;
+  return SUGG_OK;
 }
 
 }  // extern "C"

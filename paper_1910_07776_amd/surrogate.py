@@ -136,6 +136,26 @@ class MLP:
                                                         _ptr(target), x.shape[0], _ptr(self.loss), _stream()))
         return self.loss
 
+    def train_epoch(self, X, Y, perm, batch: int, lr=1e-3):
+        """len(perm) // batch training steps in one library call over the
+        mini-batches X[perm[s*batch:(s+1)*batch]] (gathered on the device);
+        returns the per-step losses (device)."""
+        self._check_x(X[:1], self.in_)
+        self._check_x(Y[:1], self.out)
+        if not (X.is_contiguous() and Y.is_contiguous() and X.shape[0] == Y.shape[0]):
+            raise ValueError("X and Y must be contiguous with one row per sample")
+        if perm.dtype != torch.int32 or not perm.is_contiguous() or perm.device != self.ctx.device:
+            raise ValueError("perm must be a contiguous int32 tensor on the device")
+        if not 1 <= batch <= self.max_batch:
+            raise ValueError(f"batch outside [1, {self.max_batch}]")
+        steps = perm.numel() // batch
+        losses = torch.zeros(steps, device=self.ctx.device)
+        A.check(self.ctx.h, A.lib().sugg_mlp_train_epoch(
+            self.ctx.h, self.h, _ptr(self.params), _ptr(self.grads), _ptr(self.m), _ptr(self.v), self.step, lr,
+            _ptr(X), _ptr(Y), X.shape[0], _ptr(perm), batch, steps, _ptr(losses), _stream()))
+        self.step += steps
+        return losses
+
     def state_dict(self):
         return {"params": self.params.clone(), "m": self.m.clone(), "v": self.v.clone(), "step": self.step,
                 "shape": (self.in_, self.hidden, self.out)}
@@ -246,18 +266,11 @@ def train(mlp: MLP, X: torch.Tensor, Y: torch.Tensor, epochs: int, batch: int = 
     steps = max(1, n // batch)
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
-    xb = torch.empty((batch, X.shape[1]), device=dev)
-    yb = torch.empty((batch, Y.shape[1]), device=dev)
     hist = []
     for ep in range(1, epochs + 1):
-        perm = torch.randperm(n, generator=g, device=dev)
-        tot = torch.zeros((), device=dev)
-        for s in range(steps):
-            idx = perm[s * batch:(s + 1) * batch]
-            torch.index_select(X, 0, idx, out=xb)
-            torch.index_select(Y, 0, idx, out=yb)
-            tot += mlp.train_step(xb, yb, lr)[0]
-        rec = {"epoch": ep, "loss": float(tot.item()) / steps}
+        perm = torch.randperm(n, generator=g, device=dev)[:steps * batch].to(torch.int32)
+        losses = mlp.train_epoch(X, Y, perm, batch, lr)
+        rec = {"epoch": ep, "loss": float(losses.sum().item()) / steps}
         if val is not None and (ep % check_every == 0 or ep == epochs):
             rec["val_mape"] = mape(predict_table(mlp, val[0]), val[1])
         hist.append(rec)
