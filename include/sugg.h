@@ -485,6 +485,24 @@ SUGG_API int32_t sugg_mlp_train_step(sugg_ctx* ctx, sugg_mlp* mlp, float* params
  * partials.  Bit-identical to train_step on the gathered batches.  perm is a
  * device int32 array of steps*batch entries; an entry outside [0, n_rows)
  * reads row 0 and the next sugg_sync reports SUGG_E_ARG.  Asynchronous. */
+/* Inference with the frozen parameters (sugg_mlp_freeze; SUGG_E_STATE
+ * without): y [batch x out] for x [batch x in], as sugg_mlp_forward without
+ * kept activations; the working weights are packed once per freeze. */
+SUGG_API int32_t sugg_mlp_infer(sugg_ctx* ctx, sugg_mlp* mlp, const float* x, int32_t batch, float* y,
+                                hipStream_t stream);
+/* Inference with the frozen parameters and Tier 3 on every row of the
+ * output (Section 2: the best n choices above the threshold, by expected
+ * benefit): idx [batch x n] the output columns >= skip whose value exceeds
+ * tau, by value descending then column ascending, -1 padded; score the
+ * values (NaN padded); count [batch] how many.  Identical to sugg_mlp_infer
+ * then sugg_rank_suggest over rows of out values (skip_head = skip).  For
+ * out = 64 or 128 the output layer ranks in its epilogue (the outputs never
+ * leave the chip unless y, nullable, asks for them).  1 <= n <= 8,
+ * 0 <= skip < out. */
+SUGG_API int32_t sugg_mlp_infer_rank(sugg_ctx* ctx, sugg_mlp* mlp, const float* x, int32_t batch, int32_t skip,
+                                     int32_t n, float tau, float* y, int32_t* idx, float* score, int32_t* count,
+                                     hipStream_t stream);
+
 SUGG_API int32_t sugg_mlp_train_epoch(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float* grads, float* m,
                                       float* v, int32_t step0, float lr, const float* X, const float* Y,
                                       int64_t n_rows, const int32_t* perm, int32_t batch, int32_t steps,

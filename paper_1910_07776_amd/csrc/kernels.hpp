@@ -154,7 +154,7 @@ hipError_t launch_path(const PathArgs<T>& a, int max_item_rows, int max_item_ker
 template <typename T>
 hipError_t launch_rank(const T* scores, const int64_t* seg_off, int32_t nseg, int32_t skip_head,
                        int32_t n, T tau, int32_t* idx_out, T* score_out, int32_t* count_out,
-                       hipStream_t s);
+                       hipStream_t s, int64_t seg_len = 0);   // seg_off null: segments of seg_len
 
 // Threshold band of short suggestion lists (entries outside the list with
 // score >= lo, ascending, at most C per segment; flag 1 on overflow).
@@ -268,7 +268,8 @@ enum GemmEpilogue : int {
   kEpiWgrad = 0,       // FP32 split-K partial of a weight gradient
   kEpiFwdHidden = 1,   // + bias, keep pre-activation, GELU, BF16 row-major and transposed
   kEpiFwdOut = 2,      // + bias -> Y; with targets: squared error partials and dY
-  kEpiBwdHidden = 3    // * GELU'(pre-activation) -> BF16 row-major and transposed
+  kEpiBwdHidden = 3,   // * GELU'(pre-activation) -> BF16 row-major and transposed
+  kEpiFwdRank = 4      // + bias -> Y (optional) and each row's top n above tau (the tile spans N)
 };
 
 // C[M x N] = A[M x K] . Bt[N x K]^T, BF16 operands, FP32 accumulation.
@@ -291,6 +292,11 @@ struct GemmArgs {
   const float* target;   // [M x N] targets
   int ldt;
   const int32_t* trow;   // nullable: output row r's target is row trow[r] of target
+  int32_t* idx_out;      // kEpiFwdRank: [M x n] columns of each row's top n (-1 padded),
+  float* score_out;      //   their values (NaN padded) and the count; columns >= skip
+  int32_t* count_out;    //   with value > tau, by value descending then column ascending
+  int n, skip;
+  float tau;
   float* loss_part;      // one partial per output tile
   float scale;           // dY = scale * (Y - T)
 };
@@ -298,6 +304,8 @@ struct GemmArgs {
 // info (nullable, 4 ints): the launched instance as (tile rows, tile columns,
 // K splits, 1 if the variant without bounds checks ran)
 hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s, int32_t* info = nullptr);
+// the output layer with the ranking epilogue: N must be 64 or 128, n <= 8
+hipError_t launch_gemm_rank(const GemmArgs& g, hipStream_t s, int32_t* info = nullptr);
 hipError_t launch_pack(const float* src, int rows, int cols, __bf16* dst, int ldd, __bf16* dst_t, int ldt,
                        hipStream_t s);
 hipError_t launch_loss_sum(const float* part, int n, float scale, float* loss, hipStream_t s);

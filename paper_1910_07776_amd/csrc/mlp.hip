@@ -39,9 +39,23 @@ __host__ __device__ constexpr size_t gemm_lds_bytes() {
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 
-__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by Abramowitz and Stegun, Handbook of Mathematical Functions, formula
+// 7.1.26: erf(a) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^(-a^2) with
+// t = 1 / (1 + p a) for a >= 0 (odd extension below 0), absolute error at
+// most 1.5e-7 in exact arithmetic; in FP32 (hardware reciprocal and
+// exponential) a few units of 1e-7 more, far below the BF16 rounding of
+// every output it feeds.  Two transcendental and six fused operations in
+// place of the library's erff.
+__device__ __forceinline__ float erf_as(float x) {
+  const float a = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+  return copysignf(1.0f - poly * __expf(-a * a), x);
+}
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+  return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
 }
 
 // Load 8 consecutive K elements of row `row` (zero outside [0, rows) x [0, K)).
@@ -54,6 +68,41 @@ __device__ __forceinline__ bf16x8 load8(const __bf16* p, int ld, int row, int ro
     for (int i = 0; i < 8; ++i) v[i] = (row < rows && k + i < K) ? p[(int64_t)row * ld + k + i] : (__bf16)0.0f;
   }
   return v;
+}
+
+// Tier 3 of the output rows held in an LDS tile y [rows x ldy]: thread t
+// takes row t / 2 and half t % 2 of its W columns (columns >= skip), keeps a
+// best-first list of KT, merges it with its partner's and writes the row's
+// top n (as rank_kernel: -1 / NaN padded, count).
+template <int KT, int W>
+__device__ __forceinline__ void rank_rows(const GemmArgs& g, const float* y, int ldy, int m0, int tid, bool exact) {
+  const int r = tid >> 1, half = tid & 1, row = m0 + r;
+  Entry<float> lst[KT];
+#pragma unroll
+  for (int i = 0; i < KT; ++i) lst[i] = empty_entry<float>();
+  const int c0 = half * (W / 2);
+  for (int c = c0 < g.skip ? g.skip : c0; c < c0 + W / 2; ++c) {
+    const float v = y[r * ldy + c];
+    if (v > g.tau) {
+      Entry<float> e;
+      e.v = v;
+      e.s = c;
+      list_insert<float, KT>(lst, e);
+    }
+  }
+  group_merge<float, KT>(lst, 2);
+  if (half == 0 && (exact || row < g.M)) {
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < KT; ++i)
+      if (i < g.n) {
+        const bool ok = lst[i].s >= 0;
+        g.idx_out[(int64_t)row * g.n + i] = ok ? lst[i].s : -1;
+        g.score_out[(int64_t)row * g.n + i] = ok ? lst[i].v : __builtin_nanf("");
+        cnt += ok ? 1 : 0;
+      }
+    g.count_out[row] = cnt;
+  }
 }
 
 // Workgroup of 4 waves in a 2 x 2 arrangement; each wave computes TM x TN
@@ -146,7 +195,7 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
   // before its first store, all loads in flight together (a load after a
   // store to memory that might alias it would wait for that store)
   float bcol[TN], pre[TM][TN][16];
-  if (EPI == kEpiFwdHidden || EPI == kEpiFwdOut) {
+  if (EPI == kEpiFwdHidden || EPI == kEpiFwdOut || EPI == kEpiFwdRank) {
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
       const int col = n0 + wn * 32 * TN + b * 32 + (lane & 31);
@@ -171,7 +220,9 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
         }
       }
   }
-  if (stage) __syncthreads();   // every wave is done with the operand tiles
+  if (stage || EPI == kEpiFwdRank) __syncthreads();   // every wave is done with the operand tiles
+  float* Ty = reinterpret_cast<float*>(gsm);           // kEpiFwdRank: the FP32 tile
+  constexpr int YLD = WGN + 1;
   float sse = 0.0f;
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -200,6 +251,10 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
             sse = fmaf(d, d, sse);
             o = g.scale * d;
           }
+        } else if (EPI == kEpiFwdRank) {
+          const float y = v + bcol[b];
+          if (g.Cf) g.Cf[(int64_t)row * g.ldcf + col] = y;
+          Ty[tr * YLD + tc] = y;
         } else {  // kEpiBwdHidden
           o = v * gelu_grad_f(pre[a][b][r]);
         }
@@ -239,6 +294,15 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
       }
     }
   }
+  if constexpr (EPI == kEpiFwdRank) {
+    // two threads per row of the tile (the row's N = WGN outputs), each a
+    // best-first list of its half (value descending, column ascending), the
+    // pair's lists merged; lists of 4 where n <= 4
+    static_assert(WGM * 2 == 256, "two threads per tile row");
+    __syncthreads();
+    if (g.n <= 4) rank_rows<4, WGN>(g, Ty, YLD, m0, tid, EX);
+    else rank_rows<kMaxSuggest, WGN>(g, Ty, YLD, m0, tid, EX);
+  }
   if (EPI == kEpiFwdOut && g.target) {
     // fixed-order reduction of the tile's squared errors
 #pragma unroll
@@ -251,7 +315,9 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
 
 template <int EPI, int TM, int TN, bool EX, int KS>
 hipError_t launch_gemm_k(const GemmArgs& g, dim3 grid, hipStream_t s) {
-  constexpr size_t lds = gemm_lds_bytes<TM, TN, KS>();
+  // the ranking epilogue keeps the FP32 output tile (rows padded by one)
+  constexpr size_t ty = EPI == kEpiFwdRank ? sizeof(float) * 64 * TM * (64 * TN + 1) : 0;
+  constexpr size_t lds = gemm_lds_bytes<TM, TN, KS>() > ty ? gemm_lds_bytes<TM, TN, KS>() : ty;
   auto kern = gemm_nt_kernel<EPI, TM, TN, EX, KS>;
   if (lds > 64 * 1024) {
     static const hipError_t attr =
@@ -292,14 +358,25 @@ hipError_t launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s, int32_t* 
 
 template <int EPI>
 hipError_t launch_gemm_e(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
-  // largest tile that still gives at least 256 workgroups; the loss partials
-  // of a training forward are laid out per 64 x 64 tile
+  // largest tile that still gives at least 256 workgroups (128 columns only
+  // where they divide N); the loss partials of a training forward are laid
+  // out per 64 x 64 tile
   const int64_t t22 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * splits;
   const int64_t t21 = (int64_t)((g.N + 63) / 64) * ((g.M + 127) / 128) * splits;
   if (EPI == kEpiFwdOut && g.target) return launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
-  if (t22 >= 256) return launch_gemm_t<EPI, 2, 2>(g, splits, s, info);
+  if (t22 >= 256 && g.N % 128 == 0) return launch_gemm_t<EPI, 2, 2>(g, splits, s, info);
   if (t21 >= 256) return launch_gemm_t<EPI, 2, 1>(g, splits, s, info);
   return launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
+}
+
+hipError_t launch_gemm_rank(const GemmArgs& g, hipStream_t s, int32_t* info) {
+  if (g.M <= 0) return hipSuccess;
+  if ((g.N != 64 && g.N != 128) || g.n < 1 || g.n > kMaxSuggest || g.skip < 0) return hipErrorInvalidValue;
+  (void)hipGetLastError();  // report only this launch's status
+  const hipError_t e = g.N == 64 ? launch_gemm_t<kEpiFwdRank, 2, 1>(g, 1, s, info)
+                                 : launch_gemm_t<kEpiFwdRank, 2, 2>(g, 1, s, info);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s, int32_t* info) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <new>
 
@@ -187,6 +188,58 @@ int mlp_infer(sugg_ctx* ctx, sugg_mlp* m, const float* x, int B, float* y, hipSt
   return forward(ctx, m, m->frozen, x, B, y, false, nullptr, nullptr, s, !m->packed_frozen);
 }
 
+namespace {
+
+// Inference and each row's top n of the outputs in columns >= skip above
+// tau: the output layer's epilogue ranks where the output width is 64 or
+// 128 (a tile row), otherwise the outputs go through the row ranking kernel.
+int infer_rank(sugg_ctx* ctx, sugg_mlp* m, const float* x, int B, int skip, int n, float tau, float* y,
+               int32_t* idx, float* score, int32_t* count, hipStream_t s) {
+  const int in = m->in, hid = m->hid, out = m->out;
+  hipError_t e = hipSuccess;
+  if (!m->packed_frozen) e = pack_weights(m, m->frozen, s);
+  if (e == hipSuccess) e = launch_pack(x, B, in, m->xb, in, nullptr, m->bm, s);
+  if (e != hipSuccess) return ctx->hip(e, "mlp pack");
+  const float* params = m->frozen;
+  GemmArgs g = gemm(m->xb, in, m->w1, in, B, hid, in);
+  g.bias = params + m->off_b1;
+  g.Cb = m->h1;
+  g.ldcb = hid;
+  e = launch_gemm(g, kEpiFwdHidden, 1, s, m->info[0]);
+  if (e != hipSuccess) return ctx->hip(e, "mlp layer 1");
+  g = gemm(m->h1, hid, m->w2, hid, B, hid, hid);
+  g.bias = params + m->off_b2;
+  g.Cb = m->h2;
+  g.ldcb = hid;
+  e = launch_gemm(g, kEpiFwdHidden, 1, s, m->info[1]);
+  if (e != hipSuccess) return ctx->hip(e, "mlp layer 2");
+  g = gemm(m->h2, hid, m->w3, hid, B, out, hid);
+  g.bias = params + m->off_b3;
+  g.Cf = y;
+  g.ldcf = out;
+  if (out == 64 || out == 128) {
+    g.idx_out = idx;
+    g.score_out = score;
+    g.count_out = count;
+    g.n = n;
+    g.skip = skip;
+    g.tau = tau;
+    e = launch_gemm_rank(g, s, m->info[2]);
+    if (e != hipSuccess) return ctx->hip(e, "mlp layer 3 with ranking");
+  } else {
+    if (!y) g.Cf = m->ybuf;
+    e = launch_gemm(g, kEpiFwdOut, 1, s, m->info[2]);
+    if (e == hipSuccess)
+      e = launch_rank<float>(g.Cf, nullptr, B, skip, n, tau, idx, score, count, s, (int64_t)out);
+    if (e != hipSuccess) return ctx->hip(e, "mlp layer 3 and ranking");
+  }
+  m->kept_batch = -1;
+  m->have_dy = false;
+  return SUGG_OK;
+}
+
+}  // namespace
+
 void mlp_dims(const sugg_mlp* m, int* in, int* out, int* max_batch) {
   *in = m->in;
   *out = m->out;
@@ -339,6 +392,26 @@ int32_t sugg_mlp_train_step(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float* 
   rc = backward(ctx, mlp, params, batch, grads, stream);
   if (rc) return rc;
   return sugg_mlp_adam(ctx, mlp, params, grads, m, v, step, lr, 0.9f, 0.999f, 1e-8f, stream);
+}
+
+int32_t sugg_mlp_infer(sugg_ctx* ctx, sugg_mlp* mlp, const float* x, int32_t batch, float* y, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!x || !y) return ctx->fail(SUGG_E_ARG, "null argument");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  return mlp_infer(ctx, mlp, x, batch, y, stream);
+}
+
+int32_t sugg_mlp_infer_rank(sugg_ctx* ctx, sugg_mlp* mlp, const float* x, int32_t batch, int32_t skip, int32_t n,
+                            float tau, float* y, int32_t* idx, float* score, int32_t* count, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!mlp || mlp->ctx != ctx) return ctx->fail(SUGG_E_ARG, "mlp missing or from another context");
+  if (!mlp->frozen) return ctx->fail(SUGG_E_STATE, "mlp has no frozen parameters (sugg_mlp_freeze)");
+  if (batch < 1 || batch > mlp->bm) return ctx->fail(SUGG_E_SHAPE, "batch %d outside [1, %d]", batch, mlp->bm);
+  if (!x || !idx || !score || !count) return ctx->fail(SUGG_E_ARG, "null argument");
+  if (n < 1 || n > SUGG_MAX_SUGGEST || skip < 0 || skip >= mlp->out || !std::isfinite(tau))
+    return ctx->fail(SUGG_E_ARG, "bad n, skip or tau");
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  return infer_rank(ctx, mlp, x, batch, skip, n, tau, y, idx, score, count, stream);
 }
 
 int32_t sugg_mlp_train_epoch(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float* grads, float* m, float* v,

@@ -236,11 +236,11 @@ template <typename T, int KT>
 __global__ void __launch_bounds__(256) rank_kernel(const T* __restrict__ scores,
                                                    const int64_t* __restrict__ seg_off, int nseg,
                                                    int skip, int n, T tau, int32_t* idx_out,
-                                                   T* score_out, int32_t* count_out) {
+                                                   T* score_out, int32_t* count_out, int64_t seg_len) {
   const int lane = threadIdx.x & 63;
   const int seg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (seg >= nseg) return;
-  const int64_t b0 = seg_off[seg], b1 = seg_off[seg + 1];
+  const int64_t b0 = seg_off ? seg_off[seg] : seg * seg_len, b1 = seg_off ? seg_off[seg + 1] : b0 + seg_len;
   const int64_t len = b1 - b0;
   Entry<T> lst[KT];
 #pragma unroll
@@ -260,16 +260,16 @@ __global__ void __launch_bounds__(256) rank_kernel(const T* __restrict__ scores,
 
 template <typename T>
 hipError_t launch_rank(const T* scores, const int64_t* seg_off, int32_t nseg, int32_t skip_head, int32_t n,
-                       T tau, int32_t* idx_out, T* score_out, int32_t* count_out, hipStream_t s) {
+                       T tau, int32_t* idx_out, T* score_out, int32_t* count_out, hipStream_t s, int64_t seg_len) {
   if (nseg <= 0) return hipSuccess;
   const int blocks = (nseg + 3) / 4;
   (void)hipGetLastError();  // report only this launch's status
   if (n <= 4)
     hipLaunchKernelGGL((rank_kernel<T, 4>), dim3(blocks), dim3(256), 0, s, scores, seg_off, nseg, skip_head,
-                       n, tau, idx_out, score_out, count_out);
+                       n, tau, idx_out, score_out, count_out, seg_len);
   else
     hipLaunchKernelGGL((rank_kernel<T, 8>), dim3(blocks), dim3(256), 0, s, scores, seg_off, nseg, skip_head,
-                       n, tau, idx_out, score_out, count_out);
+                       n, tau, idx_out, score_out, count_out, seg_len);
   return hipGetLastError();
 }
 
@@ -390,7 +390,7 @@ hipError_t launch_confirm(int32_t K, int32_t n, int32_t* idx, float* plain, cons
   template hipError_t launch_zfeat64<T>(const T*, const T*, int64_t, int32_t, const double*,              \
                                         const double*, double*, double*, hipStream_t);                    \
   template hipError_t launch_rank<T>(const T*, const int64_t*, int32_t, int32_t, int32_t, T, int32_t*, T*, \
-                                     int32_t*, hipStream_t);                                              \
+                                     int32_t*, hipStream_t, int64_t);                                     \
   template hipError_t launch_band<T>(const T*, const int64_t*, int32_t, int32_t, const int32_t*,         \
                                      const int32_t*, int32_t, double, int32_t, int32_t*, T*, int32_t*,    \
                                      hipStream_t);

@@ -136,6 +136,29 @@ class MLP:
                                                         _ptr(target), x.shape[0], _ptr(self.loss), _stream()))
         return self.loss
 
+    def infer(self, x, y=None):
+        """Inference with the frozen parameters (``freeze`` first)."""
+        self._check_x(x, self.in_)
+        if y is None:
+            y = torch.empty((x.shape[0], self.out), device=self.ctx.device)
+        A.check(self.ctx.h, A.lib().sugg_mlp_infer(self.ctx.h, self.h, _ptr(x), x.shape[0], _ptr(y), _stream()))
+        return y
+
+    def infer_rank(self, x, n: int = 3, tau: float = 0.0, skip: int = 1, y=None, out=None):
+        """Inference with the frozen parameters and each row's top n outputs
+        above tau (columns >= skip): returns (idx, score, count), written into
+        ``out`` when given; the outputs themselves into y when given."""
+        self._check_x(x, self.in_)
+        B = x.shape[0]
+        if out is None:
+            out = (torch.empty((B, n), dtype=torch.int32, device=self.ctx.device),
+                   torch.empty((B, n), device=self.ctx.device),
+                   torch.empty(B, dtype=torch.int32, device=self.ctx.device))
+        idx, sc, cnt = out
+        A.check(self.ctx.h, A.lib().sugg_mlp_infer_rank(self.ctx.h, self.h, _ptr(x), B, skip, n, float(tau), _ptr(y),
+                                                        _ptr(idx), _ptr(sc), _ptr(cnt), _stream()))
+        return idx, sc, cnt
+
     def train_epoch(self, X, Y, perm, batch: int, lr=1e-3):
         """len(perm) // batch training steps in one library call over the
         mini-batches X[perm[s*batch:(s+1)*batch]] (gathered on the device);

@@ -124,10 +124,10 @@ def test_forward_at_benchmark_batches(S, ctx, B):
     err = rel(y.cpu().numpy(), yo)
     print(f"batch {B}: max element error {err:.2e}")
     assert err < BF16_RTOL
-    # the hidden layers ran instances without bounds checks: 128 x 64 tiles
-    # with K stages of 128 at 4096 kernels, 128 x 128 tiles with K stages of
-    # 32 at 65,536
-    assert info[0, 3] > 0 and info[1, 3] > 0
+    # every layer ran instances without bounds checks: 128 x 64 tiles with
+    # K stages of 128 at 4096 kernels, 128 x 128 tiles with K stages of 32
+    # for the hidden layers at 65,536
+    assert info[0, 3] > 0 and info[1, 3] > 0 and info[2, 3] > 0
     if B == 65536:
         assert info[0].tolist() == [128, 128, 1, 32] and info[1].tolist() == [128, 128, 1, 32]
     else:
@@ -238,6 +238,38 @@ def test_epoch_call_equals_steps_on_gathered_batches(S, ctx, dims, n, batch):
     plain.sync(ctx)   # the error was reported once
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("out,n,tau", [(64, 3, 0.02), (128, 8, 0.0), (256, 3, 0.02), (64, 5, 0.3)])
+def test_infer_rank_equals_infer_then_rank(S, ctx, out, n, tau):
+    """Frozen inference with Tier 3 in the output layer's epilogue (outputs
+    of 64 or 128 columns; the row ranking kernel for wider ones) against
+    inference followed by sugg_rank_suggest: same outputs, same lists, on a
+    batch that is not a whole number of tiles."""
+    plain, sur = S
+    B = 4999
+    mlp = sur.MLP(ctx, 128, 512, out, max_batch=B, seed=31)
+    rng = np.random.default_rng(32)
+    x = torch.tensor(rng.normal(size=(B, 128)), dtype=torch.float32, device="cuda")
+    mlp.freeze()
+    y = mlp.infer(x)
+    y_fwd = mlp(x)                      # the same parameters through forward
+    y2 = torch.empty_like(y)
+    idx, sc, cnt = mlp.infer_rank(x, n=n, tau=tau, skip=1, y=y2)
+    idx0, sc0, cnt0 = mlp.infer_rank(x, n=n, tau=tau, skip=1)   # without the outputs
+    seg = torch.arange(0, B + 1, dtype=torch.int64, device="cuda") * out
+    ri, rs, rc = plain.rank_suggest(ctx, y.view(-1), seg, n=n, tau=tau, skip_head=1)
+    plain.sync(ctx)
+    assert torch.equal(y, y2) and torch.equal(y, y_fwd)
+    for a, b, c in ((idx, sc, cnt), (idx0, sc0, cnt0)):
+        assert torch.equal(a, ri) and torch.equal(c, rc)
+        assert torch.equal(torch.nan_to_num(b, nan=-7.0), torch.nan_to_num(rs, nan=-7.0))
+    if tau >= 0.3:
+        assert int(rc.min()) < n   # short lists where tau bites
+    info = launch_info(mlp)
+    if out <= 128:   # the ranking epilogue: one tile row holds a whole output row
+        assert info[2, 0] == 128 and info[2, 1] == out
+    mlp.close()
 
 
 def test_trained_surrogate_gains_over_baseline_only_method(S, ctx):
