@@ -804,11 +804,12 @@ def surrogate_extra(G, dev, no_cpu=False):
     def plain_pass():
         G.suggest(ctx, plan, counters, cycles, out=outp)
 
+    sout = {"idx": outs[0], "score": outs[1], "count": outs[2], "table": None}
+
     def sur_pass():
-        # Tier 1 of the baseline versions, the network with Tier 3 in its
-        # output layer's epilogue (the table stays on chip)
-        zz = G.load_features(ctx, plan, counters, cycles, baseline=True)
-        return inf.infer_rank(zz, n=n, tau=G.TAU, skip=1, out=outs)
+        # one call: Tier 1 of the baseline versions in BF16, the network with
+        # Tier 3 in its output layer's epilogue (the table stays on chip)
+        return G.surrogate_suggest(ctx, plan, inf, counters, cycles, out=sout)
 
     def timed(fn, reps=20):
         for _ in range(3):

@@ -266,6 +266,20 @@ SUGG_API int32_t sugg_predict_allpaths(sugg_ctx* ctx, const sugg_plan* plan, con
 SUGG_API int32_t sugg_greedy(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, const void* cycles,
                              int32_t* path_out, int32_t* steps_out, void* gain_out, hipStream_t stream);
 
+/* The surrogate's suggestions for a batch whose kernels all have one B
+ * (FP32 plan; mlp frozen, in = E, out = 2^B, max batch >= K): Tier 1 of each
+ * kernel's baseline version (version 0) with the fitted model's column
+ * statistics, rounded to BF16 as the network's input, the network, and
+ * Tier 3 over each kernel's subsets S >= 1 (n and tau of the context) as in
+ * sugg_mlp_infer_rank; table_out (nullable) [K x 2^B] receives the
+ * network's whole table.  idx_out [K x n] holds subsets S (bitmasks of the
+ * kernel's local optimisation bits), as sugg_suggest.  Same lists as
+ * sugg_load_features (baseline rows) + sugg_mlp_infer_rank (skip 1).  A bad
+ * baseline counter is reported by the next sugg_sync. */
+SUGG_API int32_t sugg_surrogate_suggest(sugg_ctx* ctx, const sugg_plan* plan, sugg_mlp* mlp, const void* counters,
+                                        const void* cycles, void* table_out, int32_t* idx_out, void* score_out,
+                                        int32_t* count_out, hipStream_t stream);
+
 /* One serving query, every step enqueued on the stream (no host wait): for
  * a plan whose K kernels all have B optimisations (FP32), a frozen surrogate
  * mapping E features to 2^B log-speedups (K <= its max batch):

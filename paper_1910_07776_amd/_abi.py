@@ -99,6 +99,7 @@ SIGNATURES = {
     "sugg_mlp_backward": (_I32, [_P, _P, _P, _P, _I32, _P, _P]),
     "sugg_mlp_adam": (_I32, [_P, _P, _P, _P, _P, _P, _I32, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
     "sugg_mlp_train_step": (_I32, [_P, _P, _P, _P, _P, _P, _I32, C.c_float, _P, _P, _I32, _P, _P]),
+    "sugg_surrogate_suggest": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "sugg_mlp_infer": (_I32, [_P, _P, _P, _I32, _P, _P]),
     "sugg_mlp_infer_rank": (_I32, [_P, _P, _P, _I32, _I32, _I32, C.c_float, _P, _P, _P, _P, _P]),
     "sugg_mlp_train_epoch": (_I32, [_P, _P, _P, _P, _P, _P, _I32, C.c_float, _P, _P, _I64, _P, _I32, _I32, _P,

@@ -855,6 +855,34 @@ int32_t sugg_greedy(sugg_ctx* ctx, const sugg_plan* plan, const void* counters, 
                            nullptr, nullptr, path_out, steps_out, (double*)gain_out, stream);
 }
 
+int32_t sugg_surrogate_suggest(sugg_ctx* ctx, const sugg_plan* plan, sugg_mlp* mlp, const void* counters,
+                               const void* cycles, void* table_out, int32_t* idx_out, void* score_out,
+                               int32_t* count_out, hipStream_t stream) {
+  if (!ctx) return SUGG_E_ARG;
+  if (!plan || plan->ctx != ctx) return ctx->fail(SUGG_E_ARG, "plan missing or from another context");
+  if (plan->dtype != SUGG_F32) return ctx->fail(SUGG_E_ARG, "the surrogate runs on FP32 plans");
+  if (plan->K == 0) return SUGG_OK;
+  if (plan->uni_B < 0) return ctx->fail(SUGG_E_SHAPE, "the surrogate needs one B for all kernels");
+  if (!counters || !cycles || !idx_out || !score_out || !count_out) return ctx->fail(SUGG_E_ARG, "null argument");
+  if (!mlp) return ctx->fail(SUGG_E_ARG, "null mlp");
+  int in = 0, out = 0, bm = 0;
+  mlp_dims(mlp, &in, &out, &bm);
+  const int B = plan->uni_B, K = plan->K;
+  if (in != plan->E || out != (1 << B)) return ctx->fail(SUGG_E_SHAPE, "mlp %d -> %d does not map E=%d to 2^%d", in, out, plan->E, B);
+  if (K > bm) return ctx->fail(SUGG_E_SHAPE, "%d kernels above the mlp's batch %d", K, bm);
+  int rc = check_model_for(ctx, plan);
+  if (rc) return rc;
+  if (!device_ok(ctx)) return ctx->fail(SUGG_E_HIP, "cannot select device");
+  // Tier 1 of each kernel's baseline version, rounded to BF16 into the
+  // network's input, then the network with Tier 3 in its output layer
+  rc = ctx->hip(launch_standardize_rows_bf16((const float*)counters, (const float*)cycles, plan->d_row_off, K,
+                                             plan->E, ctx->mu32, ctx->isg32, mlp_input(mlp), in, ctx->d_status, stream),
+                "surrogate: baseline features");
+  if (rc) return rc;
+  return mlp_infer_rank_input(ctx, mlp, K, 1, ctx->params.n_suggest, (float)ctx->params.tau, (float*)table_out,
+                              idx_out, (float*)score_out, count_out, stream);
+}
+
 int32_t sugg_serve_query(sugg_ctx* ctx, const sugg_plan* plan, sugg_mlp* mlp, const void* counters,
                          const void* cycles, double tol, double band, int32_t cap, int32_t* idx_out, void* score_out,
                          int32_t* count_out, int32_t* flag_out, hipStream_t stream) {

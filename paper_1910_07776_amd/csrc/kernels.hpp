@@ -184,6 +184,10 @@ hipError_t launch_standardize(const T* counters, const T* cycles, int64_t N, int
 template <typename T>
 hipError_t launch_standardize_rows(const T* counters, const T* cycles, const int64_t* rows, int64_t nrows, int32_t E,
                                    const T* mu, const T* isg, T* z, int32_t* status, hipStream_t s);
+// the same values rounded to BF16, row i at z + i * ldz (the surrogate's input)
+hipError_t launch_standardize_rows_bf16(const float* counters, const float* cycles, const int64_t* rows, int64_t nrows,
+                                        int32_t E, const float* mu, const float* isg, __bf16* z, int32_t ldz,
+                                        int32_t* status, hipStream_t s);
 
 // FP64 z and ln(cycles) for the regression.
 template <typename T>

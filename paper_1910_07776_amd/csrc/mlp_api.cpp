@@ -193,12 +193,13 @@ namespace {
 // Inference and each row's top n of the outputs in columns >= skip above
 // tau: the output layer's epilogue ranks where the output width is 64 or
 // 128 (a tile row), otherwise the outputs go through the row ranking kernel.
+// x == nullptr: the input is already in the BF16 input buffer (mlp_input)
 int infer_rank(sugg_ctx* ctx, sugg_mlp* m, const float* x, int B, int skip, int n, float tau, float* y,
                int32_t* idx, float* score, int32_t* count, hipStream_t s) {
   const int in = m->in, hid = m->hid, out = m->out;
   hipError_t e = hipSuccess;
   if (!m->packed_frozen) e = pack_weights(m, m->frozen, s);
-  if (e == hipSuccess) e = launch_pack(x, B, in, m->xb, in, nullptr, m->bm, s);
+  if (e == hipSuccess && x) e = launch_pack(x, B, in, m->xb, in, nullptr, m->bm, s);
   if (e != hipSuccess) return ctx->hip(e, "mlp pack");
   const float* params = m->frozen;
   GemmArgs g = gemm(m->xb, in, m->w1, in, B, hid, in);
@@ -244,6 +245,14 @@ void mlp_dims(const sugg_mlp* m, int* in, int* out, int* max_batch) {
   *in = m->in;
   *out = m->out;
   *max_batch = m->bm;
+}
+
+__bf16* mlp_input(sugg_mlp* m) { return m->xb; }
+
+int mlp_infer_rank_input(sugg_ctx* ctx, sugg_mlp* m, int B, int skip, int n, float tau, float* y, int32_t* idx,
+                         float* score, int32_t* count, hipStream_t s) {
+  if (!m->frozen) return ctx->fail(SUGG_E_STATE, "mlp has no frozen parameters (sugg_mlp_freeze)");
+  return infer_rank(ctx, m, nullptr, B, skip, n, tau, y, idx, score, count, s);
 }
 
 extern "C" {

@@ -39,6 +39,11 @@ int load_features_core(sugg_ctx* ctx, const sugg_plan* plan, const void* counter
 // array on the current device (noalloc.hip); SUGG_OK or SUGG_E_HIP
 int noalloc_scratch_setup(int device);
 void mlp_dims(const sugg_mlp* m, int* in, int* out, int* max_batch);
+// the BF16 input buffer of the mlp ([max_batch x in], row stride in), and
+// frozen inference with ranking (as sugg_mlp_infer_rank) from what it holds
+__bf16* mlp_input(sugg_mlp* m);
+int mlp_infer_rank_input(sugg_ctx* ctx, sugg_mlp* m, int B, int skip, int n, float tau, float* y, int32_t* idx,
+                         float* score, int32_t* count, hipStream_t s);
 
 struct sugg_plan {
   sugg_ctx* ctx = nullptr;   // identity only: never dereferenced after creation

@@ -166,37 +166,53 @@ hipError_t launch_standardize(const T* counters, const T* cycles, int64_t N, int
 }
 
 // ---- standardised features of selected rows ------------------------------
-// z[i][j] for row rows[i] (the baseline versions of a batch: rows = row_off).
-template <typename T>
+// z[i][j] for row rows[i] (the baseline versions of a batch: rows = row_off),
+// in the output type TO (the plan dtype, or BF16 for the surrogate's input):
+// each 16-lane group takes one row at a time (ln of its cycle count once),
+// its lanes striding over the columns; the value is (x - mu) * isg with
+// x = ln c - ln cyc, rounded once to TO.
+template <typename T, typename TO>
 __global__ void standardize_rows_kernel(const T* __restrict__ c, const T* __restrict__ cyc,
                                         const int64_t* __restrict__ rows, int64_t nrows, int E,
-                                        const T* __restrict__ mu, const T* __restrict__ isg, T* __restrict__ z,
-                                        int32_t* status) {
-  const int64_t total = nrows * E;
+                                        const T* __restrict__ mu, const T* __restrict__ isg, TO* __restrict__ z,
+                                        int ldz, int32_t* status) {
+  const int l16 = threadIdx.x & 15;
+  const int64_t g0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4, ng = ((int64_t)gridDim.x * blockDim.x) >> 4;
   bool bad = false;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t q = i / E;
-    const int j = (int)(i - q * E);
+  for (int64_t q = g0; q < nrows; q += ng) {
     const int64_t r = rows[q];
-    const T x = dlog<T>(c[r * E + j]) - dlog<T>(cyc[r]);
-    bad |= !__builtin_isfinite(x);
-    z[i] = (x - mu[j]) * isg[j];
+    const T lc = dlog<T>(cyc[r]);
+    for (int j = l16; j < E; j += 16) {
+      const T x = dlog<T>(c[r * E + j]) - lc;
+      bad |= !__builtin_isfinite(x);
+      z[q * ldz + j] = (TO)((x - mu[j]) * isg[j]);
+    }
   }
   if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(status, (int)kStatusBadCounter);
+}
+
+template <typename T, typename TO>
+hipError_t launch_standardize_rows_t(const T* counters, const T* cycles, const int64_t* rows, int64_t nrows, int32_t E,
+                                     const T* mu, const T* isg, TO* z, int ldz, int32_t* status, hipStream_t s) {
+  if (nrows <= 0 || E <= 0) return hipSuccess;
+  int64_t blocks = (nrows + 15) / 16;   // 16 rows per workgroup of 256
+  if (blocks > 16384) blocks = 16384;
+  (void)hipGetLastError();  // report only this launch's status
+  hipLaunchKernelGGL((standardize_rows_kernel<T, TO>), dim3((unsigned)blocks), dim3(256), 0, s, counters, cycles,
+                     rows, nrows, (int)E, mu, isg, z, ldz, status);
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_standardize_rows(const T* counters, const T* cycles, const int64_t* rows, int64_t nrows, int32_t E,
                                    const T* mu, const T* isg, T* z, int32_t* status, hipStream_t s) {
-  const int64_t total = nrows * E;
-  if (total <= 0) return hipSuccess;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  (void)hipGetLastError();  // report only this launch's status
-  hipLaunchKernelGGL(standardize_rows_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, counters, cycles, rows,
-                     nrows, (int)E, mu, isg, z, status);
-  return hipGetLastError();
+  return launch_standardize_rows_t<T, T>(counters, cycles, rows, nrows, E, mu, isg, z, E, status, s);
+}
+
+hipError_t launch_standardize_rows_bf16(const float* counters, const float* cycles, const int64_t* rows, int64_t nrows,
+                                        int32_t E, const float* mu, const float* isg, __bf16* z, int32_t ldz,
+                                        int32_t* status, hipStream_t s) {
+  return launch_standardize_rows_t<float, __bf16>(counters, cycles, rows, nrows, E, mu, isg, z, ldz, status, s);
 }
 
 // ---- FP64 features for the regression ------------------------------------

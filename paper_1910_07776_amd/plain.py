@@ -233,6 +233,24 @@ def judge(ctx: Context, plan: Plan, counters, cycles, cand, out=None, ref=None, 
     return out
 
 
+def surrogate_suggest(ctx: Context, plan: Plan, mlp, counters, cycles, table: bool = False, out=None):
+    """The frozen surrogate's top-n subsets of every kernel of a uniform
+    batch in one library call (baseline features in BF16, the network,
+    Tier 3 in its output layer); returns (idx, score, count, table or None)."""
+    plan.check_inputs(counters, cycles)
+    n = ctx.params["n_suggest"]
+    K, V = plan.K, 1 << int(plan.Bmax)
+    if out is None:
+        out = {"idx": torch.empty((K, n), dtype=torch.int32, device=ctx.device),
+               "score": torch.empty((K, n), dtype=plan.dtype, device=ctx.device),
+               "count": torch.empty(K, dtype=torch.int32, device=ctx.device),
+               "table": torch.empty((K, V), dtype=plan.dtype, device=ctx.device) if table else None}
+    A.check(ctx.h, A.lib().sugg_surrogate_suggest(ctx.h, plan.h, mlp.h, _ptr(counters), _ptr(cycles),
+                                                  _ptr(out.get("table")), _ptr(out["idx"]), _ptr(out["score"]),
+                                                  _ptr(out["count"]), _stream()))
+    return out["idx"], out["score"], out["count"], out.get("table")
+
+
 def serve_query(ctx: Context, plan: Plan, mlp, counters, cycles, out, flag, tol: float = 0.1, band: float = 0.1,
                 cap: int = 16):
     """One serving query in a single call (surrogate, top-n, threshold band,

@@ -272,6 +272,33 @@ def test_infer_rank_equals_infer_then_rank(S, ctx, out, n, tau):
     mlp.close()
 
 
+def test_surrogate_suggest_in_one_call(S, ctx):
+    """sugg_surrogate_suggest (baseline features written in BF16 into the
+    network's input, the network, Tier 3 in its output layer) against
+    load_features (baseline rows) + infer_rank and infer: identical lists
+    and table."""
+    plain, sur = S
+    from synthgen import make_batch
+    from synthgen.torch_world import TorchWorld
+    tr = make_batch(41, range(9000, 9128), 128, 6)
+    plain.fit(ctx, plain.Plan(ctx, tr.nopts, tr.opt_ids, 128, 6), torch.from_numpy(tr.counters).cuda(),
+              torch.from_numpy(tr.cycles).cuda())
+    tw = TorchWorld(41, 128, 6)
+    K = 3001
+    c, cy, _ = tw.chunk(2, K)
+    p = plain.Plan(ctx, np.full(K, 6, np.int32), np.tile(np.arange(6, dtype=np.int32), K), 128, 6)
+    mlp = sur.MLP(ctx, 128, 512, 64, max_batch=K, seed=33).freeze()
+    idx, sc, cnt, table = plain.surrogate_suggest(ctx, p, mlp, c, cy, table=True)
+    zz = plain.load_features(ctx, p, c, cy, baseline=True)
+    ri, rs, rc = mlp.infer_rank(zz, n=3, tau=plain.TAU, skip=1)
+    y = mlp.infer(zz)
+    plain.sync(ctx)
+    assert torch.equal(idx, ri) and torch.equal(cnt, rc)
+    assert torch.equal(torch.nan_to_num(sc, nan=-7.0), torch.nan_to_num(rs, nan=-7.0))
+    assert torch.equal(table, y)
+    mlp.close()
+
+
 def test_trained_surrogate_gains_over_baseline_only_method(S, ctx):
     """What the trained network gains over the method without it: from the
     same input (a kernel's baseline profile only), the surrogate's speedup
