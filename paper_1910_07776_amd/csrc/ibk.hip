@@ -624,15 +624,17 @@ hipError_t launch_knn_kt(const IbkKnnArgs& a, int n_tiles, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Sample shares per query tile: enough workgroups for one full round of the
-// resident ones (occupancy of this kernel instance x compute units).
+// Sample shares per query tile.
 template <int EH, int KT>
 int split_kt(int n_tiles, int cus) {
-  int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(ibk_knn_kernel<EH, KT>),
-                                                   256, 0) != hipSuccess || per < 1)
-    per = 2;
-  return n_tiles > 0 ? std::min(8, std::max(1, (per * cus + n_tiles - 1) / n_tiles)) : 1;
+  // Eight sample shares per query tile.  Workgroups go to the eight XCDs in
+  // turn (workgroup w to XCD w mod 8) and workgroup w takes share w mod 8 of
+  // its tile, so every tile's share s runs on XCD s: the XCD's L2 serves one
+  // eighth of each optimisation's samples to all of that optimisation's
+  // tiles instead of every XCD streaming every sample from HBM.
+  (void)n_tiles;
+  (void)cus;
+  return 8;
 }
 
 int ibk_split(int Epad, int k, int n_tiles, int cus) {
