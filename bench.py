@@ -1020,6 +1020,18 @@ def serving_extra(G, dev, n_queries: int = 10000):
             stp = serve.run_loop(srv, qs, arr, plain_only=True)
             res["plain_only_same_trace"] = stp
             log(f"plain only, same trace: p50 {stp['p50_ms']:.3f} ms p99 {stp['p99_ms']:.3f} ms")
+            # run-to-run spread: three more runs of each, alternating
+            rep = {"surrogate_p99_ms": [st["p99_ms"]], "plain_only_p99_ms": [stp["p99_ms"]],
+                   "surrogate_p50_ms": [st["p50_ms"]], "plain_only_p50_ms": [stp["p50_ms"]]}
+            for _ in range(3):
+                a = serve.run_loop(srv, qs, arr)
+                b = serve.run_loop(srv, qs, arr, plain_only=True)
+                rep["surrogate_p99_ms"].append(a["p99_ms"])
+                rep["plain_only_p99_ms"].append(b["p99_ms"])
+                rep["surrogate_p50_ms"].append(a["p50_ms"])
+                rep["plain_only_p50_ms"].append(b["p50_ms"])
+            res["repeats_at_80pct"] = rep
+            log(f"80% p99 over 4 runs: surrogate {rep['surrogate_p99_ms']} plain {rep['plain_only_p99_ms']}")
     srv.close()
     for m in nets.values():
         m.close()

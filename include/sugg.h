@@ -284,8 +284,9 @@ SUGG_API int32_t sugg_surrogate_suggest(sugg_ctx* ctx, const sugg_plan* plan, su
  * a plan whose K kernels all have B optimisations (FP32), a frozen surrogate
  * mapping E features to 2^B log-speedups (K <= its max batch):
  *   1. each kernel's standardised baseline row (Tier 1, as sugg_load_features
- *      with SUGG_BASELINE), 2. the surrogate's table, 3. its top n_suggest
- *      above tau, 4. the threshold band of short lists (sugg_band_select, at
+ *      with SUGG_BASELINE, rounded to BF16 into the network's input), 2. the
+ *      surrogate's table, 3. its top n_suggest above tau (in the output
+ *      layer's epilogue where 2^B is 64 or 128), 4. the threshold band of short lists (sugg_band_select, at
  *      most cap subsets), 5. the judge of the listed and band subsets
  *      against the plain composed values, 6. Tier 3's threshold checked on
  *      the plain values (every listed subset above tau, no band subset

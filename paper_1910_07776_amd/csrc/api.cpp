@@ -914,8 +914,7 @@ int32_t sugg_serve_query(sugg_ctx* ctx, const sugg_plan* plan, sugg_mlp* mlp, co
     w.cap = cap;
     std::vector<int64_t> seg(K + 1);
     for (int k = 0; k <= K; ++k) seg[k] = (int64_t)k << B;
-    hipError_t e = hipMalloc((void**)&w.z0, sizeof(float) * (size_t)K * plan->E);
-    if (e == hipSuccess) e = hipMalloc((void**)&w.ys, sizeof(float) * ((size_t)K << B));
+    hipError_t e = hipMalloc((void**)&w.ys, sizeof(float) * ((size_t)K << B));
     if (e == hipSuccess) e = hipMalloc((void**)&w.sc, sizeof(float) * (size_t)K * n);
     if (e == hipSuccess) e = hipMalloc((void**)&w.br, sizeof(float) * (size_t)K * cap);
     if (e == hipSuccess) e = hipMalloc((void**)&w.bout, sizeof(float) * (size_t)K * cap);
@@ -930,14 +929,14 @@ int32_t sugg_serve_query(sugg_ctx* ctx, const sugg_plan* plan, sugg_mlp* mlp, co
   ServeWs& w = *p->serve;
   const float* c = (const float*)counters;
   const float* cy = (const float*)cycles;
-  // 1. standardised baseline rows, 2. the surrogate's tables
-  rc = ctx->hip(launch_standardize_rows<float>(c, cy, p->d_row_off, K, p->E, ctx->mu32, ctx->isg32, w.z0,
-                                               ctx->d_status, stream), "serve: baseline features");
-  if (!rc) rc = mlp_infer(ctx, mlp, w.z0, K, w.ys, stream);
-  // 3. its top n, 4. the threshold band of short lists (overflow flags)
-  if (!rc)
-    rc = ctx->hip(launch_rank<float>(w.ys, w.seg, K, 1, n, (float)ctx->params.tau, idx_out, w.sc, count_out, stream),
-                  "serve: rank");
+  // 1. standardised baseline rows, rounded to BF16 into the network's input;
+  // 2. the surrogate's tables and 3. their top n (the output layer ranks in
+  // its epilogue where the table is 64 or 128 wide)
+  rc = ctx->hip(launch_standardize_rows_bf16(c, cy, p->d_row_off, K, p->E, ctx->mu32, ctx->isg32, mlp_input(mlp),
+                                             in, ctx->d_status, stream),
+                "serve: baseline features");
+  if (!rc) rc = mlp_infer_rank_input(ctx, mlp, K, 1, n, (float)ctx->params.tau, w.ys, idx_out, w.sc, count_out, stream);
+  // 4. the threshold band of short lists (overflow flags)
   if (!rc)
     rc = ctx->hip(launch_band<float>(w.ys, w.seg, K, 1, idx_out, count_out, n, ctx->params.tau - band, cap, w.bc,
                                      w.br, flag_out, stream), "serve: band");

@@ -21,11 +21,11 @@ struct sugg_graph {
 // Workspace of a plan's serving queries (sugg_serve_query), built on first use.
 struct ServeWs {
   int cap = 0;
-  float *z0 = nullptr, *ys = nullptr, *sc = nullptr, *br = nullptr, *bout = nullptr;
+  float *ys = nullptr, *sc = nullptr, *br = nullptr, *bout = nullptr;
   int32_t* bc = nullptr;
   int64_t* seg = nullptr;
   ~ServeWs() {
-    dfree(z0); dfree(ys); dfree(sc); dfree(br); dfree(bout); dfree(bc); dfree(seg);
+    dfree(ys); dfree(sc); dfree(br); dfree(bout); dfree(bc); dfree(seg);
   }
 };
 
