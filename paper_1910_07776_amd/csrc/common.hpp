@@ -65,9 +65,17 @@ struct Entry {
   int32_t s;
 };
 
+// Without short-circuit evaluation: branches there turn the selections of
+// the callers into selections of addresses, which keeps the lists out of
+// registers (in private memory).
+template <typename T>
+__device__ __forceinline__ bool better_vs(T av, int32_t as, T bv, int32_t bs) {
+  return (as >= 0) & ((bs < 0) | (av > bv) | ((av == bv) & (as < bs)));
+}
+
 template <typename T>
 __device__ __forceinline__ bool better(const Entry<T>& a, const Entry<T>& b) {
-  return a.s >= 0 && (b.s < 0 || a.v > b.v || (a.v == b.v && a.s < b.s));
+  return better_vs(a.v, a.s, b.v, b.s);
 }
 
 template <typename T>
@@ -78,13 +86,18 @@ __device__ __forceinline__ Entry<T> empty_entry() {
   return e;
 }
 
+// Selections member by member on values read first (a conditional copy of
+// the whole struct is lowered, for Entry<double>, through private memory).
 template <typename T>
 __device__ __forceinline__ void cswap(Entry<T>& a, Entry<T>& b) {
   // after: a is the better of the two
-  bool sw = better(b, a);
-  Entry<T> t = a;
-  a = sw ? b : a;
-  b = sw ? t : b;
+  const T av = a.v, bv = b.v;
+  const int32_t as = a.s, bs = b.s;
+  const bool sw = better_vs(bv, bs, av, as);
+  a.v = sw ? bv : av;
+  a.s = sw ? bs : as;
+  b.v = sw ? av : bv;
+  b.s = sw ? as : bs;
 }
 
 // Insert e into a best-first list of KT entries, dropping the worst.
@@ -100,8 +113,11 @@ template <typename T, int KT>
 __device__ __forceinline__ void list_merge(Entry<T> (&A)[KT], const Entry<T> (&B)[KT]) {
 #pragma unroll
   for (int i = 0; i < KT; ++i) {
-    Entry<T> b = B[KT - 1 - i];
-    if (better(b, A[i])) A[i] = b;
+    const T av = A[i].v, bv = B[KT - 1 - i].v;
+    const int32_t as = A[i].s, bs = B[KT - 1 - i].s;
+    const bool tb = better_vs(bv, bs, av, as);
+    A[i].v = tb ? bv : av;
+    A[i].s = tb ? bs : as;
   }
 #pragma unroll
   for (int d = KT / 2; d >= 1; d >>= 1) {

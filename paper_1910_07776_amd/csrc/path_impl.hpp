@@ -39,13 +39,55 @@ struct alignas(sizeof(T) * VW) VecN {
   T v[VW];
 };
 
+// Natural log in FP64 without the library's double-double steps (a third of
+// its instructions; the prediction kernels take one per counter).  With
+// x = 2^e m, m in [sqrt(1/2), sqrt(2)): ln x = e ln 2 + 2 atanh(s),
+// s = (m - 1) / (m + 1), |s| <= 0.1716, and 2 atanh(s) = 2 s (1 + s^2/3 + ...
+// + s^18/19) (the first omitted term is below 2.5e-17 of the sum).  s is the
+// quotient by a Newton-refined hardware reciprocal with a residual step that
+// also takes in the rounding of m + 1; ln 2 is split so that e times its high
+// part is exact.  Error within 1.2 units in the last place (against long
+// double over 2e7 arguments, 1e-300..1e300 and around 1); 0 gives -inf, a
+// negative or NaN argument NaN, +inf +inf; subnormals are exact inputs.
+__device__ __forceinline__ double flog64(double x) {
+  double m = __builtin_amdgcn_frexp_mant(x);   // [0.5, 1)
+  int e = __builtin_amdgcn_frexp_exp(x);
+  const bool lo = m < 0.70710678118654752440;
+  m = lo ? m * 2.0 : m;
+  e = lo ? e - 1 : e;
+  const double n = m - 1.0;          // exact
+  const double d = m + 1.0;
+  const double dl = m - (d - 1.0);   // the rounding error of d, exact
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  double s = n * r;
+  s = fma(fma(-s, dl, fma(-s, d, n)), r, s);
+  const double s2 = s * s;
+  double p = 1.0 / 19;
+  p = fma(p, s2, 1.0 / 17);
+  p = fma(p, s2, 1.0 / 15);
+  p = fma(p, s2, 1.0 / 13);
+  p = fma(p, s2, 1.0 / 11);
+  p = fma(p, s2, 1.0 / 9);
+  p = fma(p, s2, 1.0 / 7);
+  p = fma(p, s2, 1.0 / 5);
+  p = fma(p, s2, 1.0 / 3);
+  const double t = 2.0 * s;
+  const double ed = (double)e;
+  const double tail = fma(t * s2, p, ed * 0x1.9ef35793c7673p-41);
+  const double y = fma(ed, 0x1.62e42fefa2000p-1, t + tail);
+  const double inf = __builtin_huge_val();
+  return (x > 0.0 && x < inf) ? y : (x == 0.0 ? -inf : (x == inf ? inf : __builtin_nan("")));
+}
+
 // Natural log for FP64; base-2 hardware log for FP32 (callers scale by ln 2).
 template <typename T> __device__ __forceinline__ T dlog(T x);
 template <> __device__ __forceinline__ float dlog<float>(float x) { return logf(x); }
 template <> __device__ __forceinline__ double dlog<double>(double x) { return log(x); }
 template <typename T> __device__ __forceinline__ T feat_log(T x);
 template <> __device__ __forceinline__ float feat_log<float>(float x) { return __builtin_amdgcn_logf(x); }
-template <> __device__ __forceinline__ double feat_log<double>(double x) { return log(x); }
+template <> __device__ __forceinline__ double feat_log<double>(double x) { return flog64(x); }
 template <typename T> __device__ __forceinline__ T feat_log_unit();
 template <> __device__ __forceinline__ float feat_log_unit<float>() { return 0.69314718055994530942f; }
 template <> __device__ __forceinline__ double feat_log_unit<double>() { return 1.0; }
