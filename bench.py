@@ -630,8 +630,8 @@ def _depth(t):
 def ragged_headline(G, ctx, dev, steps, warm, no_cpu=False):
     """The ragged batch: 16,384 kernels with 4-10 of 10 optimisations (B
     uniform, ids a sorted random subset), 4,821,136 versions x 128 FP32
-    events (2.5 GB), one persistent launch per pass replayed from a captured
-    hipGraph; the model is fitted on 16,384 other kernels of the same world.
+    events (2.5 GB), one launch of the autotuned scoring kernel per pass
+    replayed from a captured hipGraph; the model is fitted on 16,384 other kernels of the same world.
     warm untimed passes, then exactly ``steps`` timed ones."""
     import torch
     from synthgen import make_batch

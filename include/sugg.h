@@ -127,9 +127,11 @@ SUGG_API int32_t sugg_plan_get_items(const sugg_plan* plan);
  * 1024 rows, waves 2, 4, 8 x unroll 1, 2, 4, then the streaming form with
  * unroll -1, -2, -4 (12 shapes per size, in that order), then the split form
  * where the plan has one (with the plan's item size); reps timed passes each
- * after one warm-up; keeps the fastest in the plan.  times_ms (nullable, at least
- * SUGG_TUNE_CANDIDATES floats, times_cap its length) receives the mean pass
- * time of each candidate (-1 for one the plan cannot run: an item size whose
+ * after one warm-up; the four fastest are then timed again in two rounds of
+ * 2 reps passes each, and the best of those is kept in the plan.  times_ms
+ * (nullable, at least SUGG_TUNE_CANDIDATES floats, times_cap its length)
+ * receives the mean pass time of each candidate, the second timing for the
+ * four finalists (-1 for one the plan cannot run: an item size whose
  * workspace exceeds LDS, a split form it does not have).  Needs a fitted
  * model; allocates and frees temporary outputs; synchronises the stream. */
 #define SUGG_TUNE_CANDIDATES 61

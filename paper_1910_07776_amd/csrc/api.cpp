@@ -122,18 +122,26 @@ hipError_t plan_items(sugg_plan* p, int target) {
     for (int b = 0; b < p->nopts[k]; ++b) r.opt[b] = (uint8_t)p->opt_ids[p->opt_off[k] + b];
   }
   // streaming form: consecutive whole kernels in memory order, a chunk closed
-  // before it would pass `target` rows (a larger kernel is a chunk alone)
+  // before it would pass `target` rows (a larger kernel is a chunk alone).
+  // The kernels of the last tenth of the rows go into chunks of a quarter of
+  // the target, and the chunks are dispatched largest first: the workgroups
+  // that start last are then short, and the device stays nearly full until
+  // the end of the launch (with equal chunks throughout, the last round of
+  // workgroups drained over most of a chunk's lifetime).
   std::vector<Chunk> chunks;
   std::vector<CRec> crec(K);
   p->chunk_max_rows = 1;
   p->chunk_max_nk = 1;
+  const int64_t n_rows = K > 0 ? p->row_off[K] : 0;
+  const int tail_target = std::max(target / 4, 128);
   for (int k = 0; k < K;) {
     Chunk c;
     std::memset(&c, 0, sizeof c);
     c.row0 = p->row_off[k];
     c.k0 = k;
+    const int64_t cap = 10 * c.row0 >= 9 * n_rows ? std::min(target, tail_target) : target;
     int64_t rows = 0;
-    while (k < K && (c.nk == 0 || rows + ((int64_t)1 << p->nopts[k]) <= target)) {
+    while (k < K && (c.nk == 0 || rows + ((int64_t)1 << p->nopts[k]) <= cap)) {
       CRec& r = crec[k];
       std::memset(&r, 0, sizeof r);
       r.rel = (int16_t)rows;   // < max(target, 2^SUGG_MAX_OPTS) <= 4096
@@ -148,6 +156,7 @@ hipError_t plan_items(sugg_plan* p, int target) {
     p->chunk_max_nk = std::max(p->chunk_max_nk, c.nk);
     chunks.push_back(c);
   }
+  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& x, const Chunk& y) { return x.R > y.R; });
   p->n_chunks = (int)chunks.size();
   dfree(p->d_items);
   dfree(p->d_recs);
@@ -328,6 +337,7 @@ constexpr size_t kLdsPerWorkgroup = 160 * 1024;
 constexpr int kTuneItems[] = {64, 128, 256, 512, 1024};
 constexpr int kTuneWaves[] = {2, 4, 8};
 constexpr int kTuneUnroll[] = {1, 2, 4};
+constexpr int kTuneFinalists = 4;   // candidates timed again before the choice
 static_assert(5 * (3 * 3 + 3) + 1 == SUGG_TUNE_CANDIDATES, "autotuner candidate count");
 
 template <typename T>
@@ -1029,6 +1039,30 @@ int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, cons
   int best_items = keep_items;
   float best_ms = 1e30f;
   int ci = 0;
+  struct Cand {
+    int ci, items;
+    PathLaunch cfg;
+    float ms;
+  };
+  std::vector<Cand> cands;   // every candidate that ran
+  // mean time of `passes` passes of the current shape (after one warm-up)
+  auto time_shape = [&](int passes, float& ms) {
+    ms = 0.f;
+    for (int rep = -1; rep < passes && e == hipSuccess; ++rep) {   // rep -1 warms up
+      if (rep == 0) e = hipEventRecord(e0, stream);
+      if (e != hipSuccess) break;
+      rc = plan->dtype == SUGG_F32
+               ? run_path<float>(ctx, plan, (const float*)counters, (const float*)cycles, nullptr, (float*)table,
+                                 (int32_t*)idx, (float*)score, (int32_t*)count, n, stream)
+               : run_path<double>(ctx, plan, (const double*)counters, (const double*)cycles, nullptr,
+                                  (double*)table, (int32_t*)idx, (double*)score, (int32_t*)count, n, stream);
+      if (rc) e = hipErrorUnknown;
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    ms /= passes;
+  };
   std::vector<std::pair<int, int>> shapes;   // (waves, unroll): fused shapes, then the streaming form
   for (int w : kTuneWaves)
     for (int u : kTuneUnroll) shapes.push_back({w, u});
@@ -1049,26 +1083,9 @@ int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, cons
         continue;
       }
       float ms = 0.f;
-      for (int rep = -1; rep < reps && e == hipSuccess; ++rep) {   // rep -1 warms up
-        if (rep == 0) e = hipEventRecord(e0, stream);
-        if (e != hipSuccess) break;
-        rc = plan->dtype == SUGG_F32
-                 ? run_path<float>(ctx, plan, (const float*)counters, (const float*)cycles, nullptr, (float*)table,
-                                   (int32_t*)idx, (float*)score, (int32_t*)count, n, stream)
-                 : run_path<double>(ctx, plan, (const double*)counters, (const double*)cycles, nullptr,
-                                    (double*)table, (int32_t*)idx, (double*)score, (int32_t*)count, n, stream);
-        if (rc) e = hipErrorUnknown;
-      }
-      if (e == hipSuccess) e = hipEventRecord(e1, stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      ms /= reps;
+      time_shape(reps, ms);
       if (times_ms) times_ms[ci] = ms;
-      if (e == hipSuccess && ms < best_ms) {
-        best_ms = ms;
-        best = plan->cfg;
-        best_items = plan->item_rows;
-      }
+      if (e == hipSuccess) cands.push_back({ci, plan->item_rows, plan->cfg, ms});
       ++ci;
     }
   // the split form (equal kernels of at most 64 versions): one more candidate
@@ -1077,25 +1094,31 @@ int32_t sugg_autotune(sugg_ctx* ctx, sugg_plan* plan, const void* counters, cons
   if (e == hipSuccess && plan->split_ok()) {
     plan->cfg = PathLaunch{4, 0, 0};
     float ms = 0.f;
-    for (int rep = -1; rep < reps && e == hipSuccess; ++rep) {
-      if (rep == 0) e = hipEventRecord(e0, stream);
-      if (e != hipSuccess) break;
-      rc = plan->dtype == SUGG_F32
-               ? run_path<float>(ctx, plan, (const float*)counters, (const float*)cycles, nullptr, (float*)table,
-                                 (int32_t*)idx, (float*)score, (int32_t*)count, n, stream)
-               : run_path<double>(ctx, plan, (const double*)counters, (const double*)cycles, nullptr,
-                                  (double*)table, (int32_t*)idx, (double*)score, (int32_t*)count, n, stream);
-      if (rc) e = hipErrorUnknown;
-    }
-    if (e == hipSuccess) e = hipEventRecord(e1, stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    ms /= reps;
+    time_shape(reps, ms);
     if (times_ms) times_ms[ci] = ms;
-    if (e == hipSuccess && ms < best_ms) {
-      best_ms = ms;
-      best = plan->cfg;
-      best_items = plan->item_rows;
+    if (e == hipSuccess) cands.push_back({ci, plan->item_rows, plan->cfg, ms});
+  }
+  // the fastest few are timed again, in two rounds of 2 reps passes each (a
+  // round visits each finalist once), and the best mean wins: one short
+  // sweep over all candidates cannot separate shapes a percent apart
+  std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+  const size_t n_fin = std::min<size_t>(cands.size(), kTuneFinalists);
+  std::vector<float> fin_ms(n_fin, 0.f);
+  for (int round = 0; round < 2 && e == hipSuccess; ++round)
+    for (size_t f = 0; f < n_fin && e == hipSuccess; ++f) {
+      if (plan->item_rows != cands[f].items) e = plan_items(plan, cands[f].items);
+      if (e != hipSuccess) break;
+      plan->cfg = cands[f].cfg;
+      float ms = 0.f;
+      time_shape(2 * reps, ms);
+      fin_ms[f] += ms / 2;
+    }
+  for (size_t f = 0; f < n_fin && e == hipSuccess; ++f) {
+    if (times_ms) times_ms[cands[f].ci] = fin_ms[f];
+    if (fin_ms[f] < best_ms) {
+      best_ms = fin_ms[f];
+      best = cands[f].cfg;
+      best_items = cands[f].items;
     }
   }
   plan->cfg = e == hipSuccess ? best : keep;

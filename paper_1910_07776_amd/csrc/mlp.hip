@@ -136,51 +136,71 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
-  bf16x8 ra[TM][kKVec], rb[TN][kKVec];
-  auto fetch = [&](int k0) {
+  // Two stages in flight in registers: stage s is written to LDS buffer s % 2
+  // while the loads of stage s + 1 are still outstanding, then the loads of
+  // stage s + 2 are issued and stage s is multiplied, so a global load has two
+  // stages of matrix work to arrive.  Every load is unconditional (the K
+  // offset clamped to the last stage; the surplus loads are not used), so
+  // each wait is for one stage's loads, never for all of them.
+  bf16x8 ra[2][TM][kKVec], rb[2][TN][kKVec];
+  const int nst = ke > kb ? (ke - kb + KS - 1) / KS : 0;   // stages of this split
+  const int klast = nst > 0 ? kb + (nst - 1) * KS : kb;     // (an empty split loads nothing: k >= ke)
+  auto fetch = [&](auto slot, int k0) {
+    constexpr int sl = decltype(slot)::value;
+    k0 = k0 < klast ? k0 : klast;
 #pragma unroll
     for (int v = 0; v < kKVec; ++v) {
 #pragma unroll
       for (int i = 0; i < TM; ++i)
-        ra[i][v] = EX ? *reinterpret_cast<const bf16x8*>(g.A + (int64_t)(m0 + lr + 64 * i) * g.lda + k0 + lk + 32 * v)
-                      : load8(g.A, g.lda, m0 + lr + 64 * i, g.M, k0 + lk + 32 * v, ke);
+        ra[sl][i][v] = EX ? *reinterpret_cast<const bf16x8*>(g.A + (int64_t)(m0 + lr + 64 * i) * g.lda + k0 + lk + 32 * v)
+                          : load8(g.A, g.lda, m0 + lr + 64 * i, g.M, k0 + lk + 32 * v, ke);
 #pragma unroll
       for (int i = 0; i < TN; ++i)
-        rb[i][v] = EX ? *reinterpret_cast<const bf16x8*>(g.Bt + (int64_t)(n0 + lr + 64 * i) * g.ldb + k0 + lk + 32 * v)
-                      : load8(g.Bt, g.ldb, n0 + lr + 64 * i, g.N, k0 + lk + 32 * v, ke);
+        rb[sl][i][v] = EX ? *reinterpret_cast<const bf16x8*>(g.Bt + (int64_t)(n0 + lr + 64 * i) * g.ldb + k0 + lk + 32 * v)
+                          : load8(g.Bt, g.ldb, n0 + lr + 64 * i, g.N, k0 + lk + 32 * v, ke);
     }
   };
-  fetch(kb);
-  int buf = 0;
-  for (int k0 = kb; k0 < ke; k0 += KS) {
+  // one stage: registers of `slot` into LDS buffer `slot`, the loads of the
+  // stage two ahead, the products of this one
+  auto run_stage = [&](auto slot, int k0) {
+    constexpr int sl = decltype(slot)::value;
 #pragma unroll
     for (int v = 0; v < kKVec; ++v) {
 #pragma unroll
       for (int i = 0; i < TM; ++i)
-        *reinterpret_cast<bf16x8*>(&As[buf][(lr + 64 * i) * kLdsRow + lk + 32 * v]) = ra[i][v];
+        *reinterpret_cast<bf16x8*>(&As[sl][(lr + 64 * i) * kLdsRow + lk + 32 * v]) = ra[sl][i][v];
 #pragma unroll
       for (int i = 0; i < TN; ++i)
-        *reinterpret_cast<bf16x8*>(&Bs[buf][(lr + 64 * i) * kLdsRow + lk + 32 * v]) = rb[i][v];
+        *reinterpret_cast<bf16x8*>(&Bs[sl][(lr + 64 * i) * kLdsRow + lk + 32 * v]) = rb[sl][i][v];
     }
     __syncthreads();
-    if (k0 + KS < ke) fetch(k0 + KS);
+    fetch(slot, k0 + 2 * KS);
 #pragma unroll
     for (int s = 0; s < KS; s += 16) {
       const int kk = s + (lane >> 5) * 8;
       bf16x8 fa[TM], fb[TN];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
-        fa[a] = *reinterpret_cast<const bf16x8*>(&As[buf][(wm * 32 * TM + a * 32 + (lane & 31)) * kLdsRow + kk]);
+        fa[a] = *reinterpret_cast<const bf16x8*>(&As[sl][(wm * 32 * TM + a * 32 + (lane & 31)) * kLdsRow + kk]);
 #pragma unroll
       for (int b = 0; b < TN; ++b)
-        fb[b] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn * 32 * TN + b * 32 + (lane & 31)) * kLdsRow + kk]);
+        fb[b] = *reinterpret_cast<const bf16x8*>(&Bs[sl][(wn * 32 * TN + b * 32 + (lane & 31)) * kLdsRow + kk]);
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
-    buf ^= 1;
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  fetch(S0{}, kb);
+  fetch(S1{}, kb + KS);
+  int st = 0;
+  for (; st + 2 <= nst; st += 2) {
+    run_stage(S0{}, kb + st * KS);
+    run_stage(S1{}, kb + (st + 1) * KS);
   }
+  if (st < nst) run_stage(S0{}, kb + st * KS);
 
   // epilogue: lane holds C[row(r)][col] of each 32 x 32 tile with
   // col = lane % 32, row(r) = (r / 4) * 8 + (lane / 32) * 4 + r % 4.  FP32
