@@ -321,10 +321,35 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 // read are written to rows_out [rows].
 hipError_t launch_gather_pack(const float* src, int64_t src_rows, int cols, const int32_t* idx, int rows, __bf16* dst,
                               int ldd, __bf16* dst_t, int ldt, int32_t* rows_out, int32_t* status, hipStream_t s);
-// split-K sums of a weight gradient (in split order) and row sums of a
-// transposed BF16 activation gradient (its bias gradient) in one launch
-hipError_t launch_wgrad_finish(const float* part, int64_t n, int splits, float* out, const __bf16* x, int rows,
-                               int cols, int ld, float* bias_out, hipStream_t s);
+// A weight gradient dW[M x N] = A[M x K] . Bt[N x K]^T split over K and a
+// hidden-layer backward (kEpiBwdHidden, one split) that do not depend on each
+// other, in one launch where their instances allow (else two launches; the
+// results are the same either way).
+hipError_t launch_gemm_pair(const GemmArgs& gw, int splits, const GemmArgs& gb, hipStream_t s,
+                            int32_t* info_w = nullptr, int32_t* info_b = nullptr);
+// The end of up to three weight gradients in one launch: split-K sums (in
+// split order) of the partials part [splits x n] into out [n], and row sums
+// of the transposed BF16 activation gradient x [rows x cols] (leading
+// dimension ld; its bias gradient) into bias_out [rows]; with loss non-null
+// also the loss as launch_loss_sum.
+struct WgradJob {
+  const float* part;
+  int64_t n;
+  int splits;
+  float* out;
+  const __bf16* x;
+  int rows, cols, ld;
+  float* bias_out;
+};
+struct FinishArgs {
+  WgradJob job[3];
+  int njobs;
+  const float* loss_part;   // nullable
+  int loss_n;
+  float loss_scale;
+  float* loss;
+};
+hipError_t launch_wgrad_finish(const FinishArgs& a, hipStream_t s);
 // Adam (as launch_adam) over the surrogate's flat parameters, writing the
 // updated weights of its three layers to their BF16 working copies
 // (row-major w[l]; transposed wt[l] where non-null, leading dimension = rows)

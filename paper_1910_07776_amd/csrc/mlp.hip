@@ -109,19 +109,20 @@ __device__ __forceinline__ void rank_rows(const GemmArgs& g, const float* y, int
 // MFMA tiles of 32 x 32, so the workgroup tile is (64 TM) x (64 TN).  EX: the
 // tiles cover M, N and each K range exactly and rows are 16-byte aligned, so
 // operand loads and output stores need no bounds checks.
+// One workgroup's tile (bx, by) of split bz; gx: tiles along N (the loss
+// partials are laid out per tile); gsm: the dynamic LDS.
 template <int EPI, int TM, int TN, bool EX, int KS>
-__global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
+__device__ __forceinline__ void gemm_nt_tile(const GemmArgs& g, int bx, int by, int bz, int gx, unsigned char* gsm) {
   constexpr int WGM = 64 * TM, WGN = 64 * TN;
   constexpr int kKVec = KS / 32;          // 8-element vectors per thread and tile row per stage
   constexpr int kLdsRow = lds_row<KS>();
-  extern __shared__ __align__(16) unsigned char gsm[];
   __bf16 (*As)[WGM * kLdsRow] = reinterpret_cast<__bf16 (*)[WGM * kLdsRow]>(gsm);
   __bf16 (*Bs)[WGN * kLdsRow] = reinterpret_cast<__bf16 (*)[WGN * kLdsRow]>(gsm + sizeof(__bf16) * 2 * WGM * kLdsRow);
   __shared__ float red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * WGM, n0 = blockIdx.x * WGN;
-  const int split = blockIdx.z;
+  const int m0 = by * WGM, n0 = bx * WGN;
+  const int split = bz;
   const int kb = split * g.k_per_split;
   const int ke = min(g.K, kb + g.k_per_split);
   // staging: thread t moves 8 elements at K offsets (t%4)*8 + 32 v of tile
@@ -329,15 +330,48 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
     for (int off = 32; off >= 1; off >>= 1) sse += __shfl_xor(sse, off, 64);
     if (lane == 0) red[wave] = sse;
     __syncthreads();
-    if (tid == 0) g.loss_part[blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    if (tid == 0) g.loss_part[by * gx + bx] = ((red[0] + red[1]) + red[2]) + red[3];
   }
 }
 
 template <int EPI, int TM, int TN, bool EX, int KS>
-hipError_t launch_gemm_k(const GemmArgs& g, dim3 grid, hipStream_t s) {
-  // the ranking epilogue keeps the FP32 output tile (rows padded by one)
+__global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
+  extern __shared__ __align__(16) unsigned char gsm[];
+  gemm_nt_tile<EPI, TM, TN, EX, KS>(g, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gsm);
+}
+
+// Two independent GEMMs in one launch (workgroups [0, n1) take the first,
+// the rest the second), each tile computed exactly as by its own launch.
+struct GemmGrid {
+  int nx, ny, nz;
+};
+template <int E1, int TM1, int TN1, bool EX1, int KS1, int E2, int TM2, int TN2, bool EX2, int KS2>
+__global__ void __launch_bounds__(256, 2) gemm_pair_kernel(const GemmArgs g1, const GemmGrid d1, const GemmArgs g2,
+                                                         const GemmGrid d2) {
+  extern __shared__ __align__(16) unsigned char gsm[];
+  const int n1 = d1.nx * d1.ny * d1.nz;
+  int b = blockIdx.x;
+  if (b < n1) {
+    const int xy = d1.nx * d1.ny, z = b / xy, r = b - z * xy;
+    gemm_nt_tile<E1, TM1, TN1, EX1, KS1>(g1, r % d1.nx, r / d1.nx, z, d1.nx, gsm);
+  } else {
+    b -= n1;
+    const int xy = d2.nx * d2.ny, z = b / xy, r = b - z * xy;
+    gemm_nt_tile<E2, TM2, TN2, EX2, KS2>(g2, r % d2.nx, r / d2.nx, z, d2.nx, gsm);
+  }
+}
+
+// LDS bytes of an instance (the ranking epilogue keeps the FP32 output tile,
+// rows padded by one)
+template <int EPI, int TM, int TN, int KS>
+constexpr size_t gemm_lds() {
   constexpr size_t ty = EPI == kEpiFwdRank ? sizeof(float) * 64 * TM * (64 * TN + 1) : 0;
-  constexpr size_t lds = gemm_lds_bytes<TM, TN, KS>() > ty ? gemm_lds_bytes<TM, TN, KS>() : ty;
+  return gemm_lds_bytes<TM, TN, KS>() > ty ? gemm_lds_bytes<TM, TN, KS>() : ty;
+}
+
+template <int EPI, int TM, int TN, bool EX, int KS>
+hipError_t launch_gemm_k(const GemmArgs& g, dim3 grid, hipStream_t s) {
+  constexpr size_t lds = gemm_lds<EPI, TM, TN, KS>();
   auto kern = gemm_nt_kernel<EPI, TM, TN, EX, KS>;
   if (lds > 64 * 1024) {
     static const hipError_t attr =
@@ -348,12 +382,18 @@ hipError_t launch_gemm_k(const GemmArgs& g, dim3 grid, hipStream_t s) {
   return hipSuccess;
 }
 
+// The instance a GEMM runs: workgroup tile (64 tm) x (64 tn), K stage ks,
+// exact tiles (no bounds checks).
+struct GemmPick {
+  int tm, tn, ks;
+  bool ex;
+  bool operator==(const GemmPick& o) const { return tm == o.tm && tn == o.tn && ks == o.ks && ex == o.ex; }
+};
+
 // K stage: 32 for 128 x 128 workgroup tiles (three workgroups fit a compute
 // unit's LDS); for smaller tiles 128 where every split's K range is a
 // multiple of 128, else 64 where a multiple of 64, else 32
-template <int EPI, int TM, int TN>
-hipError_t launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
-  const dim3 grid((g.N + 64 * TN - 1) / (64 * TN), (g.M + 64 * TM - 1) / (64 * TM), splits);
+GemmPick pick_ks(const GemmArgs& g, int splits, int TM, int TN) {
   const int ks = TM * TN > 2 ? 32   // 128 x 128 tiles: three workgroups per compute unit
                  : (g.K % 128 == 0 && g.k_per_split % 128 == 0) ? 128
                  : (g.K % 64 == 0 && g.k_per_split % 64 == 0) ? 64 : 32;
@@ -362,31 +402,69 @@ hipError_t launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s, int32_t* 
                   g.k_per_split % ks == 0 && (int64_t)g.k_per_split * (splits - 1) < g.K && g.lda % 8 == 0 &&
                   g.ldb % 8 == 0 && reinterpret_cast<uintptr_t>(g.A) % 16 == 0 &&
                   reinterpret_cast<uintptr_t>(g.Bt) % 16 == 0;
+  return GemmPick{TM, TN, ex ? ks : 32, ex};
+}
+
+// largest tile that still gives at least 256 workgroups (128 columns only
+// where they divide N); the loss partials of a training forward are laid
+// out per 64 x 64 tile
+GemmPick pick_gemm(int epi, const GemmArgs& g, int splits) {
+  const int64_t t22 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * splits;
+  const int64_t t21 = (int64_t)((g.N + 63) / 64) * ((g.M + 127) / 128) * splits;
+  if (epi == kEpiFwdOut && g.target) return pick_ks(g, splits, 1, 1);
+  if (t22 >= 256 && g.N % 128 == 0) return pick_ks(g, splits, 2, 2);
+  if (t21 >= 256) return pick_ks(g, splits, 2, 1);
+  return pick_ks(g, splits, 1, 1);
+}
+
+GemmGrid gemm_grid(const GemmArgs& g, const GemmPick& p, int splits) {
+  return GemmGrid{(g.N + 64 * p.tn - 1) / (64 * p.tn), (g.M + 64 * p.tm - 1) / (64 * p.tm), splits};
+}
+
+void gemm_info(const GemmPick& p, int splits, int32_t* info) {
+  if (!info) return;
+  info[0] = 64 * p.tm;
+  info[1] = 64 * p.tn;
+  info[2] = splits;
+  info[3] = p.ex ? p.ks : 0;
+}
+
+template <int EPI, int TM, int TN>
+hipError_t launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
+  const GemmPick p = pick_ks(g, splits, TM, TN);
+  const GemmGrid d = gemm_grid(g, p, splits);
+  const dim3 grid(d.nx, d.ny, d.nz);
   hipError_t e;
-  if (ex && ks == 128) e = launch_gemm_k<EPI, TM, TN, true, 128>(g, grid, s);
-  else if (ex && ks == 64) e = launch_gemm_k<EPI, TM, TN, true, 64>(g, grid, s);
-  else if (ex) e = launch_gemm_k<EPI, TM, TN, true, 32>(g, grid, s);
+  if (p.ex && p.ks == 128) e = launch_gemm_k<EPI, TM, TN, true, 128>(g, grid, s);
+  else if (p.ex && p.ks == 64) e = launch_gemm_k<EPI, TM, TN, true, 64>(g, grid, s);
+  else if (p.ex) e = launch_gemm_k<EPI, TM, TN, true, 32>(g, grid, s);
   else e = launch_gemm_k<EPI, TM, TN, false, 32>(g, grid, s);
-  if (info) {
-    info[0] = 64 * TM;
-    info[1] = 64 * TN;
-    info[2] = splits;
-    info[3] = ex ? ks : 0;
-  }
+  gemm_info(p, splits, info);
   return e;
 }
 
 template <int EPI>
 hipError_t launch_gemm_e(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
-  // largest tile that still gives at least 256 workgroups (128 columns only
-  // where they divide N); the loss partials of a training forward are laid
-  // out per 64 x 64 tile
-  const int64_t t22 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * splits;
-  const int64_t t21 = (int64_t)((g.N + 63) / 64) * ((g.M + 127) / 128) * splits;
-  if (EPI == kEpiFwdOut && g.target) return launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
-  if (t22 >= 256 && g.N % 128 == 0) return launch_gemm_t<EPI, 2, 2>(g, splits, s, info);
-  if (t21 >= 256) return launch_gemm_t<EPI, 2, 1>(g, splits, s, info);
+  const GemmPick p = pick_gemm(EPI, g, splits);
+  if (p.tm == 2 && p.tn == 2) return launch_gemm_t<EPI, 2, 2>(g, splits, s, info);
+  if (p.tm == 2) return launch_gemm_t<EPI, 2, 1>(g, splits, s, info);
   return launch_gemm_t<EPI, 1, 1>(g, splits, s, info);
+}
+
+template <int E1, int TM1, int TN1, int KS1, int E2, int TM2, int TN2, int KS2>
+hipError_t launch_pair_k(const GemmArgs& g1, const GemmGrid& d1, const GemmArgs& g2, const GemmGrid& d2,
+                         hipStream_t s) {
+  constexpr size_t l1 = gemm_lds<E1, TM1, TN1, KS1>(), l2 = gemm_lds<E2, TM2, TN2, KS2>();
+  constexpr size_t lds = l1 > l2 ? l1 : l2;
+  auto kern = gemm_pair_kernel<E1, TM1, TN1, true, KS1, E2, TM2, TN2, true, KS2>;
+  if (lds > 64 * 1024) {
+    static const hipError_t attr =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
+  }
+  const int n = d1.nx * d1.ny * d1.nz + d2.nx * d2.ny * d2.nz;
+  hipLaunchKernelGGL(kern, dim3(n), dim3(256), lds, s, g1, d1, g2, d2);
+  return hipSuccess;
 }
 
 hipError_t launch_gemm_rank(const GemmArgs& g, hipStream_t s, int32_t* info) {
@@ -397,6 +475,31 @@ hipError_t launch_gemm_rank(const GemmArgs& g, hipStream_t s, int32_t* info) {
                                  : launch_gemm_t<kEpiFwdRank, 2, 2>(g, 1, s, info);
   if (e != hipSuccess) return e;
   return hipGetLastError();
+}
+
+// A weight gradient (split over K) and a hidden-layer backward in one launch
+// where both run the instances of the surrogate's training shapes (a 64 x 64
+// weight-gradient tile with K stage 128; a 128 x 64 backward tile with K
+// stage 64 or 128), else in two launches; the results are the same.
+hipError_t launch_gemm_pair(const GemmArgs& gw, int splits, const GemmArgs& gb, hipStream_t s, int32_t* info_w,
+                            int32_t* info_b) {
+  const GemmPick pw = pick_gemm(kEpiWgrad, gw, splits), pb = pick_gemm(kEpiBwdHidden, gb, 1);
+  const bool live_w = gw.M > 0 && gw.N > 0, live_b = gb.M > 0 && gb.N > 0;
+  const bool w_ok = pw == GemmPick{1, 1, 128, true};
+  const bool b64 = pb == GemmPick{2, 1, 64, true}, b128 = pb == GemmPick{2, 1, 128, true};
+  if (live_w && live_b && w_ok && (b64 || b128)) {
+    (void)hipGetLastError();  // report only this launch's status
+    const GemmGrid dw = gemm_grid(gw, pw, splits), db = gemm_grid(gb, pb, 1);
+    const hipError_t e = b64 ? launch_pair_k<kEpiWgrad, 1, 1, 128, kEpiBwdHidden, 2, 1, 64>(gw, dw, gb, db, s)
+                             : launch_pair_k<kEpiWgrad, 1, 1, 128, kEpiBwdHidden, 2, 1, 128>(gw, dw, gb, db, s);
+    if (e != hipSuccess) return e;
+    gemm_info(pw, splits, info_w);
+    gemm_info(pb, 1, info_b);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_gemm(gw, kEpiWgrad, splits, s, info_w);
+  if (e == hipSuccess) e = launch_gemm(gb, kEpiBwdHidden, 1, s, info_b);
+  return e;
 }
 
 hipError_t launch_gemm(const GemmArgs& g, int epi, int splits, hipStream_t s, int32_t* info) {
@@ -487,31 +590,33 @@ hipError_t launch_pack(const float* src, int rows, int cols, __bf16* dst, int ld
   return hipGetLastError();
 }
 
-// The end of a weight gradient: blocks [0, nsum) sum its split-K partials
-// in split order (256 outputs each), the others take the row sums of the
-// transposed activation gradient (its bias gradient), 4 rows each.
-__global__ void wgrad_finish_kernel(const float* __restrict__ part, int64_t n, int splits, float* __restrict__ out,
-                                    int nsum, const __bf16* __restrict__ x, int rows, int cols, int ld,
-                                    float* __restrict__ bias_out) {
-  if ((int)blockIdx.x < nsum) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// The end of a weight gradient: its blocks [0, nsum) sum the split-K
+// partials in split order (256 outputs each), the others take the row sums of
+// the transposed activation gradient (its bias gradient), 4 rows each.
+__device__ __forceinline__ int64_t wgrad_nsum(const WgradJob& j) { return (j.n + 255) / 256; }
+__device__ __forceinline__ int64_t wgrad_blocks(const WgradJob& j) { return wgrad_nsum(j) + (j.rows + 3) / 4; }
+
+__device__ __forceinline__ void wgrad_finish_block(const WgradJob& j, int b) {
+  const int nsum = (int)wgrad_nsum(j);
+  if (b < nsum) {
+    const int64_t i = b * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= j.n) return;
     float v = 0.0f;
-    for (int q = 0; q < splits; ++q) v += part[(int64_t)q * n + i];
-    out[i] = v;
+    for (int q = 0; q < j.splits; ++q) v += j.part[(int64_t)q * j.n + i];
+    j.out[i] = v;
     return;
   }
   const int lane = threadIdx.x & 63;
-  const int row = (blockIdx.x - nsum) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= rows) return;
+  const int row = (b - nsum) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= j.rows) return;
   // lane sums of 8 consecutive elements per 512 (eight loads in flight),
   // then the lane tree: one fixed order
-  const __bf16* xr = x + (int64_t)row * ld;
+  const __bf16* xr = j.x + (int64_t)row * j.ld;
   float sm = 0.0f;
-  const bool vec = (ld % 8) == 0 && (reinterpret_cast<uintptr_t>(x) % 16) == 0;
+  const bool vec = (j.ld % 8) == 0 && (reinterpret_cast<uintptr_t>(j.x) % 16) == 0;
   int c0 = 0;
   if (vec) {
-    for (; c0 + 512 * 8 <= cols; c0 += 512 * 8) {
+    for (; c0 + 512 * 8 <= j.cols; c0 += 512 * 8) {
       bf16x8 q[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) q[u] = *reinterpret_cast<const bf16x8*>(xr + c0 + 512 * u + lane * 8);
@@ -520,30 +625,21 @@ __global__ void wgrad_finish_kernel(const float* __restrict__ part, int64_t n, i
 #pragma unroll
         for (int i = 0; i < 8; ++i) sm += (float)q[u][i];
     }
-    for (; c0 + 512 <= cols; c0 += 512) {
+    for (; c0 + 512 <= j.cols; c0 += 512) {
       const bf16x8 q = *reinterpret_cast<const bf16x8*>(xr + c0 + lane * 8);
 #pragma unroll
       for (int i = 0; i < 8; ++i) sm += (float)q[i];
     }
   }
-  for (int c = c0 + lane; c < cols; c += 64) sm += (float)xr[c];
+  for (int c = c0 + lane; c < j.cols; c += 64) sm += (float)xr[c];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) sm += __shfl_xor(sm, off, 64);
-  if (lane == 0) bias_out[row] = sm;
+  if (lane == 0) j.bias_out[row] = sm;
 }
 
-hipError_t launch_wgrad_finish(const float* part, int64_t n, int splits, float* out, const __bf16* x, int rows,
-                               int cols, int ld, float* bias_out, hipStream_t s) {
-  const int nsum = (int)((n + 255) / 256), nrow = (rows + 3) / 4;
-  if (nsum + nrow <= 0) return hipSuccess;
-  (void)hipGetLastError();  // report only this launch's status
-  hipLaunchKernelGGL(wgrad_finish_kernel, dim3(nsum + nrow), dim3(256), 0, s, part, n, splits, out, nsum, x, rows,
-                     cols, ld, bias_out);
-  return hipGetLastError();
-}
-
-// Loss from per-tile partial sums, in order.
-__global__ void loss_sum_kernel(const float* __restrict__ part, int n, float scale, float* __restrict__ loss) {
+// Loss from per-tile partial sums, in order (one block of 256 threads).
+__device__ __forceinline__ void loss_block(const float* __restrict__ part, int n, float scale,
+                                           float* __restrict__ loss) {
   __shared__ float red[256];
   float s = 0.0f;
   for (int i = threadIdx.x; i < n; i += 256) s += part[i];
@@ -554,6 +650,34 @@ __global__ void loss_sum_kernel(const float* __restrict__ part, int n, float sca
     __syncthreads();
   }
   if (threadIdx.x == 0) *loss = red[0] * scale;
+}
+
+// Blocks go to the jobs in order, then one block to the loss.
+__global__ void __launch_bounds__(256) wgrad_finish_kernel(const FinishArgs a) {
+  int b = blockIdx.x;
+  for (int q = 0; q < a.njobs; ++q) {
+    const int nb = (int)wgrad_blocks(a.job[q]);
+    if (b < nb) {
+      wgrad_finish_block(a.job[q], b);
+      return;
+    }
+    b -= nb;
+  }
+  if (a.loss) loss_block(a.loss_part, a.loss_n, a.loss_scale, a.loss);
+}
+
+hipError_t launch_wgrad_finish(const FinishArgs& a, hipStream_t s) {
+  int64_t blocks = a.loss ? 1 : 0;
+  for (int q = 0; q < a.njobs; ++q) blocks += (a.job[q].n + 255) / 256 + (a.job[q].rows + 3) / 4;
+  if (blocks <= 0) return hipSuccess;
+  (void)hipGetLastError();  // report only this launch's status
+  hipLaunchKernelGGL(wgrad_finish_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) loss_sum_kernel(const float* __restrict__ part, int n, float scale,
+                                                       float* __restrict__ loss) {
+  loss_block(part, n, scale, loss);
 }
 
 // Adam with bias correction (Kingma and Ba, 2015) on FP32 master weights:

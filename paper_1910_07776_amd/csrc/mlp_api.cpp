@@ -26,6 +26,7 @@ struct sugg_mlp {
   float *a1 = nullptr, *a2 = nullptr, *part = nullptr, *loss_part = nullptr, *ybuf = nullptr;
   int32_t* trow = nullptr;      // training rows of the current mini-batch (sugg_mlp_train_epoch)
   int64_t part_n = 0;
+  int64_t part_off[3] = {};   // partial regions of the weight gradients of layers 3, 2, 1
   float* frozen = nullptr;      // inference copy of the parameters (sugg_mlp_freeze)
   bool packed_frozen = false;   // the BF16 working weights hold the frozen parameters
   int32_t info[8][4] = {};   // launched GEMM instances: forward layers 1-3, then the backward's five
@@ -62,18 +63,18 @@ GemmArgs gemm(const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, int N,
 }
 
 // weight gradient dW[M x N] = A[M x K] . Bt[N x K]^T with K split across
-// workgroups, and the bias gradient db[M] = row sums of A (the transposed
-// activation gradient, K = batch), summed in one finishing launch
-hipError_t wgrad(sugg_mlp* m, const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, int N, int K, float* dW,
-                 float* db, hipStream_t s, int32_t* info) {
+// workgroups into partial region `region` of the layer, and its finishing
+// job: the split sums into dW and the bias gradient db[M] = row sums of A (the
+// transposed activation gradient, K = batch)
+GemmArgs wgrad_args(sugg_mlp* m, int region, const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, int N, int K,
+                    float* dW, float* db, int* splits, WgradJob* job) {
   GemmArgs g = gemm(A, lda, Bt, ldb, M, N, K);
   const int sp = splits_for(M, N, K);
   g.k_per_split = ((K + sp - 1) / sp + 31) / 32 * 32;
-  const int used = (K + g.k_per_split - 1) / g.k_per_split;
-  g.Cf = m->part;
-  hipError_t e = launch_gemm(g, kEpiWgrad, used, s, info);
-  if (e != hipSuccess) return e;
-  return launch_wgrad_finish(m->part, (int64_t)M * N, used, dW, A, M, K, lda, db, s);
+  *splits = (K + g.k_per_split - 1) / g.k_per_split;
+  g.Cf = m->part + m->part_off[region];
+  *job = WgradJob{g.Cf, (int64_t)M * N, *splits, dW, A, M, K, lda, db};
+  return g;
 }
 
 int check_mlp(sugg_ctx* ctx, sugg_mlp* m, int batch) {
@@ -95,8 +96,11 @@ hipError_t pack_weights(sugg_mlp* m, const float* params, hipStream_t s) {
 
 // x == nullptr: the batch is already packed in xb and xt; trow (nullable):
 // row r's target is target row trow[r]
+// defer_loss: the caller sums the loss partials (in the backward's finishing
+// launch)
 int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int B, float* y, bool keep,
-            const float* target, float* loss, hipStream_t s, bool pack_w = true, const int32_t* trow = nullptr) {
+            const float* target, float* loss, hipStream_t s, bool pack_w = true, const int32_t* trow = nullptr,
+            bool defer_loss = false) {
   const int in = m->in, hid = m->hid, out = m->out, bm = m->bm;
   hipError_t e = hipSuccess;
   if (pack_w) e = pack_weights(m, params, s);
@@ -139,7 +143,7 @@ int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int
   }
   e = launch_gemm(g, kEpiFwdOut, 1, s, m->info[2]);
   if (e != hipSuccess) return ctx->hip(e, "mlp layer 3");
-  if (target) {
+  if (target && !defer_loss) {
     const int tiles = ((B + 63) / 64) * ((out + 63) / 64);
     e = launch_loss_sum(m->loss_part, tiles, 1.0f / ((float)B * (float)out), loss, s);
     if (e != hipSuccess) return ctx->hip(e, "mlp loss");
@@ -149,11 +153,19 @@ int forward(sugg_ctx* ctx, sugg_mlp* m, const float* params, const float* x, int
   return SUGG_OK;
 }
 
-int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grads, hipStream_t s) {
+// Three launches and the finish: each layer's weight gradient shares a launch
+// with the backward through that layer (they do not depend on each other),
+// and one launch finishes all three weight and bias gradients (and, with
+// loss non-null, sums the loss partials of the forward that kept dY).
+int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grads, hipStream_t s,
+             float* loss = nullptr) {
   (void)params;
   const int in = m->in, hid = m->hid, out = m->out, bm = m->bm;
-  hipError_t e = wgrad(m, m->dyt, bm, m->h2t, bm, out, hid, B, grads + m->off_w3, grads + m->off_b3, s, m->info[3]);
-  if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 3");
+  FinishArgs fa{};
+  fa.njobs = 3;
+  int sp = 1;
+  GemmArgs gw = wgrad_args(m, 0, m->dyt, bm, m->h2t, bm, out, hid, B, grads + m->off_w3, grads + m->off_b3, &sp,
+                           &fa.job[0]);
   GemmArgs g = gemm(m->dy, out, m->w3t, out, B, hid, out);
   g.gact = m->a2;
   g.ldg = hid;
@@ -161,19 +173,27 @@ int backward(sugg_ctx* ctx, sugg_mlp* m, const float* params, int B, float* grad
   g.ldcb = hid;
   g.Ct = m->da2t;
   g.ldct = bm;
-  e = launch_gemm(g, kEpiBwdHidden, 1, s, m->info[4]);
-  if (e == hipSuccess)
-    e = wgrad(m, m->da2t, bm, m->h1t, bm, hid, hid, B, grads + m->off_w2, grads + m->off_b2, s, m->info[5]);
-  if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 2");
+  hipError_t e = launch_gemm_pair(gw, sp, g, s, m->info[3], m->info[4]);
+  if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 3");
+  gw = wgrad_args(m, 1, m->da2t, bm, m->h1t, bm, hid, hid, B, grads + m->off_w2, grads + m->off_b2, &sp, &fa.job[1]);
   g = gemm(m->da2, hid, m->w2t, hid, B, hid, hid);
   g.gact = m->a1;
   g.ldg = hid;
   g.Ct = m->da1t;
   g.ldct = bm;
-  e = launch_gemm(g, kEpiBwdHidden, 1, s, m->info[6]);
-  if (e == hipSuccess)
-    e = wgrad(m, m->da1t, bm, m->xt, bm, hid, in, B, grads + m->off_w1, grads + m->off_b1, s, m->info[7]);
+  e = launch_gemm_pair(gw, sp, g, s, m->info[5], m->info[6]);
+  if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 2");
+  gw = wgrad_args(m, 2, m->da1t, bm, m->xt, bm, hid, in, B, grads + m->off_w1, grads + m->off_b1, &sp, &fa.job[2]);
+  e = launch_gemm(gw, kEpiWgrad, sp, s, m->info[7]);
   if (e != hipSuccess) return ctx->hip(e, "mlp backward layer 1");
+  if (loss) {
+    fa.loss_part = m->loss_part;
+    fa.loss_n = ((B + 63) / 64) * ((out + 63) / 64);
+    fa.loss_scale = 1.0f / ((float)B * (float)out);
+    fa.loss = loss;
+  }
+  e = launch_wgrad_finish(fa, s);
+  if (e != hipSuccess) return ctx->hip(e, "mlp gradients");
   return SUGG_OK;
 }
 
@@ -280,9 +300,14 @@ int32_t sugg_mlp_create(sugg_ctx* ctx, int32_t in, int32_t hidden, int32_t out, 
   m->off_b3 = m->off_w3 + (int64_t)out * hidden;
   m->nparam = m->off_b3 + out;
   const size_t bm = m->bm, bf = sizeof(__bf16);
+  // one region per layer (the three weight gradients are finished together);
+  // a smaller batch uses no more splits than the largest
   int64_t part = 0;
-  for (auto mn : {std::pair<int, int>(out, hidden), {hidden, hidden}, {hidden, in}})
-    part = std::max(part, (int64_t)splits_for(mn.first, mn.second, m->bm) * mn.first * mn.second);
+  int li = 0;
+  for (auto mn : {std::pair<int, int>(out, hidden), {hidden, hidden}, {hidden, in}}) {
+    m->part_off[li++] = part;
+    part += (int64_t)splits_for(mn.first, mn.second, m->bm) * mn.first * mn.second;
+  }
   m->part_n = part;
   hipError_t e = hipSuccess;
   auto A = [&](auto*& p, size_t bytes) {
@@ -461,9 +486,9 @@ int32_t sugg_mlp_train_epoch(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float*
     e = launch_gather_pack(X, n_rows, mlp->in, perm + (int64_t)s * batch, batch, mlp->xb, mlp->in, mlp->xt, mlp->bm,
                            mlp->trow, ctx->d_status, stream);
     if (e != hipSuccess) return ctx->hip(e, "mlp gather");
-    rc = forward(ctx, mlp, params, nullptr, batch, mlp->ybuf, true, Y, losses + s, stream, false, mlp->trow);
+    rc = forward(ctx, mlp, params, nullptr, batch, mlp->ybuf, true, Y, nullptr, stream, false, mlp->trow, true);
     if (rc) return rc;
-    rc = backward(ctx, mlp, params, batch, grads, stream);
+    rc = backward(ctx, mlp, params, batch, grads, stream, losses + s);
     if (rc) return rc;
     e = launch_adam_pack(ap, step0 + s + 1, stream);
     if (e != hipSuccess) return ctx->hip(e, "mlp adam");
