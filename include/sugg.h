@@ -497,12 +497,13 @@ SUGG_API int32_t sugg_mlp_train_step(sugg_ctx* ctx, sugg_mlp* mlp, float* params
  * perm[s*batch .. (s+1)*batch) of X [n_rows x in] with targets the same rows
  * of Y [n_rows x out] (gathered by the first kernel, no copies), then what
  * sugg_mlp_train_step does with Adam step step0 + s + 1; loss of step s into
- * losses[s] (device).  Eight launches a step: the gather, three forward
- * GEMMs, two launches that each pair a weight gradient with the backward
- * through that layer, the first layer's weight gradient, one launch that
- * finishes all three weight and bias gradients and the loss, and Adam, which
- * also rewrites the BF16 working weights.  Bit-identical to train_step on the
- * gathered batches.  perm is a
+ * losses[s] (device).  Seven launches a step: three forward GEMMs, two
+ * launches that each pair a weight gradient with the backward through that
+ * layer, the first layer's weight gradient, one launch that finishes all
+ * three weight and bias gradients and the loss, and Adam (which also
+ * rewrites the BF16 working weights) together with the gather of the next
+ * mini-batch (the first gather is a launch of its own).  Bit-identical to
+ * train_step on the gathered batches.  perm is a
  * device int32 array of steps*batch entries; an entry outside [0, n_rows)
  * reads row 0 and the next sugg_sync reports SUGG_E_ARG.  Asynchronous. */
 /* Inference with the frozen parameters (sugg_mlp_freeze; SUGG_E_STATE

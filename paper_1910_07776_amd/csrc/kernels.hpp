@@ -319,8 +319,20 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 // row-major dst and transposed dst_t (as launch_pack); an index outside
 // [0, src_rows) reads row 0 and sets kStatusBadIndex in status.  The rows
 // read are written to rows_out [rows].
-hipError_t launch_gather_pack(const float* src, int64_t src_rows, int cols, const int32_t* idx, int rows, __bf16* dst,
-                              int ldd, __bf16* dst_t, int ldt, int32_t* rows_out, int32_t* status, hipStream_t s);
+struct GatherArgs {
+  const float* src;
+  int64_t src_rows;
+  int cols;
+  const int32_t* idx;
+  int rows;
+  __bf16* dst;
+  int ldd;
+  __bf16* dst_t;
+  int ldt;
+  int32_t* rows_out;
+  int32_t* status;
+};
+hipError_t launch_gather_pack(const GatherArgs& g, hipStream_t s);
 // A weight gradient dW[M x N] = A[M x K] . Bt[N x K]^T split over K and a
 // hidden-layer backward (kEpiBwdHidden, one split) that do not depend on each
 // other, in one launch where their instances allow (else two launches; the
@@ -366,5 +378,8 @@ struct AdamPackArgs {
   __bf16* wt[3];
 };
 hipError_t launch_adam_pack(const AdamPackArgs& a, int step, hipStream_t s);
+// launch_adam_pack of one step and launch_gather_pack of the next mini-batch
+// in one launch (the gather does not depend on the update)
+hipError_t launch_adam_gather(const AdamPackArgs& a, int step, const GatherArgs& g, hipStream_t s);
 
 }  // namespace sugg

@@ -537,47 +537,48 @@ __global__ void pack_bf16_kernel(const float* __restrict__ src, int rows, int co
     }
 }
 
-// pack_bf16_kernel of the rows idx[0..rows) of src (one read per element)
-__global__ void gather_pack_kernel(const float* __restrict__ src, int64_t src_rows, int cols,
-                                   const int32_t* __restrict__ idx, int rows, __bf16* dst, int ldd, __bf16* dst_t,
-                                   int ldt, int32_t* rows_out, int32_t* status) {
+// pack_bf16_kernel of the rows idx[0..rows) of src (one read per element):
+// the 32 x 32 tile (bx, by)
+__device__ __forceinline__ void gather_pack_tile(const GatherArgs& g, int bx, int by) {
   __shared__ float tile[32][33];
   __shared__ int64_t srow[32];
-  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int r0 = by * 32, c0 = bx * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   if (threadIdx.x < 32) {
     const int r = r0 + threadIdx.x;
     int64_t q = 0;
-    if (r < rows) {
-      q = idx[r];
-      if (q < 0 || q >= src_rows) {
-        atomicOr(status, (int)kStatusBadIndex);
+    if (r < g.rows) {
+      q = g.idx[r];
+      if (q < 0 || q >= g.src_rows) {
+        atomicOr(g.status, (int)kStatusBadIndex);
         q = 0;
       }
-      if (blockIdx.x == 0) rows_out[r] = (int32_t)q;
+      if (bx == 0) g.rows_out[r] = (int32_t)q;
     }
     srow[threadIdx.x] = q;
   }
   __syncthreads();
   for (int i = ty; i < 32; i += 8) {
     const int r = r0 + i, c = c0 + tx;
-    const float v = (r < rows && c < cols) ? src[srow[i] * cols + c] : 0.0f;
+    const float v = (r < g.rows && c < g.cols) ? g.src[srow[i] * g.cols + c] : 0.0f;
     tile[i][tx] = v;
-    if (r < rows && c < cols) dst[(int64_t)r * ldd + c] = to_bf16(v);
+    if (r < g.rows && c < g.cols) g.dst[(int64_t)r * g.ldd + c] = to_bf16(v);
   }
   __syncthreads();
   for (int i = ty; i < 32; i += 8) {
     const int c = c0 + i, r = r0 + tx;
-    if (r < rows && c < cols) dst_t[(int64_t)c * ldt + r] = to_bf16(tile[tx][i]);
+    if (r < g.rows && c < g.cols) g.dst_t[(int64_t)c * g.ldt + r] = to_bf16(tile[tx][i]);
   }
 }
 
-hipError_t launch_gather_pack(const float* src, int64_t src_rows, int cols, const int32_t* idx, int rows, __bf16* dst,
-                              int ldd, __bf16* dst_t, int ldt, int32_t* rows_out, int32_t* status, hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return hipSuccess;
+__global__ void __launch_bounds__(256) gather_pack_kernel(const GatherArgs g) {
+  gather_pack_tile(g, blockIdx.x, blockIdx.y);
+}
+
+hipError_t launch_gather_pack(const GatherArgs& g, hipStream_t s) {
+  if (g.rows <= 0 || g.cols <= 0) return hipSuccess;
   (void)hipGetLastError();  // report only this launch's status
-  hipLaunchKernelGGL(gather_pack_kernel, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, s, src, src_rows,
-                     cols, idx, rows, dst, ldd, dst_t, ldt, rows_out, status);
+  hipLaunchKernelGGL(gather_pack_kernel, dim3((g.cols + 31) / 32, (g.rows + 31) / 32), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
@@ -709,10 +710,9 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ gr,
 // them and writing the row-major copy directly and the transposed copy
 // through LDS; the remaining blocks update every other parameter (the
 // biases), 256 per block.
-__global__ void adam_pack_kernel(const AdamPackArgs a, int tiles0, int tiles1, int tiles2) {
+__device__ __forceinline__ void adam_pack_block(const AdamPackArgs& a, int tiles0, int tiles1, int tiles2, int b) {
   __shared__ float tile[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
-  int b = blockIdx.x;
   const int tl[3] = {tiles0, tiles1, tiles2};
   int l = 0;
   while (l < 3 && b >= tl[l]) b -= tl[l++];
@@ -747,20 +747,52 @@ __global__ void adam_pack_kernel(const AdamPackArgs a, int tiles0, int tiles1, i
   if (i < a.n) (void)adam_update(a.p, a.g, a.m, a.v, i, a.lr, a.b1, a.b2, a.eps, a.c1, a.c2);
 }
 
-hipError_t launch_adam_pack(const AdamPackArgs& a0, int step, hipStream_t s) {
-  AdamPackArgs a = a0;
+__global__ void __launch_bounds__(256) adam_pack_kernel(const AdamPackArgs a, int tiles0, int tiles1, int tiles2) {
+  adam_pack_block(a, tiles0, tiles1, tiles2, blockIdx.x);
+}
+
+// Adam of one step and the gather of the next mini-batch (which does not
+// depend on it) in one launch: blocks [0, n_adam) update, the rest gather.
+__global__ void __launch_bounds__(256) adam_gather_kernel(const AdamPackArgs a, int tiles0, int tiles1, int tiles2,
+                                                          int n_adam, const GatherArgs g, int gx) {
+  const int b = blockIdx.x;
+  if (b < n_adam) adam_pack_block(a, tiles0, tiles1, tiles2, b);
+  else gather_pack_tile(g, (b - n_adam) % gx, (b - n_adam) / gx);
+}
+
+namespace {
+// bias corrections of the step and the block counts of the three matrices'
+// tiles and of the remaining parameters
+int adam_pack_setup(AdamPackArgs& a, int step, int (&t)[3]) {
   a.c1 = 1.0f - powf(a.b1, (float)step);
   a.c2 = 1.0f - powf(a.b2, (float)step);
-  int t[3];
   int64_t inside = 0;
   for (int l = 0; l < 3; ++l) {
     t[l] = ((a.rows[l] + 31) / 32) * ((a.cols[l] + 31) / 32);
     inside += (int64_t)a.rows[l] * a.cols[l];
   }
   const int64_t rest = a.n - inside;
-  const int blocks = t[0] + t[1] + t[2] + (int)((rest + 255) / 256);
+  return t[0] + t[1] + t[2] + (int)((rest + 255) / 256);
+}
+}  // namespace
+
+hipError_t launch_adam_pack(const AdamPackArgs& a0, int step, hipStream_t s) {
+  AdamPackArgs a = a0;
+  int t[3];
+  const int blocks = adam_pack_setup(a, step, t);
   (void)hipGetLastError();  // report only this launch's status
   hipLaunchKernelGGL(adam_pack_kernel, dim3(blocks), dim3(256), 0, s, a, t[0], t[1], t[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_gather(const AdamPackArgs& a0, int step, const GatherArgs& g, hipStream_t s) {
+  if (g.rows <= 0 || g.cols <= 0) return launch_adam_pack(a0, step, s);
+  AdamPackArgs a = a0;
+  int t[3];
+  const int n_adam = adam_pack_setup(a, step, t);
+  const int gx = (g.cols + 31) / 32, gy = (g.rows + 31) / 32;
+  (void)hipGetLastError();  // report only this launch's status
+  hipLaunchKernelGGL(adam_gather_kernel, dim3(n_adam + gx * gy), dim3(256), 0, s, a, t[0], t[1], t[2], n_adam, g, gx);
   return hipGetLastError();
 }
 

@@ -482,15 +482,21 @@ int32_t sugg_mlp_train_epoch(sugg_ctx* ctx, sugg_mlp* mlp, float* params, float*
     ap.w[l] = w[l];
     ap.wt[l] = wt[l];
   }
+  // mini-batch s: rows perm[s*batch ..) gathered into the packed input (the
+  // gather of step s + 1 shares Adam's launch of step s)
+  auto gather = [&](int s) {
+    return GatherArgs{X, n_rows, mlp->in, perm + (int64_t)s * batch, batch, mlp->xb, mlp->in, mlp->xt, mlp->bm,
+                      mlp->trow, ctx->d_status};
+  };
+  e = launch_gather_pack(gather(0), stream);
+  if (e != hipSuccess) return ctx->hip(e, "mlp gather");
   for (int s = 0; s < steps; ++s) {
-    e = launch_gather_pack(X, n_rows, mlp->in, perm + (int64_t)s * batch, batch, mlp->xb, mlp->in, mlp->xt, mlp->bm,
-                           mlp->trow, ctx->d_status, stream);
-    if (e != hipSuccess) return ctx->hip(e, "mlp gather");
     rc = forward(ctx, mlp, params, nullptr, batch, mlp->ybuf, true, Y, nullptr, stream, false, mlp->trow, true);
     if (rc) return rc;
     rc = backward(ctx, mlp, params, batch, grads, stream, losses + s);
     if (rc) return rc;
-    e = launch_adam_pack(ap, step0 + s + 1, stream);
+    e = s + 1 < steps ? launch_adam_gather(ap, step0 + s + 1, gather(s + 1), stream)
+                      : launch_adam_pack(ap, step0 + s + 1, stream);
     if (e != hipSuccess) return ctx->hip(e, "mlp adam");
   }
   mlp->packed_frozen = false;
