@@ -392,10 +392,14 @@ struct GemmPick {
 
 // K stage: 32 for 128 x 128 workgroup tiles (three workgroups fit a compute
 // unit's LDS); for smaller tiles 128 where every split's K range is a
-// multiple of 128, else 64 where a multiple of 64, else 32
-GemmPick pick_ks(const GemmArgs& g, int splits, int TM, int TN) {
+// multiple of 128, else 64 where a multiple of 64, else 32.  The ranking
+// epilogue stops at 64: its 128 x 64 tiles then fit two workgroups per
+// compute unit (a surrogate pass over 65,536 kernels took 140 instead of
+// 157 us).
+GemmPick pick_ks(int epi, const GemmArgs& g, int splits, int TM, int TN) {
+  const bool k128 = g.K % 128 == 0 && g.k_per_split % 128 == 0 && epi != kEpiFwdRank;
   const int ks = TM * TN > 2 ? 32   // 128 x 128 tiles: three workgroups per compute unit
-                 : (g.K % 128 == 0 && g.k_per_split % 128 == 0) ? 128
+                 : k128 ? 128
                  : (g.K % 64 == 0 && g.k_per_split % 64 == 0) ? 64 : 32;
   // every split's K range non-empty and a whole number of stages
   const bool ex = g.M % (64 * TM) == 0 && g.N % (64 * TN) == 0 && g.K > 0 && g.K % ks == 0 &&
@@ -411,10 +415,10 @@ GemmPick pick_ks(const GemmArgs& g, int splits, int TM, int TN) {
 GemmPick pick_gemm(int epi, const GemmArgs& g, int splits) {
   const int64_t t22 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * splits;
   const int64_t t21 = (int64_t)((g.N + 63) / 64) * ((g.M + 127) / 128) * splits;
-  if (epi == kEpiFwdOut && g.target) return pick_ks(g, splits, 1, 1);
-  if (t22 >= 256 && g.N % 128 == 0) return pick_ks(g, splits, 2, 2);
-  if (t21 >= 256) return pick_ks(g, splits, 2, 1);
-  return pick_ks(g, splits, 1, 1);
+  if (epi == kEpiFwdOut && g.target) return pick_ks(epi, g, splits, 1, 1);
+  if (t22 >= 256 && g.N % 128 == 0) return pick_ks(epi, g, splits, 2, 2);
+  if (t21 >= 256) return pick_ks(epi, g, splits, 2, 1);
+  return pick_ks(epi, g, splits, 1, 1);
 }
 
 GemmGrid gemm_grid(const GemmArgs& g, const GemmPick& p, int splits) {
@@ -431,7 +435,7 @@ void gemm_info(const GemmPick& p, int splits, int32_t* info) {
 
 template <int EPI, int TM, int TN>
 hipError_t launch_gemm_t(const GemmArgs& g, int splits, hipStream_t s, int32_t* info) {
-  const GemmPick p = pick_ks(g, splits, TM, TN);
+  const GemmPick p = pick_ks(EPI, g, splits, TM, TN);
   const GemmGrid d = gemm_grid(g, p, splits);
   const dim3 grid(d.nx, d.ny, d.nz);
   hipError_t e;

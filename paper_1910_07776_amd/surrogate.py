@@ -213,53 +213,46 @@ class SurrogateFn(torch.autograd.Function):
 
 
 # ---------------------------------------------------------------- training --
-def subset_bits(B: int, device) -> torch.Tensor:
-    """[2^B, B] 0/1 matrix: bit b of subset S."""
-    S = torch.arange(1 << B, device=device)
-    return ((S[:, None] >> torch.arange(B, device=device)) & 1).float()
-
-
-def label_chunk(ctx, plan, counters, cycles, B: int, with_additive: bool = False):
+def label_chunk(ctx, plan, counters, cycles, B: int, with_baseline_grid: bool = False):
     """Plain-method labels of a uniform batch (every kernel B optimisations):
     X = standardised baseline counters [K, E], Y = composed tables [K, 2^B]
-    (sugg_predict), and optionally the baseline-only additive table
-    sum_{b in S} P(baseline, b) from the grid's baseline rows."""
+    (sugg_predict), and optionally the grid's baseline rows [K, B] (the plain
+    models' single-optimisation predictions P(baseline, b))."""
     from .plain import load_features, predict
-    table, grid = predict(ctx, plan, counters, cycles, grid=with_additive)
+    table, grid = predict(ctx, plan, counters, cycles, grid=with_baseline_grid)
     X = load_features(ctx, plan, counters, cycles, baseline=True)
     Y = table.view(plan.K, 1 << B)
-    add = None
-    if with_additive:
+    g0 = None
+    if with_baseline_grid:
         g0 = grid[torch.as_tensor(plan.row_off[:-1], device=grid.device)][:, :B]
-        add = g0 @ subset_bits(B, grid.device).T
-    return X, Y, add
+    return X, Y, g0
 
 
 def build_dataset(ctx, tw, n_kernels: int, chunk: int = 65536, chunk_base: int = 0, with_truth: bool = False,
-                  with_additive: bool = False):
+                  with_baseline_grid: bool = False):
     """Draw n_kernels kernels of the TorchWorld tw in chunks and label them
     with the plain path.  Returns a dict of device tensors X, Y (and T, the
-    generator's true log-speedups; A, the additive baseline-only table)."""
+    generator's true log-speedups; G0, the grid's baseline rows)."""
     from .plain import Plan
     B, E, dev = tw.B, tw.E, ctx.device
     out = {"X": torch.empty((n_kernels, E), device=dev), "Y": torch.empty((n_kernels, 1 << B), device=dev)}
     if with_truth:
         out["T"] = torch.empty((n_kernels, 1 << B), device=dev)
-    if with_additive:
-        out["A"] = torch.empty((n_kernels, 1 << B), device=dev)
+    if with_baseline_grid:
+        out["G0"] = torch.empty((n_kernels, B), device=dev)
     plans = {}
     for i, c0 in enumerate(range(0, n_kernels, chunk)):
         K = min(chunk, n_kernels - c0)
         if K not in plans:
             plans[K] = Plan(ctx, np.full(K, B, np.int32), np.tile(np.arange(B, dtype=np.int32), K), E, tw.D)
         counters, cycles, truth = tw.chunk(chunk_base + i, K)
-        X, Y, add = label_chunk(ctx, plans[K], counters, cycles, B, with_additive)
+        X, Y, g0 = label_chunk(ctx, plans[K], counters, cycles, B, with_baseline_grid)
         out["X"][c0:c0 + K] = X
         out["Y"][c0:c0 + K] = Y
         if with_truth:
             out["T"][c0:c0 + K] = truth.float()
-        if with_additive:
-            out["A"][c0:c0 + K] = add
+        if with_baseline_grid:
+            out["G0"][c0:c0 + K] = g0
         del counters, cycles
     return out
 
