@@ -334,10 +334,29 @@ __device__ __forceinline__ void gemm_nt_tile(const GemmArgs& g, int bx, int by, 
   }
 }
 
+// The tile (bx, by) of the i-th workgroup of an nx x ny grid.  Workgroups go
+// to the eight XCDs in turn (i mod 8); where ny is a multiple of 8 (and the
+// grid starts on XCD 0), the nx tiles of a row block all go to one XCD, so
+// the block's A rows are fetched into that XCD's L2 once and used nx times
+// there (in row-major order each went to another XCD and was fetched nx
+// times).  The tiles and their arithmetic are the same either way.
+__device__ __forceinline__ void xcd_tile(int i, int nx, int ny, bool xcd, int& bx, int& by) {
+  if (xcd && ny % 8 == 0) {
+    const int x = i % 8, s = i / 8;
+    by = x + 8 * (s / nx);
+    bx = s % nx;
+  } else {
+    by = i / nx;
+    bx = i % nx;
+  }
+}
+
 template <int EPI, int TM, int TN, bool EX, int KS>
 __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(const GemmArgs g) {
   extern __shared__ __align__(16) unsigned char gsm[];
-  gemm_nt_tile<EPI, TM, TN, EX, KS>(g, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gsm);
+  int bx, by;
+  xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, true, bx, by);
+  gemm_nt_tile<EPI, TM, TN, EX, KS>(g, bx, by, blockIdx.z, gridDim.x, gsm);
 }
 
 // Two independent GEMMs in one launch (workgroups [0, n1) take the first,
@@ -350,14 +369,16 @@ __global__ void __launch_bounds__(256, 2) gemm_pair_kernel(const GemmArgs g1, co
                                                          const GemmGrid d2) {
   extern __shared__ __align__(16) unsigned char gsm[];
   const int n1 = d1.nx * d1.ny * d1.nz;
-  int b = blockIdx.x;
+  int b = blockIdx.x, bx, by;
   if (b < n1) {
     const int xy = d1.nx * d1.ny, z = b / xy, r = b - z * xy;
-    gemm_nt_tile<E1, TM1, TN1, EX1, KS1>(g1, r % d1.nx, r / d1.nx, z, d1.nx, gsm);
+    xcd_tile(r, d1.nx, d1.ny, true, bx, by);
+    gemm_nt_tile<E1, TM1, TN1, EX1, KS1>(g1, bx, by, z, d1.nx, gsm);
   } else {
     b -= n1;
     const int xy = d2.nx * d2.ny, z = b / xy, r = b - z * xy;
-    gemm_nt_tile<E2, TM2, TN2, EX2, KS2>(g2, r % d2.nx, r / d2.nx, z, d2.nx, gsm);
+    xcd_tile(r, d2.nx, d2.ny, n1 % 8 == 0, bx, by);
+    gemm_nt_tile<E2, TM2, TN2, EX2, KS2>(g2, bx, by, z, d2.nx, gsm);
   }
 }
 
