@@ -184,6 +184,48 @@ __device__ __forceinline__ void knn_insert(float (&ld)[KT], int (&li)[KT], float
   }
 }
 
+// During the sweep a lane's KT candidates are kept unordered, with the worst
+// of them (wd, wi) and its slot wp tracked: an insertion overwrites that slot
+// and finds the new worst (a fixed pass of KT - 1 comparisons), about half the
+// work of sinking the entry through an ordered list.  The set kept is the
+// same; it is ordered once, at the end.
+template <int KT>
+__device__ __forceinline__ void knn_put(float (&ld)[KT], int (&li)[KT], float& wd, int& wi, int& wp, float d, int s) {
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    ld[j] = j == wp ? d : ld[j];
+    li[j] = j == wp ? s : li[j];
+  }
+  wd = ld[0];
+  wi = li[0];
+  wp = 0;
+#pragma unroll
+  for (int j = 1; j < KT; ++j) {
+    const bool w = knn_better<KT>(wd, wi, ld[j], li[j]);   // slot j is worse than the worst so far
+    wd = w ? ld[j] : wd;
+    wi = w ? li[j] : wi;
+    wp = w ? j : wp;
+  }
+}
+
+// Odd-even transposition sort of the unordered list into ascending order
+// (KT rounds of fixed compare-exchanges).
+template <int KT>
+__device__ __forceinline__ void knn_sort(float (&ld)[KT], int (&li)[KT]) {
+#pragma unroll
+  for (int r = 0; r < KT; ++r)
+#pragma unroll
+    for (int j = r & 1; j + 1 < KT; j += 2) {
+      const bool sw = knn_better<KT>(ld[j + 1], li[j + 1], ld[j], li[j]);
+      const float td = ld[j];
+      const int ti = li[j];
+      ld[j] = sw ? ld[j + 1] : td;
+      li[j] = sw ? li[j + 1] : ti;
+      ld[j + 1] = sw ? td : ld[j + 1];
+      li[j + 1] = sw ? ti : li[j + 1];
+    }
+}
+
 // One workgroup: one tile of up to 128 queries of one optimisation (wave w
 // owns queries 32w .. 32w+31, one per lane column), sweeping the
 // optimisation's samples (contiguous rows) in tiles of 32 staged in LDS; the
@@ -245,13 +287,15 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
     ld[j] = INFINITY;
     li[j] = INT_MAX;
   }
+  float wd = INFINITY;   // the worst kept candidate, at slot wp
+  int wi = INT_MAX, wp = 0;
 
   int qc = 0;
   auto flush = [&]() {
     for (int j = 0; j < qc; ++j) {
       const float d = qd[j * 256 + tid];
       const int sidx = qi[j * 256 + tid];
-      if (knn_better<KT>(d, sidx, ld[KT - 1], li[KT - 1])) knn_insert<KT>(ld, li, d, sidx);
+      if (knn_better<KT>(d, sidx, wd, wi)) knn_put<KT>(ld, li, wd, wi, wp, d, sidx);
     }
     qc = 0;
   };
@@ -278,10 +322,18 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
     if (tid < kIbkTile) tn[tid] = stn;
   };
 
+  // Queues are merged by every wave of the workgroup at the same tile, when
+  // one of them could overflow: merges at different tiles would each hold
+  // the other waves at the next barrier.  flag[t % 2] is tile t's decision;
+  // the other slot is cleared for the next tile.
+  __shared__ int flag[2];
+  if (tid < 2) flag[tid] = 0;
+  int it = 0;
   if (tb < te) fetch(tb);
-  for (int t0 = tb; t0 < te; t0 += kIbkTile) {   // uniform over the workgroup
+  for (int t0 = tb; t0 < te; t0 += kIbkTile, ++it) {   // uniform over the workgroup
     store();
     __syncthreads();
+    if (tid == 0) flag[(it + 1) & 1] = 0;
     if (t0 + kIbkTile < te) fetch(t0 + kIbkTile);   // in flight during the products
     if (wave_live) {
       // two accumulation chains (alternate groups of four features) keep
@@ -317,19 +369,21 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
         const float4 t4 = tq[r >> 2];
         const float tnv = (r & 3) == 0 ? t4.x : (r & 3) == 1 ? t4.y : (r & 3) == 2 ? t4.z : t4.w;
         const float d = qn + tnv - 2.0f * (acc0[r] + acc1[r]);
-        if (knn_better<KT>(d, t0 + i, ld[KT - 1], li[KT - 1])) {
+        if (knn_better<KT>(d, t0 + i, wd, wi)) {
           qd[qc * 256 + tid] = d;
           qi[qc * 256 + tid] = t0 + i;
           ++qc;
         }
       }
-      // merge the queues before one of them could overflow on the next tile:
-      // the wave pays for its fullest lane, once for all of them
-      if (__ballot(qc > kIbkQueue - 16) != 0ull) flush();
+      // merge the queues before one of them could overflow on the next tile
+      // (a wave pays for its fullest lane, once for all of them)
+      if (__ballot(qc > kIbkQueue - 16) != 0ull && lane == 0) flag[it & 1] = 1;
     }
     __syncthreads();   // the tile is consumed before the next store
+    if (flag[it & 1]) flush();
   }
   flush();
+  knn_sort<KT>(ld, li);
   // the two lanes of a query column saw disjoint samples: merge the partner's
   // list, then average the k nearest labels
   float od[KT];
