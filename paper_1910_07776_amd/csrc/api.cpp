@@ -415,7 +415,8 @@ namespace {
 
 template <typename T>
 int run_judge(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, const int32_t* cand, int32_t C,
-                     T* out, const T* ref, double tol, int32_t* flag, int32_t accumulate, hipStream_t s) {
+                     T* out, const T* ref, double tol, int32_t* flag, int32_t accumulate, hipStream_t s,
+                     int32_t C2 = 0, const int32_t* cand2 = nullptr, T* out2 = nullptr, const T* ref2 = nullptr) {
   JudgeArgs<T> j;
   j.counters = c;
   j.cycles = cyc;
@@ -438,6 +439,10 @@ int run_judge(sugg_ctx* ctx, const sugg_plan* p, const T* c, const T* cyc, const
   j.flag = flag;
   j.accumulate = accumulate;
   j.status = ctx->d_status;
+  j.C2 = C2;
+  j.cand2 = cand2;
+  j.out2 = out2;
+  j.ref2 = ref2;
   PathArgs<T> a{};
   a.judge = &j;
   a.E = p->E;
@@ -950,9 +955,11 @@ int32_t sugg_serve_query(sugg_ctx* ctx, const sugg_plan* plan, sugg_mlp* mlp, co
   if (!rc)
     rc = ctx->hip(launch_band<float>(w.ys, w.seg, K, 1, idx_out, count_out, n, ctx->params.tau - band, cap, w.bc,
                                      w.br, flag_out, stream), "serve: band");
-  // 5. the judge on both (plain values of the listed subsets are the answer's scores)
-  if (!rc) rc = run_judge<float>(ctx, p, c, cy, idx_out, n, (float*)score_out, w.sc, tol, flag_out, 1, stream);
-  if (!rc) rc = run_judge<float>(ctx, p, c, cy, w.bc, cap, w.bout, w.br, tol, flag_out, 1, stream);
+  // 5. the judge on both, in one launch (plain values of the listed subsets
+  // are the answer's scores)
+  if (!rc)
+    rc = run_judge<float>(ctx, p, c, cy, idx_out, n, (float*)score_out, w.sc, tol, flag_out, 1, stream, cap, w.bc,
+                          w.bout, w.br);
   // 6. Tier 3's contract by the plain values: listed subsets above the
   // threshold, no band subset above it; kept lists sorted by plain value
   if (!rc)

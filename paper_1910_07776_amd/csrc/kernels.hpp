@@ -45,6 +45,12 @@ struct JudgeArgs {
   int32_t* flag;           // [K] or null: 1 where some candidate differs from ref by > tol
   int32_t accumulate;      // nonzero: keep flags already set (no clearing)
   int32_t* status;
+  // a second candidate set judged in the same launch (C2 = 0: none), with
+  // its own cand2 [K, C2], out2 and ref2, and the same flags
+  int32_t C2;
+  const int32_t* cand2;
+  T* out2;
+  const T* ref2;
 };
 
 // Arguments of the fused scoring kernel (predict / suggest).

@@ -637,13 +637,19 @@ __global__ void __launch_bounds__(256) judge_kernel(const JudgeArgs<T> a) {
   T s_r[NCH][VW], m_r[NCH][VW];
   column_constants<T, NCH, VW, false>(a.mu, a.isg, E, l16, s_r, m_r);
   __syncthreads();   // the only barrier: waves below work independently
-  const int64_t job = (int64_t)blockIdx.x * 4 + (tid >> 6);
-  if (job >= (int64_t)a.K * a.C) return;
-  const int k = (int)(job / a.C);
-  const int32_t S = a.cand[job];
+  // jobs [0, K C) are the first set's, the next K C2 the second's
+  int64_t job = (int64_t)blockIdx.x * 4 + (tid >> 6);
+  const int64_t n1 = (int64_t)a.K * a.C;
+  if (job >= n1 + (int64_t)a.K * a.C2) return;
+  const bool second = job >= n1;
+  if (second) job -= n1;
+  const int k = (int)(job / (second ? a.C2 : a.C));
+  const int32_t S = second ? a.cand2[job] : a.cand[job];
+  T* const out = second ? a.out2 : a.out;
+  const T* const ref = second ? a.ref2 : a.ref;
   const int B = a.nopts[k];
   if (S <= 0 || S >= (1 << B)) {
-    if (lane == 0) a.out[job] = S == 0 ? T(0) : qnan<T>();
+    if (lane == 0) out[job] = S == 0 ? T(0) : qnan<T>();
     return;   // no candidate: nothing to disagree with
   }
   const int nt = __popc((uint32_t)S);
@@ -683,10 +689,10 @@ __global__ void __launch_bounds__(256) judge_kernel(const JudgeArgs<T> a) {
     }
   }
   if (lane == 0) {
-    a.out[job] = L;
+    out[job] = L;
     // fallback test: the reference (surrogate) value of this subset differs
     // from the plain value by more than tol
-    if (a.flag && !(fabs((double)a.ref[job] - (double)L) <= a.tol)) atomicOr(a.flag + k, 1);
+    if (a.flag && !(fabs((double)ref[job] - (double)L) <= a.tol)) atomicOr(a.flag + k, 1);
   }
   if (__ballot(bad) != 0 && lane == 0) atomicOr(a.status, (int)kStatusBadCounter);
 }
@@ -694,7 +700,7 @@ __global__ void __launch_bounds__(256) judge_kernel(const JudgeArgs<T> a) {
 template <typename T, int VPL>
 hipError_t launch_judge_vpl(const JudgeArgs<T>& a, hipStream_t s) {
   constexpr int VEC = 16 / sizeof(T);
-  const int64_t jobs = (int64_t)a.K * a.C;
+  const int64_t jobs = (int64_t)a.K * a.C + (int64_t)a.K * a.C2;
   if (jobs <= 0) return hipSuccess;
   const size_t smem = sizeof(T) * ((size_t)a.D * kRowLanes * VPL + a.D);
   const dim3 grid((unsigned)((jobs + 3) / 4));
