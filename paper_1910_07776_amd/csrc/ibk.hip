@@ -184,45 +184,50 @@ __device__ __forceinline__ void knn_insert(float (&ld)[KT], int (&li)[KT], float
   }
 }
 
-// During the sweep a lane's KT candidates are kept unordered, with the worst
-// of them (wd, wi) and its slot wp tracked: an insertion overwrites that slot
-// and finds the new worst (a fixed pass of KT - 1 comparisons), about half the
-// work of sinking the entry through an ordered list.  The set kept is the
-// same; it is ordered once, at the end.
+// During the sweep a lane's candidates are 64-bit keys: the distance's bits
+// mapped to an unsigned order in the high word, the sample index in the low
+// word, so one unsigned comparison orders two candidates by (distance, index)
+// exactly as knn_better does (-0 is taken as +0 first).  The KT keys are kept
+// unordered, with the largest (the worst candidate) and its slot tracked: an
+// insertion overwrites that slot and finds the new largest in one fixed
+// pass.  The set kept is the same as an ordered list's; it is ordered once,
+// at the end.
+__device__ __forceinline__ uint64_t knn_key(float d, int s) {
+  const uint32_t b = __float_as_uint(d + 0.0f);
+  const uint32_t o = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return ((uint64_t)o << 32) | (uint32_t)s;
+}
+__device__ __forceinline__ float knn_key_d(uint64_t k) {
+  const uint32_t o = (uint32_t)(k >> 32);
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+__device__ __forceinline__ int knn_key_s(uint64_t k) { return (int)(uint32_t)k; }
+
 template <int KT>
-__device__ __forceinline__ void knn_put(float (&ld)[KT], int (&li)[KT], float& wd, int& wi, int& wp, float d, int s) {
+__device__ __forceinline__ void knn_put(uint64_t (&lk)[KT], uint64_t& wk, int& wp, uint64_t key) {
 #pragma unroll
-  for (int j = 0; j < KT; ++j) {
-    ld[j] = j == wp ? d : ld[j];
-    li[j] = j == wp ? s : li[j];
-  }
-  wd = ld[0];
-  wi = li[0];
+  for (int j = 0; j < KT; ++j) lk[j] = j == wp ? key : lk[j];
+  wk = lk[0];
   wp = 0;
 #pragma unroll
   for (int j = 1; j < KT; ++j) {
-    const bool w = knn_better<KT>(wd, wi, ld[j], li[j]);   // slot j is worse than the worst so far
-    wd = w ? ld[j] : wd;
-    wi = w ? li[j] : wi;
+    const bool w = lk[j] > wk;
+    wk = w ? lk[j] : wk;
     wp = w ? j : wp;
   }
 }
 
-// Odd-even transposition sort of the unordered list into ascending order
-// (KT rounds of fixed compare-exchanges).
+// Odd-even transposition sort of the keys into ascending order (KT rounds of
+// fixed compare-exchanges).
 template <int KT>
-__device__ __forceinline__ void knn_sort(float (&ld)[KT], int (&li)[KT]) {
+__device__ __forceinline__ void knn_sort(uint64_t (&lk)[KT]) {
 #pragma unroll
   for (int r = 0; r < KT; ++r)
 #pragma unroll
     for (int j = r & 1; j + 1 < KT; j += 2) {
-      const bool sw = knn_better<KT>(ld[j + 1], li[j + 1], ld[j], li[j]);
-      const float td = ld[j];
-      const int ti = li[j];
-      ld[j] = sw ? ld[j + 1] : td;
-      li[j] = sw ? li[j + 1] : ti;
-      ld[j + 1] = sw ? td : ld[j + 1];
-      li[j + 1] = sw ? ti : li[j + 1];
+      const uint64_t a = lk[j], b = lk[j + 1];
+      lk[j] = a < b ? a : b;
+      lk[j + 1] = a < b ? b : a;
     }
 }
 
@@ -233,8 +238,14 @@ __device__ __forceinline__ void knn_sort(float (&ld)[KT], int (&li)[KT]) {
 // l holds query (l mod 32)'s feature half h = l / 32: the matrix core's
 // k-slot h of step j carries feature h*EH + j, for samples (A) and queries
 // (B) alike, so the block product is the full dot product.
+// two workgroups per compute unit where the registers allow it without
+// spilling (up to 128 events with lists of at most 16), else one
 template <int EH, int KT>
-__global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
+constexpr int ibk_knn_waves() { return EH <= 64 && KT <= 16 ? 2 : 1; }
+
+template <int EH, int KT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ibk_knn_waves<EH, KT>())))
+ibk_knn_kernel(const IbkKnnArgs a) {
   constexpr int EP = 2 * EH;
   constexpr int LS = EP + 4;                           // padded LDS row (floats)
   constexpr int F4 = (kIbkTile * EP / 4) / 256;        // float4 per thread per tile
@@ -243,8 +254,7 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
   __shared__ __align__(16) float tn[kIbkTile];
   // per-lane queue of candidates that beat the list's last entry as of the
   // latest merge (entry j of thread t at [j * 256 + t])
-  __shared__ float qd[kIbkQueue * 256];
-  __shared__ int qi[kIbkQueue * 256];
+  __shared__ uint64_t qk[kIbkQueue * 256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 31, h = lane >> 5;
   const int tile = blockIdx.x / a.split, part = blockIdx.x - tile * a.split;
@@ -280,22 +290,18 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
 #pragma unroll
   for (int j = 0; j < EH; ++j) qn = fmaf(qv[j], qv[j], qn);
   qn += __shfl_xor(qn, 32, kWave);
-  float ld[KT];
-  int li[KT];
+  uint64_t lk[KT];
+  const uint64_t empty = knn_key(INFINITY, INT_MAX);
 #pragma unroll
-  for (int j = 0; j < KT; ++j) {
-    ld[j] = INFINITY;
-    li[j] = INT_MAX;
-  }
-  float wd = INFINITY;   // the worst kept candidate, at slot wp
-  int wi = INT_MAX, wp = 0;
+  for (int j = 0; j < KT; ++j) lk[j] = empty;
+  uint64_t wk = empty;   // the worst kept candidate, at slot wp
+  int wp = 0;
 
   int qc = 0;
   auto flush = [&]() {
     for (int j = 0; j < qc; ++j) {
-      const float d = qd[j * 256 + tid];
-      const int sidx = qi[j * 256 + tid];
-      if (knn_better<KT>(d, sidx, wd, wi)) knn_put<KT>(ld, li, wd, wi, wp, d, sidx);
+      const uint64_t key = qk[j * 256 + tid];
+      if (key < wk) knn_put<KT>(lk, wk, wp, key);
     }
     qc = 0;
   };
@@ -369,9 +375,9 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
         const float4 t4 = tq[r >> 2];
         const float tnv = (r & 3) == 0 ? t4.x : (r & 3) == 1 ? t4.y : (r & 3) == 2 ? t4.z : t4.w;
         const float d = qn + tnv - 2.0f * (acc0[r] + acc1[r]);
-        if (knn_better<KT>(d, t0 + i, wd, wi)) {
-          qd[qc * 256 + tid] = d;
-          qi[qc * 256 + tid] = t0 + i;
+        const uint64_t key = knn_key(d, t0 + i);
+        if (key < wk) {
+          qk[qc * 256 + tid] = key;
           ++qc;
         }
       }
@@ -383,7 +389,14 @@ __global__ void __launch_bounds__(256) ibk_knn_kernel(const IbkKnnArgs a) {
     if (flag[it & 1]) flush();
   }
   flush();
-  knn_sort<KT>(ld, li);
+  knn_sort<KT>(lk);
+  float ld[KT];
+  int li[KT];
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    ld[j] = knn_key_d(lk[j]);
+    li[j] = knn_key_s(lk[j]);
+  }
   // the two lanes of a query column saw disjoint samples: merge the partner's
   // list, then average the k nearest labels
   float od[KT];
