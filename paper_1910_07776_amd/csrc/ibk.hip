@@ -299,9 +299,18 @@ ibk_knn_kernel(const IbkKnnArgs a) {
 
   int qc = 0;
   auto flush = [&]() {
-    for (int j = 0; j < qc; ++j) {
-      const uint64_t key = qk[j * 256 + tid];
-      if (key < wk) knn_put<KT>(lk, wk, wp, key);
+    // four queue entries read at a time (slots past qc read as the largest
+    // key, which never enters): one LDS wait per four insertions
+    for (int j = 0; j < qc; j += 4) {
+      uint64_t key[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = j + u < kIbkQueue ? j + u : kIbkQueue - 1;   // in bounds even if read unconditionally
+        key[u] = j + u < qc ? qk[q * 256 + tid] : ~0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (key[u] < wk) knn_put<KT>(lk, wk, wp, key[u]);
     }
     qc = 0;
   };
