@@ -14,7 +14,7 @@ constexpr int kIbkMaxK = 16;       // largest k
 constexpr int kIbkList = 24;       // FP32 candidates kept per query (k plus a margin, at most 24)
 constexpr int kIbkQueries = 128;   // queries per workgroup (4 waves x 32)
 constexpr int kIbkTile = 32;       // database samples per staged tile
-constexpr int kIbkQueue = 28;      // queued candidates per lane (at least 16, one tile's)
+constexpr int kIbkQueue = 30;      // queued candidates per lane (at least 16, one tile's)
 
 // Database of one fitted IBK model.  Samples of global optimisation o are
 // [off[o], off[o+1]), stored kernel by kernel, then by before-version S; each
